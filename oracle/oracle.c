@@ -1,0 +1,243 @@
+/*
+ * CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded definitions of what the GPU traversal path
+ * computes. Only the test suite, the smoke check and the benchmark's CPU
+ * baseline leg may load this file's library; the product library never does,
+ * and the two share no code (this file includes nothing from the package).
+ *
+ * Graph model (paper Section 3, "Graphs" and "Graph representations"): an
+ * undirected unweighted graph on vertices 0..n-1; an undirected edge (u, v)
+ * appears as v in the neighbour set of u and u in the neighbour set of v. The
+ * paper's evaluated graphs are symmetrised, unweighted and simple (Section 6.2,
+ * graph-size table), so self-pairs are dropped and repeated pairs collapse.
+ * Each neighbour set is kept as a sorted growable array (the "sequence of sets"
+ * representation of Section 3.1), built directly from the raw pairs.
+ *
+ * Algorithms (paper Table "algs-list": BFS, Connectivity, PageRank): the paper
+ * names them and defers their details to GBBS, so each function computes the
+ * plain definition of the result:
+ *   - BFS: hop distance from the source via a FIFO queue, plus the discovering
+ *     vertex as parent (any BFS parent is valid; the checker below accepts any).
+ *   - CC: every vertex labelled with the smallest vertex ID in its component.
+ *   - PageRank: T power-iteration steps in FP64 with uniform teleport and the
+ *     mass of zero-degree vertices spread uniformly.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int64_t n;
+  int64_t m;        /* directed entries = sum of degrees */
+  int64_t *len;     /* neighbour-set sizes */
+  int64_t *cap;
+  int32_t **nb;     /* sorted, unique neighbour sets */
+} oracle_graph;
+
+static int push(oracle_graph *g, int64_t u, int32_t v) {
+  if (g->len[u] == g->cap[u]) {
+    int64_t nc = g->cap[u] ? 2 * g->cap[u] : 4;
+    int32_t *p = (int32_t *)realloc(g->nb[u], sizeof(int32_t) * (size_t)nc);
+    if (!p) return -1;
+    g->nb[u] = p;
+    g->cap[u] = nc;
+  }
+  g->nb[u][g->len[u]++] = v;
+  return 0;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+void oracle_graph_free(oracle_graph *g) {
+  if (!g) return;
+  if (g->nb)
+    for (int64_t v = 0; v < g->n; ++v) free(g->nb[v]);
+  free(g->nb); free(g->len); free(g->cap); free(g);
+}
+
+/* Build neighbour sets from raw pairs: add both directions, skip u == v, then
+ * sort every set and drop repeats. Returns NULL on bad input or no memory. */
+oracle_graph *oracle_graph_new(int64_t n, int64_t npairs, const int32_t *a, const int32_t *b) {
+  if (n < 0 || npairs < 0) return NULL;
+  oracle_graph *g = (oracle_graph *)calloc(1, sizeof(oracle_graph));
+  if (!g) return NULL;
+  g->n = n;
+  g->len = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  g->cap = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  g->nb = (int32_t **)calloc((size_t)(n + 1), sizeof(int32_t *));
+  if (!g->len || !g->cap || !g->nb) { oracle_graph_free(g); return NULL; }
+  for (int64_t i = 0; i < npairs; ++i) {
+    int64_t u = a[i], v = b[i];
+    if (u < 0 || v < 0 || u >= n || v >= n) { oracle_graph_free(g); return NULL; }
+    if (u == v) continue;
+    if (push(g, u, (int32_t)v) || push(g, v, (int32_t)u)) { oracle_graph_free(g); return NULL; }
+  }
+  g->m = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (g->len[v] > 1) qsort(g->nb[v], (size_t)g->len[v], sizeof(int32_t), cmp_i32);
+    int64_t w = 0;
+    for (int64_t i = 0; i < g->len[v]; ++i)
+      if (w == 0 || g->nb[v][i] != g->nb[v][w - 1]) g->nb[v][w++] = g->nb[v][i];
+    g->len[v] = w;
+    g->m += w;
+  }
+  return g;
+}
+
+int64_t oracle_num_vertices(const oracle_graph *g) { return g->n; }
+int64_t oracle_num_edges(const oracle_graph *g) { return g->m; }
+int64_t oracle_degree(const oracle_graph *g, int64_t v) { return (v >= 0 && v < g->n) ? g->len[v] : -1; }
+
+/* Copy the neighbour set of v into out (up to cap); returns its size. */
+int64_t oracle_neighbors(const oracle_graph *g, int64_t v, int32_t *out, int64_t cap) {
+  if (v < 0 || v >= g->n) return -1;
+  int64_t k = g->len[v] < cap ? g->len[v] : cap;
+  if (k > 0) memcpy(out, g->nb[v], sizeof(int32_t) * (size_t)k);
+  return g->len[v];
+}
+
+/* Write every neighbour set back to back with the running count before each
+ * (used by tests to compare container contents; off has n + 1 entries). */
+void oracle_export(const oracle_graph *g, int64_t *off, int32_t *nbr) {
+  int64_t pos = 0;
+  for (int64_t v = 0; v < g->n; ++v) {
+    off[v] = pos;
+    for (int64_t i = 0; i < g->len[v]; ++i) nbr[pos++] = g->nb[v][i];
+  }
+  off[g->n] = pos;
+}
+
+/* Breadth-first search: depth = hop distance (-1 unreachable), parent = the
+ * vertex whose neighbour scan first reached it (src is its own parent). */
+int oracle_bfs(const oracle_graph *g, int64_t src, int32_t *depth, int32_t *parent) {
+  if (src < 0 || src >= g->n) return -1;
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1));
+  if (!queue) return -2;
+  for (int64_t v = 0; v < g->n; ++v) { depth[v] = -1; parent[v] = -1; }
+  int64_t head = 0, tail = 0;
+  depth[src] = 0; parent[src] = (int32_t)src;
+  queue[tail++] = (int32_t)src;
+  while (head < tail) {
+    int32_t u = queue[head++];
+    for (int64_t i = 0; i < g->len[u]; ++i) {
+      int32_t v = g->nb[u][i];
+      if (depth[v] == -1) {
+        depth[v] = depth[u] + 1;
+        parent[v] = u;
+        queue[tail++] = v;
+      }
+    }
+  }
+  free(queue);
+  return 0;
+}
+
+/* Connected components: scan vertices in increasing ID order; an unlabelled
+ * vertex is the smallest ID of its component, so a BFS from it labels the
+ * whole component with its ID. */
+int oracle_cc(const oracle_graph *g, int32_t *label) {
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1));
+  if (!queue) return -2;
+  for (int64_t v = 0; v < g->n; ++v) label[v] = -1;
+  for (int64_t s = 0; s < g->n; ++s) {
+    if (label[s] != -1) continue;
+    int64_t head = 0, tail = 0;
+    label[s] = (int32_t)s;
+    queue[tail++] = (int32_t)s;
+    while (head < tail) {
+      int32_t u = queue[head++];
+      for (int64_t i = 0; i < g->len[u]; ++i) {
+        int32_t v = g->nb[u][i];
+        if (label[v] == -1) { label[v] = (int32_t)s; queue[tail++] = v; }
+      }
+    }
+  }
+  free(queue);
+  return 0;
+}
+
+/*
+ * PageRank, T steps, FP64. Start from p = 1/n. One step:
+ *   D     = sum of p[u] over vertices with degree 0,
+ *   p'[v] = (1 - d)/n + d * ( sum over neighbours u of v of p[u]/deg(u)  +  D/n ).
+ * Sums run sequentially in ascending neighbour order. No convergence test.
+ */
+int oracle_pagerank(const oracle_graph *g, double d, int32_t T, double *rank) {
+  int64_t n = g->n;
+  if (n == 0) return 0;
+  if (T < 0) return -1;
+  double *next = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!next) return -2;
+  for (int64_t v = 0; v < n; ++v) rank[v] = 1.0 / (double)n;
+  for (int32_t t = 0; t < T; ++t) {
+    double D = 0.0;
+    for (int64_t u = 0; u < n; ++u)
+      if (g->len[u] == 0) D += rank[u];
+    for (int64_t v = 0; v < n; ++v) {
+      double s = 0.0;
+      for (int64_t i = 0; i < g->len[v]; ++i) {
+        int32_t u = g->nb[v][i];
+        s += rank[u] / (double)g->len[u];
+      }
+      next[v] = (1.0 - d) / (double)n + d * (s + D / (double)n);
+    }
+    memcpy(rank, next, sizeof(double) * (size_t)n);
+  }
+  free(next);
+  return 0;
+}
+
+/* Multi-source BFS as k independent BFS runs. depth is vertex-major:
+ * depth[v * k + j] = hop distance from srcs[j], 255 when unreachable.
+ * Returns -3 if some finite distance does not fit below 255. */
+int oracle_msbfs(const oracle_graph *g, const int64_t *srcs, int32_t k, uint8_t *depth) {
+  int64_t n = g->n;
+  int32_t *dd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *pp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!dd || !pp) { free(dd); free(pp); return -2; }
+  int rc = 0;
+  for (int32_t j = 0; j < k && rc == 0; ++j) {
+    rc = oracle_bfs(g, srcs[j], dd, pp);
+    for (int64_t v = 0; v < n && rc == 0; ++v) {
+      if (dd[v] >= 255) rc = -3;
+      depth[v * k + j] = (uint8_t)(dd[v] < 0 ? 255 : dd[v]);
+    }
+  }
+  free(dd); free(pp);
+  return rc;
+}
+
+/*
+ * Check a BFS result (depth, parent) for source src against this graph:
+ * depth must equal the true hop distances exactly; parent[src] == src; every
+ * other reached v has parent p with (p, v) an edge and depth[p] == depth[v]-1;
+ * unreached vertices have depth == parent == -1. Returns the number of
+ * violations (0 = valid), -2 on no memory.
+ */
+int64_t oracle_check_bfs(const oracle_graph *g, int64_t src, const int32_t *depth, const int32_t *parent) {
+  int64_t n = g->n, bad = 0;
+  int32_t *dd = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *pp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!dd || !pp) { free(dd); free(pp); return -2; }
+  if (oracle_bfs(g, src, dd, pp) != 0) { free(dd); free(pp); return -1; }
+  for (int64_t v = 0; v < n; ++v) {
+    if (depth[v] != dd[v]) { ++bad; continue; }
+    if (dd[v] < 0) { bad += (parent[v] != -1); continue; }
+    if (v == src) { bad += (parent[v] != (int32_t)src); continue; }
+    int32_t p = parent[v];
+    if (p < 0 || p >= n || dd[p] != dd[v] - 1) { ++bad; continue; }
+    /* (p, v) must be an edge: binary search in the sorted set of v */
+    int64_t lo = 0, hi = g->len[v];
+    while (lo < hi) {
+      int64_t mid = (lo + hi) / 2;
+      if (g->nb[v][mid] < p) lo = mid + 1; else hi = mid;
+    }
+    if (lo >= g->len[v] || g->nb[v][lo] != p) ++bad;
+  }
+  free(dd); free(pp);
+  return bad;
+}

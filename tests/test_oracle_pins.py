@@ -1,0 +1,315 @@
+"""Pins for the CPU oracle against mathematics it does not share code with.
+
+Every check compares the oracle with something other than itself: brute force
+(Floyd-Warshall, union-find), library routines (scipy.sparse.csgraph,
+numpy.linalg.solve, torch.autograd), closed forms (paths, cycles, stars,
+cliques, lattices, regular graphs) and invariants (sum of ranks is 1).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csg
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from oracle import mlp
+from tests import brute
+
+
+def G(n, pairs):
+    a = np.array([p[0] for p in pairs], np.int32)
+    b = np.array([p[1] for p in pairs], np.int32)
+    return oracle.Graph(n, a, b), a, b
+
+
+tiny_graphs = st.integers(1, 40).flatmap(
+    lambda n: st.tuples(st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)),
+                                             max_size=3 * n)))
+
+
+# ---------------------------------------------------------------- graph build
+
+@settings(max_examples=60, deadline=None)
+@given(tiny_graphs)
+def test_neighbour_sets_match_edge_set(case):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    E = brute.simple_edges(n, a, b)
+    assert g.m == 2 * len(E)
+    for v in range(n):
+        want = sorted({y for (x, y) in E if x == v} | {x for (x, y) in E if y == v})
+        assert g.neighbors(v).tolist() == want
+    off, nbr = g.export()
+    assert off[0] == 0 and off[-1] == g.m and np.all(np.diff(off) >= 0)
+
+
+def test_rejects_out_of_range_pairs():
+    with pytest.raises(ValueError):
+        oracle.Graph(3, np.array([0], np.int32), np.array([3], np.int32))
+
+
+# ---------------------------------------------------------------- BFS
+
+@settings(max_examples=80, deadline=None)
+@given(tiny_graphs, st.integers(0, 10 ** 6))
+def test_bfs_matches_floyd_warshall_and_scipy(case, s):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    src = s % n
+    depth, parent = g.bfs(src)
+    A = brute.adjacency_matrix(n, a, b)
+    D = brute.floyd_warshall_hops(A)
+    assert depth.tolist() == D[src].tolist()
+    sd = csg.shortest_path(sp.csr_matrix(A), unweighted=True, indices=src)
+    want = np.where(np.isinf(sd), -1, sd).astype(np.int64)
+    assert depth.tolist() == want.tolist()
+    # parent validity checked independently of the oracle's checker
+    for v in range(n):
+        if depth[v] < 0:
+            assert parent[v] == -1
+        elif v == src:
+            assert parent[v] == src
+        else:
+            p = parent[v]
+            assert A[p, v] == 1 and depth[p] == depth[v] - 1
+    assert g.check_bfs(src, depth, parent) == 0
+
+
+def test_bfs_closed_forms():
+    n = 50
+    g, _, _ = G(n, [(i, i + 1) for i in range(n - 1)])          # path
+    assert g.bfs(7)[0].tolist() == [abs(v - 7) for v in range(n)]
+    g, _, _ = G(n, [(i, (i + 1) % n) for i in range(n)])         # cycle
+    assert g.bfs(3)[0].tolist() == [min(abs(v - 3), n - abs(v - 3)) for v in range(n)]
+    g, _, _ = G(n, [(0, i) for i in range(1, n)])                # star
+    assert g.bfs(0)[0].tolist() == [0] + [1] * (n - 1)
+    assert g.bfs(5)[0].tolist() == [1] + [2 if v != 5 else 0 for v in range(1, n)]
+    k = 12
+    g, _, _ = G(k, [(i, j) for i in range(k) for j in range(i + 1, k)])  # clique
+    assert g.bfs(4)[0].tolist() == [0 if v == 4 else 1 for v in range(k)]
+    R, C = 9, 13                                                  # full lattice: Manhattan
+    pairs = [(r * C + c, r * C + c + 1) for r in range(R) for c in range(C - 1)]
+    pairs += [(r * C + c, (r + 1) * C + c) for r in range(R - 1) for c in range(C)]
+    g, _, _ = G(R * C, pairs)
+    s = 3 * C + 5
+    assert g.bfs(s)[0].tolist() == [abs(v // C - 3) + abs(v % C - 5) for v in range(R * C)]
+    g, _, _ = G(6, [])                                            # no edges
+    d, p = g.bfs(2)
+    assert d.tolist() == [-1, -1, 0, -1, -1, -1] and p.tolist() == [-1, -1, 2, -1, -1, -1]
+
+
+def test_bfs_checker_catches_planted_mistakes():
+    # 3 is at depth 2 with two valid parents (1 and 4); 5 only has a self-loop
+    g, a, b = G(6, [(0, 1), (1, 2), (1, 3), (0, 4), (4, 3), (5, 5)])
+    d, p = g.bfs(0)
+    assert d.tolist() == [0, 1, 2, 2, 1, -1]
+    assert g.check_bfs(0, d, p) == 0
+    bad = d.copy(); bad[3] += 1
+    assert g.check_bfs(0, bad, p) > 0                 # wrong depth
+    bad = p.copy(); bad[3] = 2                        # 2 is not adjacent to 3
+    assert g.check_bfs(0, d, bad) > 0
+    bad = p.copy(); bad[2] = 4                        # 4 is not adjacent to 2
+    assert g.check_bfs(0, d, bad) > 0
+    bad = p.copy(); bad[2] = 2                        # a vertex at the same depth
+    assert g.check_bfs(0, d, bad) > 0
+    bad = p.copy(); bad[0] = -1                       # root must be its own parent
+    assert g.check_bfs(0, d, bad) > 0
+    bad = p.copy(); bad[5] = 0                        # unreached must stay -1
+    assert g.check_bfs(0, d, bad) > 0
+    alt = p.copy(); alt[3] = 4 if p[3] == 1 else 1    # the other valid parent is accepted
+    assert g.check_bfs(0, d, alt) == 0
+
+
+# ---------------------------------------------------------------- CC
+
+@settings(max_examples=80, deadline=None)
+@given(tiny_graphs)
+def test_cc_matches_union_find_and_scipy(case):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    lab = g.cc()
+    assert lab.tolist() == brute.union_find_min_labels(n, a, b).tolist()
+    ncomp, comp = csg.connected_components(sp.csr_matrix(brute.adjacency_matrix(n, a, b)), directed=False)
+    mins = {}
+    for v in range(n):
+        mins.setdefault(comp[v], v)
+    assert lab.tolist() == [mins[comp[v]] for v in range(n)]
+    assert len(set(lab.tolist())) == ncomp
+
+
+def test_cc_closed_forms():
+    g, _, _ = G(5, [])
+    assert g.cc().tolist() == [0, 1, 2, 3, 4]
+    # disjoint cliques {7,2,9}, {1,4}, {0,3,5,6,8}
+    cl = [[7, 2, 9], [1, 4], [0, 3, 5, 6, 8]]
+    pairs = [(c[i], c[j]) for c in cl for i in range(len(c)) for j in range(i + 1, len(c))]
+    g, _, _ = G(10, pairs)
+    want = [0] * 10
+    for c in cl:
+        for v in c:
+            want[v] = min(c)
+    assert g.cc().tolist() == want
+
+
+# ---------------------------------------------------------------- PageRank
+
+@settings(max_examples=40, deadline=None)
+@given(tiny_graphs, st.sampled_from([0.85, 0.5, 0.99]), st.integers(0, 25))
+def test_pagerank_matches_dense_power_iteration(case, d, T):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    p = g.pagerank(d, T)
+    want = brute.pagerank_power(brute.adjacency_matrix(n, a, b), d, T)
+    assert np.max(np.abs(p - want)) < 1e-13
+    assert abs(p.sum() - 1.0) < 1e-12
+
+
+@settings(max_examples=30, deadline=None)
+@given(tiny_graphs)
+def test_pagerank_converges_to_linear_solve(case):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    p = g.pagerank(0.85, 300)
+    want = brute.pagerank_fixed_point(brute.adjacency_matrix(n, a, b), 0.85)
+    assert np.max(np.abs(p - want)) < 1e-12
+
+
+def test_pagerank_closed_forms():
+    n = 30
+    for pairs in ([(i, (i + 1) % n) for i in range(n)],                       # cycle
+                  [(i, j) for i in range(n) for j in range(i + 1, n)],         # clique
+                  []):                                                          # no edges
+        g, _, _ = G(n, pairs)
+        assert np.allclose(g.pagerank(0.85, 20), 1.0 / n, rtol=0, atol=1e-15)
+    # star K_{1,k}: fixed point of the centre is ((1-d)/n + d) / (1 + d)
+    k, d = 9, 0.85
+    n = k + 1
+    g, _, _ = G(n, [(0, i) for i in range(1, n)])
+    p = g.pagerank(d, 400)
+    pc = ((1 - d) / n + d) / (1 + d)
+    assert abs(p[0] - pc) < 1e-14
+    assert np.allclose(p[1:], (1 - pc) / k, rtol=0, atol=1e-14)
+
+
+def test_pagerank_one_step_exact_fractions():
+    # path 0-1-2 plus isolated 3, one step from 1/4 each, in exact rationals
+    g, _, _ = G(4, [(0, 1), (1, 2)])
+    d = Fraction(85, 100)
+    n = 4
+    p0 = Fraction(1, 4)
+    D = p0                                    # vertex 3 has degree 0
+    base = (1 - d) / n + d * D / n
+    want = [base + d * (p0 / 2), base + d * (p0 + p0), base + d * (p0 / 2), base]
+    got = g.pagerank(0.85, 1)
+    assert np.max(np.abs(got - np.array([float(x) for x in want]))) < 1e-16
+
+
+# ---------------------------------------------------------------- MS-BFS
+
+@settings(max_examples=30, deadline=None)
+@given(tiny_graphs, st.integers(1, 9))
+def test_msbfs_columns_are_single_bfs(case, k):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    srcs = np.array([(7 * j + 3) % n for j in range(k)], np.int64)
+    D = g.msbfs(srcs)
+    for j in range(k):
+        d, _ = g.bfs(int(srcs[j]))
+        assert D[:, j].tolist() == np.where(d < 0, 255, d).tolist()
+
+
+# ---------------------------------------------------------------- MLP
+
+def _params(F, H, K, rng):
+    return {k: rng.standard_normal(s) * 0.5 for k, s in mlp.shapes(F, H, K).items()}
+
+
+def test_mlp_backward_matches_finite_differences():
+    rng = np.random.default_rng(4)
+    F, H, K, N = 5, 7, 4, 11
+    p = _params(F, H, K, rng)
+    X, Y = rng.standard_normal((N, F)), rng.standard_normal((N, K))
+    M = (rng.random((N, K)) < 0.7).astype(float)
+    _, g = mlp.loss_and_grads(p, X, Y, M)
+    h = 1e-6
+    for name in mlp.PARAM_NAMES:
+        num = np.zeros_like(p[name])
+        for idx in np.ndindex(*p[name].shape):
+            old = p[name][idx]
+            p[name][idx] = old + h
+            lp = mlp.loss(mlp.forward(p, X)[0], Y, M)
+            p[name][idx] = old - h
+            lm = mlp.loss(mlp.forward(p, X)[0], Y, M)
+            p[name][idx] = old
+            num[idx] = (lp - lm) / (2 * h)
+        rel = np.linalg.norm(num - g[name]) / max(np.linalg.norm(num), 1e-12)
+        assert rel < 1e-6, name
+
+
+def test_mlp_backward_matches_torch_autograd():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    F, H, K, N = 12, 32, 7, 64
+    p = _params(F, H, K, rng)
+    X, Y = rng.standard_normal((N, F)), rng.standard_normal((N, K))
+    M = (rng.random((N, K)) < 0.5).astype(float)
+    L, g = mlp.loss_and_grads(p, X, Y, M)
+    tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    Xt, Yt, Mt = (torch.tensor(a, dtype=torch.float64) for a in (X, Y, M))
+    h1 = torch.relu(Xt @ tp["W1"] + tp["b1"])
+    h2 = torch.relu(h1 @ tp["W2"] + tp["b2"])
+    out = h2 @ tp["W3"] + tp["b3"]
+    lt = (Mt * (out - Yt) ** 2).sum() / Mt.sum().clamp(min=1)
+    lt.backward()
+    assert abs(lt.item() - L) < 1e-12
+    for k in mlp.PARAM_NAMES:
+        assert np.allclose(tp[k].grad.numpy(), g[k], rtol=1e-11, atol=1e-13), k
+
+
+def test_adam_first_step_closed_form():
+    # with zero moments, bias correction makes the first step lr * g / (|g| + eps)
+    rng = np.random.default_rng(6)
+    p = _params(3, 4, 2, rng)
+    g = {k: rng.standard_normal(v.shape) for k, v in p.items()}
+    st_ = mlp.adam_init(p)
+    q = mlp.adam_step({k: v.copy() for k, v in p.items()}, g, st_, 1, lr=0.01)
+    for k in mlp.PARAM_NAMES:
+        assert np.allclose(p[k] - q[k], 0.01 * g[k] / (np.abs(g[k]) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_training_fits_a_learnable_target():
+    rng = np.random.default_rng(7)
+    F, H, K, N = 4, 16, 3, 256
+    X = rng.standard_normal((N, F))
+    Y = np.stack([X[:, 0] * 2 - X[:, 1], np.abs(X[:, 2]), X[:, 3] ** 2], axis=1)
+    M = np.ones_like(Y)
+    p0 = _params(F, H, K, rng)
+    _, losses = mlp.train(p0, X, Y, M, 1500, lr=3e-3)
+    assert losses[-1] < 0.05 * losses[0]
+
+
+def test_predict_argmin_respects_mask_and_ties():
+    p = {k: np.zeros(s) for k, s in mlp.shapes(2, 3, 4).items()}
+    p["b3"] = np.array([1.0, 0.5, 0.5, 2.0])
+    X = np.zeros((2, 2))
+    assert mlp.predict_argmin(p, X).tolist() == [1, 1]
+    assert mlp.predict_argmin(p, X, allowed=[[True, False, True, True]] * 2).tolist() == [2, 2]
+
+
+# ---------------------------------------------------------------- golden fixture
+
+def test_golden_small_graph():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "small_graph.json")
+    gold = json.load(open(path))
+    g, _, _ = G(gold["n"], [tuple(p) for p in gold["pairs"]])
+    assert g.bfs(0)[0].tolist() == gold["bfs_depth_from_0"]
+    assert g.bfs(6)[0].tolist() == gold["bfs_depth_from_6"]
+    assert g.cc().tolist() == gold["cc_min_label"]
+    want = np.array([float(Fraction(x)) for x in gold["pagerank_d085_T3"]])
+    assert np.max(np.abs(g.pagerank(0.85, 3) - want)) < 1e-16
+    assert sum(Fraction(x) for x in gold["pagerank_d085_T3"]) == 1
