@@ -39,8 +39,8 @@ def hops(src, nb):
 def pagerank_exact(nb, d, T):
     p = [Fraction(1, N)] * N
     for _ in range(T):
-        D = sum(p[u] for u in range(N) if not nb[u])
-        p = [(1 - d) / N + d * (sum(p[u] / len(nb[u]) for u in nb[v]) + D / N) for v in range(N)]
+        D = sum((p[u] for u in range(N) if not nb[u]), Fraction(0))
+        p = [(1 - d) / N + d * (sum((p[u] / len(nb[u]) for u in nb[v]), Fraction(0)) + D / N) for v in range(N)]
     return p
 
 
