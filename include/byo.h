@@ -1,0 +1,229 @@
+/*
+ * byo.h -- C ABI of the MI355X (gfx950) edgeMap traversal library.
+ *
+ * The library implements the read path of the paper's graph-container API
+ * (BYO, arXiv 2405.11671): a GraphContainer over a static CSR
+ * (num_vertices, num_edges, degree, map_neighbors and its early-exit and
+ * parallel variants; Section 4.2), the Ligra/GBBS vertexSubset (sparse ID list
+ * or dense bit array; Section 3.2 "VertexSubsets" and the bit-array change of
+ * Section 4.4), and edgeMap(G, U, F) (Section 3.2 "EdgeMap"), plus the
+ * algorithms the paper evaluates on top of it that reduce to edgeMap: BFS,
+ * connectivity and PageRank (Table algs-list, Section 6.2).
+ *
+ * Conventions shared by every entry point:
+ *  - Vertex IDs are int32 (n < 2^31); CSR offsets are int64.
+ *  - "d_" pointers are device (HBM) pointers, "h_" pointers host pointers.
+ *    Device buffers passed in stay owned by the caller; the library owns what
+ *    it allocates and frees it in the matching destroy call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *    enqueue their kernels on it. Calls that return a host scalar computed on
+ *    the device synchronise that stream before returning.
+ *  - Calls on one graph object share its workspace: issue them from one host
+ *    thread on one stream (concurrent calls on the same graph race).
+ *  - Every call returns a byo_status. On error nothing is written to the
+ *    out-parameters and byo_last_error() describes the failure (thread-local).
+ *    Nothing in the library ever falls back to host computation.
+ */
+#ifndef BYO_H_
+#define BYO_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BYO_OK = 0,
+  BYO_EINVAL = -1,   /* bad argument or malformed input */
+  BYO_ENOMEM = -2,   /* device or host allocation failed */
+  BYO_EHIP = -3,     /* a HIP runtime call failed */
+  BYO_ELIMIT = -4,   /* level / round cap reached before convergence */
+  BYO_ESTATE = -5    /* object in the wrong state (e.g. no selector weights) */
+} byo_status;
+
+typedef struct byo_graph byo_graph;   /* opaque CSR GraphContainer on one device */
+typedef struct byo_vset byo_vset;     /* opaque vertexSubset (sparse list and/or dense bitmap) */
+typedef struct byo_batch byo_batch;   /* opaque batch of graphs run in one launch sequence */
+
+/* ------------------------------------------------------------------------
+ * edgeMap variants. The paper's API study (Section 6.3, Table
+ * api-components-avg) shows that which map variants a container offers
+ * changes only running time; here every variant computes the same result and
+ * only the schedule differs.
+ *   PUSH_*: sparse input (ID list), apply F from each u in U to N(u)
+ *           ("map_neighbors" / "parallel_map_neighbors", Section 4.2).
+ *   PULL_*: dense input (bitmap), each candidate v scans N(v) for members of
+ *           U and stops at the first hit where F allows it
+ *           ("map_neighbors_early_exit" / "parallel_map_neighbors_early_exit").
+ * ---------------------------------------------------------------------- */
+typedef enum {
+  BYO_V_PUSH_THREAD = 0,  /* one thread per frontier vertex, serial map */
+  BYO_V_PUSH_WAVE = 1,    /* one 64-lane wavefront per frontier vertex */
+  BYO_V_PUSH_BUCKET = 2,  /* degree-bucketed: thread / wavefront / workgroup per vertex */
+  BYO_V_PUSH_EDGE = 3,    /* edge-balanced: equal slices of sum(deg(U)) per workgroup */
+  BYO_V_PULL_THREAD = 4,  /* one thread per vertex, serial early-exit map */
+  BYO_V_PULL_WAVE = 5,    /* thread first, then wavefront-parallel early-exit map for long lists */
+  BYO_NUM_VARIANTS = 6
+} byo_variant;
+
+typedef enum {
+  BYO_SEL_HEURISTIC = 0,  /* dense pull iff |U| + sum(deg(U)) > m / dense_divisor (Section 6.3) */
+  BYO_SEL_MLP = 1,        /* learned selector (weights from byo_selector_set); heuristic if none */
+  BYO_SEL_FIXED = 2       /* always fixed_variant */
+} byo_selector_mode;
+
+/* Options; fill with byo_opts_default() and override fields. */
+typedef struct byo_opts {
+  int32_t selector;       /* byo_selector_mode (default HEURISTIC) */
+  int32_t fixed_variant;  /* byo_variant used with BYO_SEL_FIXED (default PUSH_EDGE) */
+  int32_t dense_divisor;  /* heuristic cutoff divisor (default 20) */
+  int32_t t_wave;         /* PUSH_BUCKET / PULL_WAVE: degree >= t_wave goes to a wavefront (default 32) */
+  int32_t t_block;        /* PUSH_BUCKET: degree >= t_block goes to a workgroup (default 4096) */
+  int32_t max_levels;     /* BFS level / CC round cap; 0 = n + 1 */
+  int32_t cc_shortcut;    /* CC: pointer-jumping pass after each round (default 1) */
+  int32_t small_frontier; /* frontiers at most this size run in the device-resident
+                             single-workgroup loop (0 = off; default 0) */
+  int32_t reserved[8];
+} byo_opts;
+
+/* Per-call statistics (optional out-parameter; pass NULL to skip). */
+typedef struct byo_run_stats {
+  int32_t levels;                          /* BFS levels / CC rounds / PR iterations executed */
+  int32_t device_levels;                   /* of those, levels run in the device-resident loop */
+  int64_t variant_count[BYO_NUM_VARIANTS]; /* edgeMap calls per variant */
+  int64_t reached;                         /* BFS: vertices reached; CC: components */
+  int64_t edges;                           /* BFS: sum of degrees of reached vertices */
+} byo_run_stats;
+
+/* Status string of the last failing call on this thread ("" if none). */
+const char *byo_last_error(void);
+/* Library version string. */
+const char *byo_version(void);
+void byo_opts_default(byo_opts *opts);
+
+/* ------------------------------------------------------------------------
+ * CSR construction (host). From raw pairs (src[i], dst[i]) over n vertices:
+ * add both directions, drop self-pairs, sort each row and drop repeats
+ * (the paper's graphs are symmetrised, simple and unweighted, Section 6.2).
+ * Caller allocates h_off (n + 1 entries) and h_nbr (capacity 2 * npairs);
+ * *m_out receives the number of directed entries written. Uses host threads.
+ * ---------------------------------------------------------------------- */
+byo_status byo_csr_from_pairs(const int32_t *h_src, const int32_t *h_dst, int64_t npairs, int64_t n,
+                              int64_t *h_off, int32_t *h_nbr, int64_t *m_out);
+
+/* ------------------------------------------------------------------------
+ * GraphContainer (Section 4.2). CSR: offsets off[n + 1] (int64, off[0] = 0,
+ * non-decreasing, off[n] = m), neighbours nbr[m] (int32, each row strictly
+ * increasing, no self-loops, undirected = every (u, v) has (v, u)).
+ * Flags choose where off/nbr live and whether they are copied or borrowed.
+ * With BYO_VALIDATE the structure is checked on the device and
+ * BYO_EINVAL is returned if any rule above fails.
+ * ---------------------------------------------------------------------- */
+#define BYO_HOST_INPUT 0x1u     /* off/nbr are host pointers: copied to the device */
+#define BYO_DEVICE_COPY 0x2u    /* off/nbr are device pointers: copied */
+#define BYO_DEVICE_BORROW 0x4u  /* off/nbr are device pointers: used in place; caller keeps them alive */
+#define BYO_VALIDATE 0x8u       /* check the CSR rules (including symmetry) on the device */
+
+byo_status byo_graph_from_csr(const int64_t *off, const int32_t *nbr, int64_t n, int64_t m, uint32_t flags,
+                              void *stream, byo_graph **out);
+void byo_graph_destroy(byo_graph *g);
+int64_t byo_num_vertices(const byo_graph *g);        /* n (required API) */
+int64_t byo_num_edges(const byo_graph *g);           /* m = directed entries (optional API) */
+byo_status byo_degree(const byo_graph *g, int64_t v, int64_t *out);  /* |N(v)|, syncs */
+/* getNeighbors expressed with map (Table gbbs-byo-translation): copies up to cap
+ * neighbours of v, ascending, into h_buf; *count = |N(v)|. Syncs. */
+byo_status byo_get_neighbors(const byo_graph *g, int64_t v, int32_t *h_buf, int64_t cap, int64_t *count);
+/* Device pointers to the CSR arrays and the int32 degree array deg[n]. */
+byo_status byo_graph_arrays(const byo_graph *g, const int64_t **d_off, const int32_t **d_nbr,
+                            const int32_t **d_deg);
+/* Degree statistics computed at creation: max degree, number of isolated
+ * vertices, mean and coefficient of variation of the degree. */
+byo_status byo_graph_stats(const byo_graph *g, int64_t *max_deg, int64_t *isolated, double *mean,
+                           double *cv);
+
+/* ------------------------------------------------------------------------
+ * vertexSubset (Section 3.2): sparse (IDs) or dense (bit array u64[ceil(n/64)],
+ * bit v%64 of word v/64; Section 4.4 replaces the bool array with this).
+ * ---------------------------------------------------------------------- */
+byo_status byo_vset_create(const byo_graph *g, byo_vset **out);   /* empty subset */
+void byo_vset_destroy(byo_vset *s);
+/* Replace the contents with k distinct IDs from device memory (each < n). */
+byo_status byo_vset_from_ids(byo_vset *s, const int32_t *d_ids, int64_t k, void *stream);
+/* Replace the contents with a device bitmap of ceil(n/64) words (bits >= n ignored). */
+byo_status byo_vset_from_bitmap(byo_vset *s, const uint64_t *d_bits, void *stream);
+byo_status byo_vset_fill(byo_vset *s, void *stream);              /* all n vertices */
+byo_status byo_vset_size(byo_vset *s, int64_t *out, void *stream); /* |s|, syncs */
+/* Write the members in ascending order to d_ids (capacity cap); *k = |s|.
+ * BYO_EINVAL if cap < |s|. Syncs. */
+byo_status byo_vset_to_ids(byo_vset *s, int32_t *d_ids, int64_t cap, int64_t *k, void *stream);
+/* Write the dense form (ceil(n/64) words, bits >= n zero) to d_bits. */
+byo_status byo_vset_to_bitmap(byo_vset *s, uint64_t *d_bits, void *stream);
+
+/* ------------------------------------------------------------------------
+ * edgeMap(G, U, F) (Section 3.2): apply F to edges out of U and return in
+ * `out` the targets F accepts. F is a closed set of functors whose state is
+ * device memory:
+ *   BYO_F_BFS:    state byo_bfs_fn. For u in U, v in N(u) with parent[v] == -1:
+ *                 set parent[v] = u (any such u), depth[v] = level + 1, emit v,
+ *                 and set bit v of `visited`. Requires: visited bit v is set
+ *                 iff parent[v] != -1, with bits >= n set in the last word.
+ *   BYO_F_CC_MIN: state byo_cc_fn. For u in U, v in N(u): label[v] =
+ *                 min(label[v], label[u]); emit v if its label decreased.
+ *   BYO_F_PR_ACC: state byo_pr_fn. acc[v] = sum over u in N(v) and U of
+ *                 contrib[u] (every v; FP32; U must be the full set).
+ * `variant` < 0 lets opts->selector choose; otherwise the given variant runs
+ * (PR_ACC ignores it). *variant_used (nullable) receives the choice.
+ * ---------------------------------------------------------------------- */
+typedef enum { BYO_F_BFS = 0, BYO_F_CC_MIN = 1, BYO_F_PR_ACC = 2 } byo_edge_fn;
+typedef struct { int32_t *parent; int32_t *depth; uint64_t *visited; int32_t level; } byo_bfs_fn;
+typedef struct { int32_t *label; } byo_cc_fn;
+typedef struct { const float *contrib; float *acc; } byo_pr_fn;
+
+byo_status byo_edge_map(byo_graph *g, byo_vset *U, byo_edge_fn F, const void *F_state, byo_vset *out,
+                        int32_t variant, const byo_opts *opts, void *stream, int32_t *variant_used);
+
+/* ------------------------------------------------------------------------
+ * Algorithms (Table algs-list). Outputs are caller-owned device arrays of n.
+ * ---------------------------------------------------------------------- */
+/* BFS from src: depth[v] = hop distance (-1 unreached), parent[v] = a
+ * neighbour at depth - 1 (parent[src] = src, -1 unreached). */
+byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
+                   void *stream, byo_run_stats *stats);
+/* Connectivity by min-label propagation over edgeMap: label[v] = smallest
+ * vertex ID in v's component. */
+byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *stream, byo_run_stats *stats);
+/* PageRank, FP32, `iters` steps from 1/n: p'[v] = (1-d)/n + d * (sum over
+ * u in N(v) of p[u]/deg(u) + D/n), D = mass on degree-0 vertices. */
+byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, float *d_rank, const byo_opts *opts,
+                        void *stream, byo_run_stats *stats);
+/* Multi-source BFS from k <= 256 sources, 64 sources per u64 word.
+ * d_depth is vertex-major uint8: depth[v * k + j] = hop distance from
+ * h_srcs[j] (255 = unreached). BYO_ELIMIT if a distance reaches 255. */
+byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, uint8_t *d_depth, const byo_opts *opts,
+                     void *stream, byo_run_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Batched execution over many graphs (host CSRs): the graphs are laid out
+ * back to back in one device CSR (a disjoint union) and traversed together,
+ * so uneven sizes share every launch.
+ * ---------------------------------------------------------------------- */
+byo_status byo_batch_create(int32_t count, const int64_t *const *h_offs, const int32_t *const *h_nbrs,
+                            const int64_t *ns, void *stream, byo_batch **out);
+void byo_batch_destroy(byo_batch *b);
+byo_status byo_batch_info(const byo_batch *b, int64_t *total_n, int64_t *total_m);
+/* Vertex offset of graph i in the concatenated numbering (i in [0, count]). */
+byo_status byo_batch_vertex_offset(const byo_batch *b, int32_t i, int64_t *out);
+/* BFS in every graph at once: h_srcs[i] is the source of graph i (local ID).
+ * Outputs are concatenated: entries [voff(i), voff(i+1)) belong to graph i,
+ * parent IDs are local to their graph. */
+byo_status byo_batch_bfs(byo_batch *b, const int64_t *h_srcs, int32_t *d_depth, int32_t *d_parent,
+                         const byo_opts *opts, void *stream, byo_run_stats *stats);
+/* Connectivity in every graph at once; labels are local IDs. */
+byo_status byo_batch_cc(byo_batch *b, int32_t *d_label, const byo_opts *opts, void *stream,
+                        byo_run_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BYO_H_ */

@@ -1,0 +1,249 @@
+"""MI355X (gfx950) edgeMap traversal library: Python binding.
+
+Thin wrapper over the C ABI (include/byo.h): it converts arguments, allocates
+outputs as torch tensors on the current HIP device and passes the current
+stream. All traversal work runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (ByoError, F_BFS, F_CC_MIN, F_PR_ACC, NUM_VARIANTS, SEL_FIXED, SEL_HEURISTIC, SEL_MLP,
+                   V_PULL_THREAD, V_PULL_WAVE, V_PUSH_BUCKET, V_PUSH_EDGE, V_PUSH_THREAD, V_PUSH_WAVE, VARIANTS,
+                   default_opts)
+
+__all__ = ["Graph", "VSet", "bfs", "cc", "pagerank", "edge_map", "csr_from_pairs", "default_opts", "ByoError",
+           "VARIANTS", "NUM_VARIANTS"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def csr_from_pairs(n: int, src: np.ndarray, dst: np.ndarray):
+    """Host CSR (int64 offsets, int32 sorted unique neighbours) from raw pairs."""
+    lib = _lib.load()
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    off = np.empty(n + 1, np.int64)
+    nbr = np.empty(max(2 * src.shape[0], 1), np.int32)
+    m = ctypes.c_int64(0)
+    _lib.check(lib.byo_csr_from_pairs(src.ctypes.data, dst.ctypes.data, src.shape[0], n, off.ctypes.data,
+                                      nbr.ctypes.data, ctypes.byref(m)))
+    return off, nbr[: m.value]
+
+
+class Graph:
+    """CSR GraphContainer on the current device (num_vertices, num_edges, degree, map_neighbors)."""
+
+    def __init__(self, handle, n, m, keep=None):
+        self._h = handle
+        self.n = n
+        self.m = m
+        self._keep = keep
+
+    @classmethod
+    def from_csr(cls, off: np.ndarray, nbr: np.ndarray, validate: bool = False):
+        lib = _lib.load()
+        off = np.ascontiguousarray(off, np.int64)
+        nbr = np.ascontiguousarray(nbr, np.int32)
+        n = off.shape[0] - 1
+        m = int(off[-1]) if n >= 0 else 0
+        h = ctypes.c_void_p()
+        flags = _lib.HOST_INPUT | (_lib.VALIDATE if validate else 0)
+        _lib.check(lib.byo_graph_from_csr(off.ctypes.data, nbr.ctypes.data if nbr.size else None, n, m, flags,
+                                          _stream(), ctypes.byref(h)))
+        return cls(h, n, m)
+
+    @classmethod
+    def from_device_csr(cls, off_t, nbr_t, borrow: bool = True, validate: bool = False):
+        lib = _lib.load()
+        n = off_t.shape[0] - 1
+        m = nbr_t.shape[0]
+        h = ctypes.c_void_p()
+        flags = (_lib.DEVICE_BORROW if borrow else _lib.DEVICE_COPY) | (_lib.VALIDATE if validate else 0)
+        _lib.check(lib.byo_graph_from_csr(_ptr(off_t), _ptr(nbr_t), n, m, flags, _stream(), ctypes.byref(h)))
+        return cls(h, n, m, keep=(off_t, nbr_t) if borrow else None)
+
+    @classmethod
+    def from_pairs(cls, pairs, validate: bool = False):
+        off, nbr = csr_from_pairs(pairs.n, pairs.src, pairs.dst)
+        g = cls.from_csr(off, nbr, validate=validate)
+        return g
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().byo_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def num_vertices(self) -> int:
+        return int(_lib.load().byo_num_vertices(self._h))
+
+    def num_edges(self) -> int:
+        return int(_lib.load().byo_num_edges(self._h))
+
+    def degree(self, v: int) -> int:
+        out = ctypes.c_int64()
+        _lib.check(_lib.load().byo_degree(self._h, v, ctypes.byref(out)))
+        return out.value
+
+    def neighbors(self, v: int) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        d = self.degree(v)
+        buf = np.empty(max(d, 1), np.int32)
+        _lib.check(_lib.load().byo_get_neighbors(self._h, v, buf.ctypes.data, d, ctypes.byref(cnt)))
+        return buf[: cnt.value]
+
+    def stats(self):
+        mx, iso = ctypes.c_int64(), ctypes.c_int64()
+        mean, cv = ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.load().byo_graph_stats(self._h, ctypes.byref(mx), ctypes.byref(iso), ctypes.byref(mean),
+                                               ctypes.byref(cv)))
+        return {"max_degree": mx.value, "isolated": iso.value, "mean_degree": mean.value, "cv_degree": cv.value}
+
+    def device_arrays(self):
+        """(off, nbr, deg) device pointers as ints."""
+        o, nb, d = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _lib.check(_lib.load().byo_graph_arrays(self._h, ctypes.byref(o), ctypes.byref(nb), ctypes.byref(d)))
+        return o.value, nb.value, d.value
+
+
+class VSet:
+    """vertexSubset over a graph: sparse ID list and/or dense bitmap on the device."""
+
+    def __init__(self, g: Graph):
+        self.g = g
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().byo_vset_create(g.handle, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                _lib.load().byo_vset_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def set_ids(self, ids_t):
+        _lib.check(_lib.load().byo_vset_from_ids(self._h, _ptr(ids_t) if ids_t.numel() else None, ids_t.numel(),
+                                                 _stream()))
+        return self
+
+    def set_bitmap(self, bits_t):
+        _lib.check(_lib.load().byo_vset_from_bitmap(self._h, _ptr(bits_t), _stream()))
+        return self
+
+    def fill(self):
+        _lib.check(_lib.load().byo_vset_fill(self._h, _stream()))
+        return self
+
+    def size(self) -> int:
+        out = ctypes.c_int64()
+        _lib.check(_lib.load().byo_vset_size(self._h, ctypes.byref(out), _stream()))
+        return out.value
+
+    def ids(self):
+        torch = _torch()
+        k = self.size()
+        out = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
+        got = ctypes.c_int64()
+        _lib.check(_lib.load().byo_vset_to_ids(self._h, _ptr(out), out.numel(), ctypes.byref(got), _stream()))
+        return out[: got.value]
+
+    def bitmap(self):
+        torch = _torch()
+        words = (self.g.n + 63) // 64
+        out = torch.empty(max(words, 1), dtype=torch.int64, device="cuda")
+        _lib.check(_lib.load().byo_vset_to_bitmap(self._h, _ptr(out), _stream()))
+        return out[:words]
+
+
+def _opts(opts, kw):
+    if opts is None:
+        opts = default_opts(**kw)
+    elif kw:
+        for k, v in kw.items():
+            setattr(opts, k, int(v))
+    return opts
+
+
+def bfs(g: Graph, src: int, opts=None, depth=None, parent=None, **kw):
+    """BFS from src: (depth, parent, stats) as int32 device tensors."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    depth = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if depth is None else depth
+    parent = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if parent is None else parent
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_bfs(g.handle, int(src), _ptr(depth), _ptr(parent), ctypes.byref(o), _stream(),
+                                   ctypes.byref(stt)))
+    return depth[: g.n], parent[: g.n], stt.as_dict()
+
+
+def cc(g: Graph, opts=None, label=None, **kw):
+    """Min-ID component labels (int32 device tensor) and stats."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    label = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if label is None else label
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_cc(g.handle, _ptr(label), ctypes.byref(o), _stream(), ctypes.byref(stt)))
+    return label[: g.n], stt.as_dict()
+
+
+def pagerank(g: Graph, damping: float = 0.85, iters: int = 20, opts=None, rank=None, **kw):
+    """FP32 PageRank after `iters` steps (float32 device tensor)."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    rank = torch.empty(max(g.n, 1), dtype=torch.float32, device="cuda") if rank is None else rank
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_pagerank(g.handle, float(damping), int(iters), _ptr(rank), ctypes.byref(o),
+                                        _stream(), ctypes.byref(stt)))
+    return rank[: g.n], stt.as_dict()
+
+
+def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, opts=None, **kw) -> int:
+    """edgeMap(G, U, F) into `out`; returns the variant that ran."""
+    o = _opts(opts, kw)
+    used = ctypes.c_int32(-1)
+    _lib.check(_lib.load().byo_edge_map(g.handle, U.handle, int(fn), ctypes.byref(state), out.handle, int(variant),
+                                        ctypes.byref(o), _stream(), ctypes.byref(used)))
+    return used.value
+
+
+def bfs_fn_state(parent_t, depth_t, visited_t, level: int):
+    return _lib.BfsFn(parent_t.data_ptr(), depth_t.data_ptr(), visited_t.data_ptr(), int(level))
+
+
+def cc_fn_state(label_t):
+    return _lib.CcFn(label_t.data_ptr())
+
+
+def pr_fn_state(contrib_t, acc_t):
+    return _lib.PrFn(contrib_t.data_ptr(), acc_t.data_ptr())

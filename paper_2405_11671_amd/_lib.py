@@ -1,0 +1,143 @@
+"""ctypes declarations for libbyo.so (the C ABI in include/byo.h).
+
+Argument marshalling only: every step of the traversal runs in the library's
+HIP kernels. Importing fails loudly when the built library is missing; there is
+no host fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbyo.so")
+
+NUM_VARIANTS = 6
+VARIANTS = ("push_thread", "push_wave", "push_bucket", "push_edge", "pull_thread", "pull_wave")
+V_PUSH_THREAD, V_PUSH_WAVE, V_PUSH_BUCKET, V_PUSH_EDGE, V_PULL_THREAD, V_PULL_WAVE = range(6)
+SEL_HEURISTIC, SEL_MLP, SEL_FIXED = 0, 1, 2
+F_BFS, F_CC_MIN, F_PR_ACC = 0, 1, 2
+HOST_INPUT, DEVICE_COPY, DEVICE_BORROW, VALIDATE = 0x1, 0x2, 0x4, 0x8
+
+STATUS = {0: "BYO_OK", -1: "BYO_EINVAL", -2: "BYO_ENOMEM", -3: "BYO_EHIP", -4: "BYO_ELIMIT", -5: "BYO_ESTATE"}
+
+
+class ByoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("selector", ctypes.c_int32), ("fixed_variant", ctypes.c_int32),
+                ("dense_divisor", ctypes.c_int32), ("t_wave", ctypes.c_int32),
+                ("t_block", ctypes.c_int32), ("max_levels", ctypes.c_int32),
+                ("cc_shortcut", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("device_levels", ctypes.c_int32),
+                ("variant_count", ctypes.c_int64 * NUM_VARIANTS),
+                ("reached", ctypes.c_int64), ("edges", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {"levels": self.levels, "device_levels": self.device_levels,
+                "variant_count": dict(zip(VARIANTS, list(self.variant_count))),
+                "reached": self.reached, "edges": self.edges}
+
+
+class BfsFn(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("visited", ctypes.c_void_p),
+                ("level", ctypes.c_int32)]
+
+
+class CcFn(ctypes.Structure):
+    _fields_ = [("label", ctypes.c_void_p)]
+
+
+class PrFn(ctypes.Structure):
+    _fields_ = [("contrib", ctypes.c_void_p), ("acc", ctypes.c_void_p)]
+
+
+_lib = None
+
+vp = ctypes.c_void_p
+i32 = ctypes.c_int32
+i64 = ctypes.c_int64
+u32 = ctypes.c_uint32
+i64p = ctypes.POINTER(ctypes.c_int64)
+i32p = ctypes.POINTER(ctypes.c_int32)
+dbl = ctypes.c_double
+dblp = ctypes.POINTER(ctypes.c_double)
+st = ctypes.c_int
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "byo_last_error": (ctypes.c_char_p, []),
+    "byo_version": (ctypes.c_char_p, []),
+    "byo_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "byo_csr_from_pairs": (st, [vp, vp, i64, i64, vp, vp, i64p]),
+    "byo_graph_from_csr": (st, [vp, vp, i64, i64, u32, vp, ctypes.POINTER(vp)]),
+    "byo_graph_destroy": (None, [vp]),
+    "byo_num_vertices": (i64, [vp]),
+    "byo_num_edges": (i64, [vp]),
+    "byo_degree": (st, [vp, i64, i64p]),
+    "byo_get_neighbors": (st, [vp, i64, vp, i64, i64p]),
+    "byo_graph_arrays": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+    "byo_graph_stats": (st, [vp, i64p, i64p, dblp, dblp]),
+    "byo_vset_create": (st, [vp, ctypes.POINTER(vp)]),
+    "byo_vset_destroy": (None, [vp]),
+    "byo_vset_from_ids": (st, [vp, vp, i64, vp]),
+    "byo_vset_from_bitmap": (st, [vp, vp, vp]),
+    "byo_vset_fill": (st, [vp, vp]),
+    "byo_vset_size": (st, [vp, i64p, vp]),
+    "byo_vset_to_ids": (st, [vp, vp, i64, i64p, vp]),
+    "byo_vset_to_bitmap": (st, [vp, vp, vp]),
+    "byo_edge_map": (st, [vp, vp, i32, vp, vp, i32, ctypes.POINTER(Opts), vp, i32p]),
+    "byo_bfs": (st, [vp, i64, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
+    "byo_cc": (st, [vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
+    "byo_pagerank": (st, [vp, dbl, i32, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
+}
+
+
+def _declare(lib, sigs):
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+
+
+def extra_signatures():
+    """Signatures of entry points declared in the other public headers."""
+    from . import _lib_ext
+    return _lib_ext.SIGNATURES
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2405_11671_amd.build.build() "
+                              "(the HIP library is required: there is no fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        _declare(lib, SIGNATURES)
+        _declare(lib, extra_signatures())
+        _lib = lib
+    return _lib
+
+
+def check(status: int):
+    if status != 0:
+        msg = load().byo_last_error().decode(errors="replace")
+        raise ByoError(status, msg)
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().byo_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(f"unknown option {k}")
+        setattr(o, k, int(v))
+    return o

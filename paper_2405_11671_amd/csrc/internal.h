@@ -1,0 +1,244 @@
+// Internal declarations shared by the library's HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "byo.h"
+
+// ---------------------------------------------------------------- errors
+
+namespace byo {
+
+void set_error(const std::string &msg);
+byo_status fail(byo_status st, const std::string &msg);
+byo_status hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+}  // namespace byo
+
+#define BYO_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t _e = (call);                                                  \
+    if (_e != hipSuccess) return byo::hip_fail(_e, #call, __FILE__, __LINE__); \
+  } while (0)
+
+#define BYO_CHECK(cond, st, msg)            \
+  do {                                      \
+    if (!(cond)) return byo::fail((st), (msg)); \
+  } while (0)
+
+#define BYO_TRY(expr)                      \
+  do {                                     \
+    byo_status _s = (expr);                \
+    if (_s != BYO_OK) return _s;           \
+  } while (0)
+
+// ---------------------------------------------------------------- device helpers
+
+#define BYO_WAVE 64
+#define BYO_NUM_XCD 8
+
+namespace byo {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (lane_id() == 0) ? 0ull : (~0ull >> (64 - lane_id()));
+}
+
+// Uniform read of lane `src`'s value (v_readlane; independent of EXEC).
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int src) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ int32_t read_lane_i32(int32_t v, int src) {
+  return (int32_t)__builtin_amdgcn_readlane((uint32_t)v, src);
+}
+
+// Wavefront-aggregated append: every active lane with `pred` writes `val`
+// into out[] at a slot reserved with one atomic per wavefront. Safe in
+// divergent code (ballot and readlane act on the active lanes only).
+__device__ __forceinline__ void wave_append(bool pred, int32_t val, int32_t *out,
+                                            unsigned long long *count) {
+  uint64_t m = __ballot(pred);
+  if (m == 0) return;
+  int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  base = read_lane_u64(base, leader);
+  if (pred) out[base + __popcll(m & lanemask_lt())] = val;
+}
+
+// Hardware places workgroup b on XCD b % 8. Remap so that each XCD receives
+// one contiguous range of logical block indices (its L2 then holds one range).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nblocks) {
+  uint32_t per = nblocks / BYO_NUM_XCD, rem = nblocks % BYO_NUM_XCD;
+  uint32_t x = bid % BYO_NUM_XCD, i = bid / BYO_NUM_XCD;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// Block-wide sum; result valid in every thread. All threads must call it.
+template <typename T, int BLOCK>
+__device__ __forceinline__ T block_sum(T v) {
+  __shared__ T part[BLOCK / BYO_WAVE];
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) part[threadIdx.x / BYO_WAVE] = v;
+  __syncthreads();
+  T r = 0;
+#pragma unroll
+  for (int i = 0; i < BLOCK / BYO_WAVE; ++i) r += part[i];
+  return r;
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t *bits, int64_t v) {
+  return (bits[v >> 6] >> (v & 63)) & 1ull;
+}
+
+}  // namespace byo
+
+// ---------------------------------------------------------------- objects
+
+// Per-level counters written by edgeMap kernels (ring of slots, see edgemap).
+struct byo_counters {
+  unsigned long long count;   // vertices emitted
+  unsigned long long degsum;  // sum of their degrees
+  unsigned long long aux0;    // variant-specific (e.g. edges inspected)
+  unsigned long long aux1;
+};
+#define BYO_COUNTER_SLOTS 4
+
+struct byo_workspace {
+  int64_t n = 0;
+  int64_t words = 0;
+  uint64_t *visited = nullptr;       // [words]
+  uint64_t *bits[2] = {nullptr, nullptr};  // frontier bitmaps
+  int32_t *ids[2] = {nullptr, nullptr};    // frontier ID lists
+  long long *scan = nullptr;         // [n + 1] exclusive scans over frontier degrees
+  long long *partial = nullptr;      // block partials for scans / compaction
+  int64_t partial_cap = 0;
+  byo_counters *ctr = nullptr;       // [BYO_COUNTER_SLOTS]
+  byo_counters *h_ctr = nullptr;     // pinned host mirror
+  int32_t *misc = nullptr;           // small device scratch (flags)
+  // PageRank
+  float *contrib[2] = {nullptr, nullptr};
+  float *dpart = nullptr;            // dangling partial sums
+  float *base = nullptr;             // per-iteration constant term
+  int64_t *heavy_rows = nullptr;     // rows split into chunks
+  int64_t *chunk_row = nullptr;      // per chunk: row
+  int64_t *chunk_beg = nullptr;      // per chunk: first edge
+  int32_t *row_chunk0 = nullptr;     // per vertex: first chunk index (or -1)
+  float *chunk_sum = nullptr;
+  int64_t nchunks = -1;
+  int32_t pr_dpart_blocks = 0;
+};
+
+struct byo_graph {
+  int64_t n = 0, m = 0;
+  int64_t *off = nullptr;
+  int32_t *nbr = nullptr;
+  int32_t *deg = nullptr;
+  bool owns_csr = false;
+  int device = 0;
+  int64_t max_deg = 0, isolated = 0;
+  double mean_deg = 0.0, cv_deg = 0.0;
+  byo_workspace ws;
+};
+
+// vertexSubset: which representations are current is tracked by flags.
+struct byo_vset {
+  const byo_graph *g = nullptr;
+  int64_t n = 0, words = 0;
+  int32_t *ids = nullptr;      // [n]
+  uint64_t *bits = nullptr;    // [words]
+  bool sparse_valid = false;
+  bool dense_valid = false;
+  int64_t count = 0;           // |U| (always known on the host)
+  unsigned long long *d_tmp = nullptr;
+};
+
+// ---------------------------------------------------------------- internal API
+
+namespace byo {
+
+byo_status ws_ensure_traversal(byo_graph *g);
+byo_status ws_ensure_pagerank(byo_graph *g, hipStream_t s);
+void ws_free(byo_workspace &ws);
+
+// conversions (vset.hip)
+byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);
+byo_status ids_to_bitmap(const int32_t *ids, int64_t k, uint64_t *bits, int64_t words, hipStream_t s);
+// Ascending compaction of a bitmap into ids; writes the count to d_count.
+byo_status bitmap_to_ids(const uint64_t *bits, int64_t words, int64_t n, int32_t *ids,
+                         long long *partial, int64_t partial_cap, unsigned long long *d_count,
+                         hipStream_t s);
+int64_t compaction_blocks(int64_t words);
+byo_status fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
+byo_status fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
+byo_status sync_read(hipStream_t s, const void *d_src, void *h_dst, size_t bytes);
+
+// exclusive scan of frontier degrees: scan[i] = sum_{j<i} deg(ids[j]); scan[k] = total
+byo_status frontier_degree_scan(const byo_graph *g, const int32_t *ids, int64_t k, long long *scan,
+                                long long *partial, int64_t partial_cap, hipStream_t s);
+
+struct level_io {
+  // input frontier
+  const int32_t *in_ids;
+  const uint64_t *in_bits;
+  int64_t in_count;
+  // output frontier
+  int32_t *out_ids;       // may be null for dense-only output
+  uint64_t *out_bits;     // may be null for sparse-only output
+  byo_counters *ctr;      // this level's counter slot
+  byo_counters *ctr_clear;  // slot to zero for a later level (may be null)
+};
+
+struct bfs_state {
+  int32_t *parent;
+  int32_t *depth;
+  uint64_t *visited;
+  int32_t level;
+};
+
+// One BFS edgeMap level with the given variant. Push variants need in_ids
+// (and the degree scan for PUSH_EDGE in g->ws.scan); pull variants need
+// in_bits and produce dense output (out_bits) only.
+// known_total: sum of deg(U) if the caller knows it (skips a read-back), else -1.
+byo_status bfs_level(byo_graph *g, int variant, const bfs_state &st, const level_io &io,
+                     const byo_opts &o, hipStream_t s, long long known_total = -1);
+byo_status cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, const byo_opts &o,
+                    hipStream_t s, long long known_total = -1);
+// acc[v] = sum over u in N(v) of contrib[u] (pagerank.hip)
+byo_status pr_accumulate(byo_graph *g, const float *contrib, float *acc, hipStream_t s);
+byo_status cc_shortcut(byo_graph *g, int32_t *label, uint64_t *out_bits, byo_counters *ctr, hipStream_t s);
+
+// variant choice (selector.hip)
+struct level_features {
+  int64_t n, m, k, degsum, unvisited, max_deg, level;
+  double cv;
+  bool dense_in;
+};
+int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull);
+int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull);
+
+}  // namespace byo

@@ -1,0 +1,363 @@
+// Level loops for BFS and min-label connectivity over edgeMap (paper Table
+// algs-list; BFS emits unvisited neighbours, Section 3.2), the public
+// edgeMap entry point, and the direction / load-balance choice made before
+// every edgeMap call from |U|, sum(deg(U)) and m (Section 6.3: num_edges and
+// degree decide the sparse/dense cutoff).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace byo {
+
+// ---------------------------------------------------------------- variant choice
+
+static bool is_pull(int v) { return v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE; }
+
+int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull) {
+  int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
+  bool dense = allow_pull && (f.k + f.degsum > f.m / div);
+  if (dense) return (f.cv > 1.0 || f.max_deg > 4 * (o.t_wave > 0 ? o.t_wave : 32)) ? BYO_V_PULL_WAVE
+                                                                                   : BYO_V_PULL_THREAD;
+  // sparse: edge-balanced when the graph is skewed or the frontier is heavy
+  double avg = f.k > 0 ? (double)f.degsum / (double)f.k : 0.0;
+  if (f.max_deg >= (o.t_block > 0 ? o.t_block : 4096) || f.degsum >= 65536) return BYO_V_PUSH_EDGE;
+  if (avg >= (o.t_wave > 0 ? o.t_wave : 32)) return BYO_V_PUSH_WAVE;
+  return BYO_V_PUSH_THREAD;
+}
+
+// The learned selector lives in mlp.hip; it returns -1 when it has no weights.
+int mlp_choose_variant(const level_features &f, bool allow_pull);
+
+int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) {
+  if (o.selector == BYO_SEL_FIXED) {
+    int v = o.fixed_variant;
+    if (v < 0 || v >= BYO_NUM_VARIANTS) v = BYO_V_PUSH_EDGE;
+    if (!allow_pull && is_pull(v)) v = BYO_V_PUSH_EDGE;
+    return v;
+  }
+  if (o.selector == BYO_SEL_MLP) {
+    int v = mlp_choose_variant(f, allow_pull);
+    if (v >= 0) return v;
+  }
+  return heuristic_variant(o, f, allow_pull);
+}
+
+// ---------------------------------------------------------------- small kernels
+
+__global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, uint64_t *visited, int64_t n, int64_t words,
+                                int32_t src, int32_t *ids, byo_counters *ctr, const int32_t *deg) {
+  // called with one block after the fills
+  if (threadIdx.x < BYO_COUNTER_SLOTS) {
+    ctr[threadIdx.x].count = 0;
+    ctr[threadIdx.x].degsum = 0;
+    ctr[threadIdx.x].aux0 = 0;
+    ctr[threadIdx.x].aux1 = 0;
+  }
+  if (threadIdx.x == 0) {
+    parent[src] = src;
+    depth[src] = 0;
+    uint64_t tail = (n & 63) ? (~0ull << (n & 63)) : 0ull;
+    if (words > 0 && (int64_t)(src >> 6) == words - 1)
+      visited[src >> 6] = tail | (1ull << (src & 63));
+    else {
+      visited[src >> 6] = 1ull << (src & 63);
+      if (words > 0) visited[words - 1] = tail;
+    }
+    ids[0] = src;
+  }
+}
+
+__global__ void set_tail_kernel(uint64_t *bits, int64_t n, int64_t words) {
+  if (threadIdx.x == 0 && (n & 63)) bits[words - 1] |= (~0ull << (n & 63));
+}
+
+__global__ void iota_kernel(int32_t *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = (int32_t)i;
+}
+
+__global__ void zero_counters_kernel(byo_counters *ctr) {
+  if (threadIdx.x < BYO_COUNTER_SLOTS) {
+    ctr[threadIdx.x].count = 0;
+    ctr[threadIdx.x].degsum = 0;
+    ctr[threadIdx.x].aux0 = 0;
+    ctr[threadIdx.x].aux1 = 0;
+  }
+}
+
+static byo_status read_slot(byo_graph *g, int slot, hipStream_t s, byo_counters *out) {
+  BYO_HIP(hipMemcpyAsync(g->ws.h_ctr + slot, g->ws.ctr + slot, sizeof(byo_counters), hipMemcpyDeviceToHost, s));
+  BYO_HIP(hipStreamSynchronize(s));
+  *out = g->ws.h_ctr[slot];
+  return BYO_OK;
+}
+
+static level_features features(const byo_graph *g, int64_t k, int64_t degsum, int64_t unvisited, int64_t level,
+                               bool dense_in) {
+  level_features f;
+  f.n = g->n;
+  f.m = g->m;
+  f.k = k;
+  f.degsum = degsum;
+  f.unvisited = unvisited;
+  f.max_deg = g->max_deg;
+  f.level = level;
+  f.cv = g->cv_deg;
+  f.dense_in = dense_in;
+  return f;
+}
+
+// Frontier held in the workspace: ids[cur] and/or bits[cur].
+struct frontier {
+  int cur = 0;
+  bool sparse = false, dense = false;
+  int64_t k = 0, degsum = 0;
+};
+
+static byo_status make_sparse(byo_graph *g, frontier &fr, hipStream_t s) {
+  if (fr.sparse) return BYO_OK;
+  byo_workspace &w = g->ws;
+  BYO_TRY(bitmap_to_ids(w.bits[fr.cur], w.words, g->n, w.ids[fr.cur], w.partial, w.partial_cap,
+                        (unsigned long long *)w.misc, s));
+  fr.sparse = true;
+  return BYO_OK;
+}
+
+static byo_status make_dense(byo_graph *g, frontier &fr, hipStream_t s) {
+  if (fr.dense) return BYO_OK;
+  byo_workspace &w = g->ws;
+  BYO_TRY(ids_to_bitmap(w.ids[fr.cur], fr.k, w.bits[fr.cur], w.words, s));
+  fr.dense = true;
+  return BYO_OK;
+}
+
+}  // namespace byo
+
+using namespace byo;
+
+extern "C" {
+
+byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
+                   void *stream, byo_run_stats *stats) {
+  BYO_CHECK(g && d_depth && d_parent, BYO_EINVAL, "null argument");
+  BYO_CHECK(src >= 0 && src < g->n, BYO_EINVAL, "source out of range");
+  byo_opts o;
+  byo_opts_default(&o);
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  BYO_TRY(ws_ensure_traversal(g));
+  byo_workspace &w = g->ws;
+  int64_t n = g->n;
+  BYO_TRY(fill_i32(d_parent, n, -1, s));
+  BYO_TRY(fill_i32(d_depth, n, -1, s));
+  BYO_TRY(fill_u64(w.visited, w.words, 0ull, s));
+  bfs_init_kernel<<<1, 64, 0, s>>>(d_parent, d_depth, w.visited, n, w.words, (int32_t)src, w.ids[0], w.ctr,
+                                   g->deg);
+  BYO_HIP(hipGetLastError());
+  int32_t dsrc = 0;
+  BYO_TRY(sync_read(s, g->deg + src, &dsrc, sizeof(dsrc)));
+
+  byo_run_stats st;
+  std::memset(&st, 0, sizeof(st));
+  frontier fr;
+  fr.cur = 0;
+  fr.sparse = true;
+  fr.k = 1;
+  fr.degsum = dsrc;
+  int64_t reached = 1, edges = dsrc;
+  int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
+  bfs_state bs{d_parent, d_depth, w.visited, 0};
+  int32_t level = 0;
+  while (true) {
+    if (level >= cap) {
+      if (stats) *stats = st;
+      return fail(BYO_ELIMIT, "BFS level cap reached");
+    }
+    level_features f = features(g, fr.k, fr.degsum, n - reached, level, fr.dense && !fr.sparse);
+    int v = choose_variant(o, f, true);
+    int nxt = 1 - fr.cur;
+    level_io io;
+    std::memset(&io, 0, sizeof(io));
+    io.in_count = fr.k;
+    io.ctr = w.ctr + (level % BYO_COUNTER_SLOTS);
+    io.ctr_clear = w.ctr + ((level + 2) % BYO_COUNTER_SLOTS);
+    if (is_pull(v)) {
+      BYO_TRY(make_dense(g, fr, s));
+      io.in_bits = w.bits[fr.cur];
+      io.out_bits = w.bits[nxt];
+    } else {
+      BYO_TRY(make_sparse(g, fr, s));
+      io.in_ids = w.ids[fr.cur];
+      io.out_ids = w.ids[nxt];
+    }
+    bs.level = level;
+    BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
+    st.variant_count[v]++;
+    byo_counters c;
+    BYO_TRY(read_slot(g, level % BYO_COUNTER_SLOTS, s, &c));
+    ++level;
+    if (c.count == 0) break;
+    reached += (int64_t)c.count;
+    edges += (int64_t)c.degsum;
+    fr.cur = nxt;
+    fr.sparse = !is_pull(v);
+    fr.dense = is_pull(v);
+    fr.k = (int64_t)c.count;
+    fr.degsum = (int64_t)c.degsum;
+  }
+  st.levels = level;
+  st.reached = reached;
+  st.edges = edges;
+  if (stats) *stats = st;
+  return BYO_OK;
+}
+
+byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *stream, byo_run_stats *stats) {
+  BYO_CHECK(g && d_label, BYO_EINVAL, "null argument");
+  byo_opts o;
+  byo_opts_default(&o);
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t n = g->n;
+  byo_run_stats st;
+  std::memset(&st, 0, sizeof(st));
+  if (n == 0) {
+    if (stats) *stats = st;
+    return BYO_OK;
+  }
+  BYO_TRY(ws_ensure_traversal(g));
+  byo_workspace &w = g->ws;
+  iota_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, s>>>(d_label, n);
+  zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);
+  BYO_HIP(hipGetLastError());
+  // every vertex starts in the frontier
+  BYO_TRY(fill_u64(w.bits[0], w.words, ~0ull, s));
+  if (n & 63) {
+    // clear bits >= n: the frontier bitmap never holds them
+    uint64_t last = ~0ull >> (64 - (n & 63));
+    BYO_HIP(hipMemcpyAsync(w.bits[0] + (w.words - 1), &last, sizeof(last), hipMemcpyHostToDevice, s));
+    BYO_HIP(hipStreamSynchronize(s));
+  }
+  frontier fr;
+  fr.cur = 0;
+  fr.dense = true;
+  fr.k = n;
+  fr.degsum = g->m;
+  int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
+  int32_t round = 0;
+  while (true) {
+    if (round >= cap) {
+      if (stats) *stats = st;
+      return fail(BYO_ELIMIT, "connectivity round cap reached");
+    }
+    level_features f = features(g, fr.k, fr.degsum, n, round, fr.dense && !fr.sparse);
+    int v = choose_variant(o, f, true);
+    int nxt = 1 - fr.cur;
+    level_io io;
+    std::memset(&io, 0, sizeof(io));
+    io.in_count = fr.k;
+    io.ctr = w.ctr + (round % BYO_COUNTER_SLOTS);
+    io.ctr_clear = w.ctr + ((round + 2) % BYO_COUNTER_SLOTS);
+    io.out_bits = w.bits[nxt];
+    bool shortcut = o.cc_shortcut != 0;
+    if (is_pull(v)) {
+      BYO_TRY(make_dense(g, fr, s));
+      io.in_bits = w.bits[fr.cur];
+    } else {
+      BYO_TRY(make_sparse(g, fr, s));
+      io.in_ids = w.ids[fr.cur];
+      io.out_ids = shortcut ? nullptr : w.ids[nxt];
+    }
+    BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
+    if (shortcut) BYO_TRY(cc_shortcut(g, d_label, w.bits[nxt], io.ctr, s));
+    st.variant_count[v]++;
+    byo_counters c;
+    BYO_TRY(read_slot(g, round % BYO_COUNTER_SLOTS, s, &c));
+    ++round;
+    if (c.count == 0) break;
+    fr.cur = nxt;
+    fr.dense = true;
+    fr.sparse = !is_pull(v) && !shortcut;
+    fr.k = (int64_t)c.count;
+    fr.degsum = (int64_t)c.degsum;
+  }
+  st.levels = round;
+  if (stats) *stats = st;
+  return BYO_OK;
+}
+
+byo_status byo_edge_map(byo_graph *g, byo_vset *U, byo_edge_fn F, const void *F_state, byo_vset *out,
+                        int32_t variant, const byo_opts *opts, void *stream, int32_t *variant_used) {
+  BYO_CHECK(g && U && out && F_state, BYO_EINVAL, "null argument");
+  BYO_CHECK(U->g == g && out->g == g, BYO_EINVAL, "subsets belong to another graph");
+  BYO_CHECK(U != out, BYO_EINVAL, "input and output subsets must differ");
+  BYO_CHECK(variant < BYO_NUM_VARIANTS, BYO_EINVAL, "unknown variant");
+  byo_opts o;
+  byo_opts_default(&o);
+  if (opts) o = *opts;
+  hipStream_t s = (hipStream_t)stream;
+  BYO_TRY(ws_ensure_traversal(g));
+  byo_workspace &w = g->ws;
+  if (F == BYO_F_PR_ACC) {
+    BYO_CHECK(U->count == g->n, BYO_EINVAL, "PR_ACC needs the full vertex set as input");
+    const byo_pr_fn *pf = (const byo_pr_fn *)F_state;
+    BYO_TRY(pr_accumulate(g, pf->contrib, pf->acc, s));
+    BYO_TRY(byo_vset_fill(out, stream));
+    if (variant_used) *variant_used = BYO_V_PULL_WAVE;
+    return BYO_OK;
+  }
+  BYO_CHECK(F == BYO_F_BFS || F == BYO_F_CC_MIN, BYO_EINVAL, "unknown edge function");
+  // input degree sum (needed by the selector and the edge-balanced variant)
+  if (!U->sparse_valid) {
+    BYO_TRY(bitmap_to_ids(U->bits, U->words, U->n, U->ids, w.partial, w.partial_cap, U->d_tmp, s));
+    U->sparse_valid = true;
+  }
+  long long degsum = 0;
+  if (U->count > 0) {
+    BYO_TRY(frontier_degree_scan(g, U->ids, U->count, w.scan, w.partial, w.partial_cap, s));
+    BYO_TRY(sync_read(s, w.scan + U->count, &degsum, sizeof(degsum)));
+  }
+  level_features f = features(g, U->count, degsum, g->n, 0, false);
+  int v = variant >= 0 ? variant : choose_variant(o, f, true);
+  if (is_pull(v) && !U->dense_valid) {
+    BYO_TRY(ids_to_bitmap(U->ids, U->count, U->bits, U->words, s));
+    U->dense_valid = true;
+  }
+  zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);
+  BYO_HIP(hipGetLastError());
+  level_io io;
+  std::memset(&io, 0, sizeof(io));
+  io.in_ids = U->ids;
+  io.in_bits = U->bits;
+  io.in_count = U->count;
+  io.ctr = w.ctr;
+  io.ctr_clear = nullptr;
+  io.out_bits = out->bits;
+  io.out_ids = is_pull(v) ? nullptr : out->ids;
+  if (F == BYO_F_BFS) {
+    const byo_bfs_fn *bf = (const byo_bfs_fn *)F_state;
+    BYO_CHECK(bf->parent && bf->depth && bf->visited, BYO_EINVAL, "BFS state has a null array");
+    bfs_state bs{bf->parent, bf->depth, bf->visited, bf->level};
+    if (!is_pull(v)) {
+      // push fills the dense output too, so both forms are valid afterwards
+      BYO_TRY(bitmap_clear(out->bits, out->words, s));
+    }
+    BYO_TRY(bfs_level(g, v, bs, io, o, s, degsum));
+  } else {
+    const byo_cc_fn *cf = (const byo_cc_fn *)F_state;
+    BYO_CHECK(cf->label, BYO_EINVAL, "label array is null");
+    BYO_TRY(cc_level(g, v, cf->label, io, o, s, degsum));
+  }
+  byo_counters c;
+  BYO_TRY(read_slot(g, 0, s, &c));
+  out->count = (int64_t)c.count;
+  out->dense_valid = true;
+  out->sparse_valid = !is_pull(v);
+  if (variant_used) *variant_used = v;
+  return BYO_OK;
+}
+
+}  // extern "C"
