@@ -1,0 +1,149 @@
+"""Benchmark: GTEPS of the edgeMap hot path on RMAT scale 22 (one MI355X).
+
+One step = BFS from 16 sources + PageRank (20 steps, FP32) + connectivity,
+all on the same resident graph. TEPS conventions:
+  BFS: undirected edges in the reached component per source (Graph500),
+  PageRank: iterations x m directed edges, connectivity: m/2 undirected edges.
+value = all traversed edges of the step / step time.
+
+Prints ONE JSON line (see the repository's measurement notes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--sources", type=int, default=16)
+    ap.add_argument("--pr-iters", type=int, default=20)
+    ap.add_argument("--ms-sources", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-sources", type=int, default=2)
+    ap.add_argument("--cpu-sample-pr-iters", type=int, default=2)
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2405_11671_amd as byo
+    from paper_2405_11671_amd import gen
+
+    t0 = time.time()
+    pairs = gen.rmat_pairs(args.scale, 16, gen.GRAPH500_ABCD, seed=1, permute=True)
+    srcs = gen.pick_sources(pairs, args.sources, seed=2)
+    off, nbr = byo.csr_from_pairs(pairs.n, pairs.src, pairs.dst)
+    n, m = pairs.n, int(off[-1])
+    log(f"[bench] rmat-{args.scale}: n={n} m={m} built in {time.time() - t0:.1f}s")
+    torch.cuda.init()
+    g = byo.Graph.from_csr(off, nbr)
+    torch.cuda.synchronize()
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    label = torch.empty(n, dtype=torch.int32, device="cuda")
+    rank = torch.empty(n, dtype=torch.float32, device="cuda")
+    opts = byo.default_opts()
+
+    ms_srcs = gen.pick_sources(pairs, args.ms_sources, seed=2)
+    ms_depth = torch.empty(n * len(ms_srcs), dtype=torch.uint8, device="cuda")
+
+    def step(record=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        _, mst = byo.msbfs(g, ms_srcs, opts=opts, depth=ms_depth)
+        ev[1].record()
+        byo.pagerank(g, 0.85, args.pr_iters, opts=opts, rank=rank)
+        ev[2].record()
+        _, cst = byo.cc(g, opts=opts, label=label)
+        ev[3].record()
+        ms_edges = mst["edges"] // 2
+        if record is not None:
+            torch.cuda.synchronize()
+            record.append({"ms_ms": ev[0].elapsed_time(ev[1]), "pr_ms": ev[1].elapsed_time(ev[2]),
+                           "cc_ms": ev[2].elapsed_time(ev[3]), "ms_edges": ms_edges,
+                           "ms_levels": mst["levels"], "cc_rounds": cst["levels"]})
+        return ms_edges
+
+    def plain_bfs():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        e = 0
+        for s_ in srcs:
+            _, _, st = byo.bfs(g, int(s_), opts=opts, depth=depth, parent=parent)
+            e += st["edges"] // 2
+        torch.cuda.synchronize()
+        return e / (time.perf_counter() - t) / 1e9
+
+    for _ in range(args.warmup):
+        step()
+        plain_bfs()
+    torch.cuda.synchronize()
+    rec = []
+    byo.ktimer_reset()
+    byo.ktimer_enable(True)
+    t = time.perf_counter()
+    edges_total = 0
+    for _ in range(args.steps):
+        ms_e = step(rec)
+        edges_total += ms_e + args.pr_iters * m + m // 2
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    byo.ktimer_enable(False)
+    kt = {f: byo.ktimer_read(f) for f in byo._lib.K_FAMILIES}
+    ms_per_step = wall * 1e3 / args.steps
+    value = edges_total / wall / 1e9
+    plain = [plain_bfs() for _ in range(3)]
+    ms_ms = float(np.median([r["ms_ms"] for r in rec]))
+    pr_ms = float(np.median([r["pr_ms"] for r in rec]))
+    cc_ms = float(np.median([r["cc_ms"] for r in rec]))
+    pr_launches, pr_kms = kt["pr_pull"]
+    pr_avg_ms = pr_kms / max(pr_launches, 1)
+    pr_bytes = 4 * m + 16 * n + 8          # per launch: neighbours, offsets, contrib read + write
+    detail = {
+        "msbfs_gteps": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9, "msbfs_ms": ms_ms,
+        "msbfs_sources": len(ms_srcs), "msbfs_levels": rec[0]["ms_levels"],
+        "pr_gteps": args.pr_iters * m / (pr_ms * 1e-3) / 1e9, "pr_ms": pr_ms,
+        "cc_ms": cc_ms, "cc_rounds": rec[0]["cc_rounds"],
+        "plain_bfs_gteps": float(np.median(plain)),
+        "batched_vs_plain": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9 / float(np.median(plain)),
+        "pr_pull_avg_ms": pr_avg_ms, "pr_pull_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
+        "kernel_ms": {f: round(v[1] / args.steps, 3) for f, v in kt.items() if v[0]},
+    }
+    out = {
+        "metric": "GTEPS (batched BFS + PageRank + CC edgeMap traversals) on RMAT-22",
+        "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32+f32", "data": "synthetic",
+        "config": {"workload": f"rmat-{args.scale} ef16 (0.57,0.19,0.19,0.05) symmetrized; "
+                               f"msbfs x{len(ms_srcs)} + pagerank {args.pr_iters} it + cc", "n": n, "m": m},
+        "detail": {k: round(v, 4) if isinstance(v, float) else v for k, v in detail.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

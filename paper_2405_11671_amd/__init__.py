@@ -247,3 +247,46 @@ def cc_fn_state(label_t):
 
 def pr_fn_state(contrib_t, acc_t):
     return _lib.PrFn(contrib_t.data_ptr(), acc_t.data_ptr())
+
+
+def msbfs(g: Graph, srcs, opts=None, depth=None, **kw):
+    """Multi-source BFS from up to 256 sources: uint8 depths [n, k] (255 = unreached) and stats."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    srcs = np.ascontiguousarray(np.asarray(srcs, np.int64))
+    k = int(srcs.shape[0])
+    depth = torch.empty(max(g.n * k, 1), dtype=torch.uint8, device="cuda") if depth is None else depth
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_msbfs(g.handle, srcs.ctypes.data, k, _ptr(depth), ctypes.byref(o), _stream(),
+                                     ctypes.byref(stt)))
+    return depth[: g.n * k].view(g.n, k), stt.as_dict()
+
+
+def trace_enable(on: bool = True):
+    _lib.check(_lib.load().byo_trace_enable(1 if on else 0))
+
+
+def trace_read():
+    lib = _lib.load()
+    cnt = ctypes.c_int64()
+    _lib.check(lib.byo_trace_pending(ctypes.byref(cnt)))
+    buf = (_lib.LevelRecord * max(cnt.value, 1))()
+    got = ctypes.c_int64()
+    _lib.check(lib.byo_trace_read(buf, cnt.value, ctypes.byref(got)))
+    return [buf[i].as_dict() for i in range(got.value)]
+
+
+def ktimer_enable(on: bool = True):
+    _lib.check(_lib.load().byo_ktimer_enable(1 if on else 0))
+
+
+def ktimer_reset():
+    _lib.check(_lib.load().byo_ktimer_reset())
+
+
+def ktimer_read(family):
+    """(launches, total device ms) for a kernel family name or id."""
+    fid = _lib.K_FAMILIES.index(family) if isinstance(family, str) else int(family)
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _lib.check(_lib.load().byo_ktimer_read(fid, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

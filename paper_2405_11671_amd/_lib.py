@@ -47,6 +47,21 @@ class RunStats(ctypes.Structure):
                 "reached": self.reached, "edges": self.edges}
 
 
+class LevelRecord(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("level", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("dense_in", ctypes.c_int32), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("degsum", ctypes.c_int64), ("unvisited", ctypes.c_int64),
+                ("out_count", ctypes.c_int64), ("out_degsum", ctypes.c_int64), ("max_deg", ctypes.c_int64),
+                ("cv", ctypes.c_double), ("ms", ctypes.c_float), ("reserved", ctypes.c_float)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+K_FAMILIES = ("bfs_push", "bfs_pull", "cc_push", "cc_pull", "pr_pull", "pr_chunk", "msbfs_push", "msbfs_pull",
+              "compact", "cc_shortcut", "msbfs_finish", "small_loop", "mlp")
+
+
 class BfsFn(ctypes.Structure):
     _fields_ = [("parent", ctypes.c_void_p), ("depth", ctypes.c_void_p), ("visited", ctypes.c_void_p),
                 ("level", ctypes.c_int32)]

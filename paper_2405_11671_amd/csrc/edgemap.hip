@@ -70,6 +70,50 @@ struct CcF {
   }
 };
 
+
+// ---------------------------------------------------------------- pull scans
+
+// Serial early-exit scans issue PULL_ILP independent neighbour loads (and
+// bitmap probes) per step instead of one dependent chain per neighbour.
+constexpr int PULL_ILP = 8;
+
+// First u in nbr[beg, lim) (ascending) whose bit is set in `bits`, else -1.
+__device__ __forceinline__ int32_t first_member(const int32_t *__restrict__ nbr, const uint64_t *__restrict__ bits,
+                                                int64_t beg, int64_t lim) {
+  for (int64_t e = beg; e < lim; e += PULL_ILP) {
+    int32_t u[PULL_ILP];
+    uint64_t w[PULL_ILP];
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) u[j] = (e + j < lim) ? nbr[e + j] : -1;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) w[j] = u[j] >= 0 ? bits[u[j] >> 6] : 0ull;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j)
+      if ((w[j] >> (u[j] & 63)) & 1ull) return u[j];
+  }
+  return -1;
+}
+
+// min(best, label[u] for u in nbr[beg, lim) with bit u set in `bits`).
+__device__ __forceinline__ int32_t min_member_label(const int32_t *__restrict__ nbr, const uint64_t *__restrict__ bits,
+                                                    const int32_t *label, int64_t beg, int64_t lim,
+                                                    int32_t best) {
+  for (int64_t e = beg; e < lim; e += PULL_ILP) {
+    int32_t u[PULL_ILP];
+    uint64_t w[PULL_ILP];
+    int32_t l[PULL_ILP];
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) u[j] = (e + j < lim) ? nbr[e + j] : -1;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) w[j] = u[j] >= 0 ? bits[u[j] >> 6] : 0ull;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) l[j] = ((w[j] >> (u[j] & 63)) & 1ull) ? label[u[j]] : best;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) best = l[j] < best ? l[j] : best;
+  }
+  return best;
+}
+
 // ---------------------------------------------------------------- emission
 
 __device__ __forceinline__ void wave_count(bool pred, unsigned long long *count) {
@@ -318,14 +362,8 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
       beg = a.off[v];
       end = a.off[v + 1];
       int64_t lim = WAVE_ASSIST ? (end - beg > a.t_wave ? beg + a.t_wave : end) : end;
-      for (int64_t e = beg; e < lim; ++e) {
-        int32_t u = a.nbr[e];
-        if (test_bit(a.in_bits, u)) {
-          par = u;
-          found = true;
-          break;
-        }
-      }
+      par = first_member(a.nbr, a.in_bits, beg, lim);
+      found = par >= 0;
     }
     if (WAVE_ASSIST) {
       uint64_t pm = __ballot(cand && !found && end - beg > a.t_wave);
@@ -334,18 +372,31 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
         pm &= pm - 1;
         int64_t lb = (int64_t)read_lane_u64((uint64_t)(beg + a.t_wave), l);
         int64_t le = (int64_t)read_lane_u64((uint64_t)end, l);
-        for (int64_t base = lb; base < le; base += BYO_WAVE) {
-          int64_t e = base + lane_id();
-          int32_t u = e < le ? a.nbr[e] : 0;
-          bool hit = e < le && test_bit(a.in_bits, u);
-          uint64_t hm = __ballot(hit);
-          if (hm) {
-            int32_t pu = read_lane_i32(u, __ffsll((long long)hm) - 1);
-            if (lane_id() == l) {
-              par = pu;
-              found = true;
+        bool done = false;
+        for (int64_t base = lb; base < le && !done; base += 4 * BYO_WAVE) {
+          int32_t u[4];
+          bool hit[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            int64_t e = base + j * BYO_WAVE + lane_id();
+            u[j] = e < le ? a.nbr[e] : 0;
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            int64_t e = base + j * BYO_WAVE + lane_id();
+            hit[j] = e < le && test_bit(a.in_bits, u[j]);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            uint64_t hm = __ballot(hit[j]);
+            if (hm && !done) {
+              int32_t pu = read_lane_i32(u[j], __ffsll((long long)hm) - 1);
+              if (lane_id() == l) {
+                par = pu;
+                found = true;
+              }
+              done = true;
             }
-            break;
           }
         }
       }
@@ -397,13 +448,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
       beg = a.off[v];
       end = a.off[v + 1];
       int64_t lim = WAVE_ASSIST ? (end - beg > a.t_wave ? beg + a.t_wave : end) : end;
-      for (int64_t e = beg; e < lim; ++e) {
-        int32_t u = a.nbr[e];
-        if (test_bit(a.in_bits, u)) {
-          int32_t lu = f.label[u];
-          best = lu < best ? lu : best;
-        }
-      }
+      best = min_member_label(a.nbr, a.in_bits, f.label, beg, lim, best);
     }
     if (WAVE_ASSIST) {
       uint64_t pm = __ballot(valid && end - beg > a.t_wave);
@@ -557,6 +602,7 @@ byo_status bfs_level(byo_graph *g, int variant, const bfs_state &st, const level
   if (variant == BYO_V_PULL_THREAD || variant == BYO_V_PULL_WAVE) {
     BYO_CHECK(io.in_bits && io.out_bits, BYO_EINVAL, "pull needs dense input and output");
     if (a.words == 0) return BYO_OK;
+    ktimer_scope kt(BYO_K_BFS_PULL, s);
     if (variant == BYO_V_PULL_THREAD)
       bfs_pull_kernel<false><<<pull_grid(a.words), EM_BLOCK, 0, s>>>(a, f);
     else
@@ -574,6 +620,7 @@ byo_status bfs_level(byo_graph *g, int variant, const bfs_state &st, const level
     }
     if (a.total == 0) variant = BYO_V_PUSH_THREAD;
   }
+  ktimer_scope kt(BYO_K_BFS_PUSH, s);
   return launch_push(variant, a, f, s);
 }
 
@@ -585,6 +632,7 @@ byo_status cc_level(byo_graph *g, int variant, int32_t *label, const level_io &i
   if (variant == BYO_V_PULL_THREAD || variant == BYO_V_PULL_WAVE) {
     BYO_CHECK(io.in_bits, BYO_EINVAL, "pull needs dense input");
     if (a.words == 0) return BYO_OK;
+    ktimer_scope kt(BYO_K_CC_PULL, s);
     if (variant == BYO_V_PULL_THREAD)
       cc_pull_kernel<false><<<pull_grid(a.words), EM_BLOCK, 0, s>>>(a, f);
     else
@@ -603,15 +651,75 @@ byo_status cc_level(byo_graph *g, int variant, int32_t *label, const level_io &i
     }
     if (a.total == 0) variant = BYO_V_PUSH_THREAD;
   }
+  ktimer_scope kt(BYO_K_CC_PUSH, s);
   return launch_push(variant, a, f, s);
 }
 
 byo_status cc_shortcut(byo_graph *g, int32_t *label, uint64_t *out_bits, byo_counters *ctr, hipStream_t s) {
   int64_t words = (g->n + 63) / 64;
   if (words == 0) return BYO_OK;
+  ktimer_scope kt(BYO_K_CC_SHORTCUT, s);
   cc_shortcut_kernel<<<pull_grid(words), EM_BLOCK, 0, s>>>(label, g->deg, g->n, words, out_bits, ctr);
   BYO_HIP(hipGetLastError());
   return BYO_OK;
+}
+
+// ---------------------------------------------------------------- multi-source push (bit-parallel)
+
+// Multi-source BFS push: the frontier bits of u (one bit per source) that v
+// has not seen yet are OR-ed into visit[v]; v is emitted once per level by
+// whoever first sets its bit in `touched`.
+template <int W>
+struct MsF {
+  const uint64_t *front;
+  const uint64_t *seen;
+  uint64_t *visit;
+  static constexpr bool kDenseFromUpdate = true;
+  __device__ __forceinline__ int32_t src_value(int32_t u) const { return u; }
+  __device__ __forceinline__ bool update(int32_t u, int32_t /*su*/, int32_t v, uint64_t *touched) const {
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint64_t fb = front[(int64_t)u * W + w];
+      if (!fb) continue;
+      uint64_t nb = fb & ~seen[(int64_t)v * W + w];
+      if (nb) {
+        atomicOr((unsigned long long *)&visit[(int64_t)v * W + w], (unsigned long long)nb);
+        any = true;
+      }
+    }
+    if (!any) return false;
+    uint64_t bit = 1ull << (v & 63);
+    unsigned long long prev = atomicOr((unsigned long long *)&touched[v >> 6], (unsigned long long)bit);
+    return !(prev & bit);
+  }
+};
+
+template <int W>
+static byo_status ms_push_w(byo_graph *g, int variant, const ms_state &ms, const level_io &io, const byo_opts &o,
+                            hipStream_t s, long long known_total) {
+  LevelArgs a = make_args(g, io, o);
+  MsF<W> f{ms.front, ms.seen, ms.visit};
+  if (variant == BYO_V_PUSH_EDGE && a.k > 0) {
+    BYO_TRY(frontier_degree_scan(g, io.in_ids, io.in_count, g->ws.scan, g->ws.partial, g->ws.partial_cap, s));
+    a.total = known_total;
+    if (a.total == 0) variant = BYO_V_PUSH_THREAD;
+  }
+  ktimer_scope kt(BYO_K_MSBFS_PUSH, s);
+  return launch_push(variant, a, f, s);
+}
+
+byo_status ms_push_level(byo_graph *g, int variant, const ms_state &ms, const level_io &io, const byo_opts &o,
+                         hipStream_t s, long long known_total) {
+  BYO_CHECK(io.out_bits && io.out_ids, BYO_EINVAL, "multi-source push needs touched list and bitmap");
+  BYO_CHECK(variant >= 0 && variant <= BYO_V_PUSH_EDGE, BYO_EINVAL, "multi-source push needs a push variant");
+  switch (ms.W) {
+    case 1: return ms_push_w<1>(g, variant, ms, io, o, s, known_total);
+    case 2: return ms_push_w<2>(g, variant, ms, io, o, s, known_total);
+    case 3: return ms_push_w<3>(g, variant, ms, io, o, s, known_total);
+    case 4: return ms_push_w<4>(g, variant, ms, io, o, s, known_total);
+    default: return fail(BYO_EINVAL, "1 to 4 source words");
+  }
 }
 
 }  // namespace byo

@@ -33,21 +33,38 @@ byo_status sync_read(hipStream_t s, const void *d_src, void *h_dst, size_t bytes
 
 // ---------------------------------------------------------------- kernels
 
-__global__ void degree_stats_kernel(const int64_t *__restrict__ off, int64_t n, int32_t *__restrict__ deg,
-                                    unsigned long long *__restrict__ out /* max, isolated, sumsq */) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long d = 0;
-  if (v < n) {
-    d = (unsigned long long)(off[v + 1] - off[v]);
-    deg[v] = (int32_t)d;
+// deg[v] = off[v+1] - off[v]; zero_bits = bitmap of degree-0 vertices;
+// out = {max degree, number of degree-0 vertices, sum of squared degrees}.
+__global__ void __launch_bounds__(256) degree_stats_kernel(const int64_t *__restrict__ off, int64_t n,
+                                                           int32_t *__restrict__ deg, uint64_t *__restrict__ zero_bits,
+                                                           unsigned long long *__restrict__ out) {
+  unsigned long long mx = 0, iso = 0, sq = 0;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+    int64_t v = base + threadIdx.x;
+    unsigned long long d = 0;
+    bool z = false;
+    if (v < n) {
+      d = (unsigned long long)(off[v + 1] - off[v]);
+      deg[v] = (int32_t)d;
+      z = d == 0;
+    }
+    uint64_t zm = __ballot(z);
+    if (lane_id() == 0 && v < n) zero_bits[v >> 6] = zm;
+    mx = d > mx ? d : mx;
+    iso += z;
+    sq += d * d;
   }
-  unsigned long long mx = wave_max(d);
-  unsigned long long iso = __popcll(__ballot(v < n && d == 0));
-  unsigned long long sq = wave_sum(d * d);
-  if (lane_id() == 0) {
-    atomicMax(&out[0], mx);
-    if (iso) atomicAdd(&out[1], iso);
-    atomicAdd(&out[2], sq);
+  __shared__ unsigned long long smx[4];
+  mx = wave_max(mx);
+  if (lane_id() == 0) smx[threadIdx.x / 64] = mx;
+  unsigned long long tiso = block_sum<unsigned long long, 256>(iso);
+  unsigned long long tsq = block_sum<unsigned long long, 256>(sq);
+  if (threadIdx.x == 0) {
+    unsigned long long m4 = smx[0];
+    for (int i = 1; i < 4; ++i) m4 = smx[i] > m4 ? smx[i] : m4;
+    atomicMax(&out[0], m4);
+    if (tiso) atomicAdd(&out[1], tiso);
+    atomicAdd(&out[2], tsq);
   }
 }
 
@@ -134,6 +151,7 @@ void ws_free(byo_workspace &w) {
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);
+  ms_release(w);
   w = byo_workspace();
 }
 
@@ -294,6 +312,7 @@ byo_status byo_graph_from_csr(const int64_t *off, const int32_t *nbr, int64_t n,
       if (g->nbr) (void)hipFree(g->nbr);
     }
     if (g->deg) (void)hipFree(g->deg);
+    if (g->zero_bits) (void)hipFree(g->zero_bits);
     delete g;
     return st;
   };
@@ -329,7 +348,9 @@ byo_status byo_graph_from_csr(const int64_t *off, const int32_t *nbr, int64_t n,
     if (h_tmp[3]) return done(fail(BYO_EINVAL, "CSR offsets malformed (" + std::to_string(h_tmp[3]) + " bad)"));
     if (n > 0) validate_rows_kernel<<<grid_for(n * BYO_WAVE, 256, 16384), 256, 0, s>>>(g->off, g->nbr, n, 1, d_tmp + 4);
   }
-  if (n > 0) degree_stats_kernel<<<grid_for(n, 256, 1 << 30), 256, 0, s>>>(g->off, n, g->deg, d_tmp);
+  e = hipMalloc(&g->zero_bits, sizeof(uint64_t) * (size_t)std::max<int64_t>((n + 63) / 64, 1));
+  if (e != hipSuccess) return done(hip_fail(e, "hipMalloc(zero_bits)", __FILE__, __LINE__));
+  if (n > 0) degree_stats_kernel<<<grid_for(n, 256, 2048), 256, 0, s>>>(g->off, n, g->deg, g->zero_bits, d_tmp);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(h_tmp, d_tmp, sizeof(h_tmp), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -358,6 +379,7 @@ void byo_graph_destroy(byo_graph *g) {
     if (g->nbr) (void)hipFree(g->nbr);
   }
   if (g->deg) (void)hipFree(g->deg);
+  if (g->zero_bits) (void)hipFree(g->zero_bits);
   delete g;
 }
 

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "byo.h"
+#include "byo_trace.h"
 
 // ---------------------------------------------------------------- errors
 
@@ -151,6 +152,7 @@ struct byo_workspace {
   float *chunk_sum = nullptr;
   int64_t nchunks = -1;
   int32_t pr_dpart_blocks = 0;
+  void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
 };
 
 struct byo_graph {
@@ -158,6 +160,7 @@ struct byo_graph {
   int64_t *off = nullptr;
   int32_t *nbr = nullptr;
   int32_t *deg = nullptr;
+  uint64_t *zero_bits = nullptr;   // bitmap of degree-0 vertices
   bool owns_csr = false;
   int device = 0;
   int64_t max_deg = 0, isolated = 0;
@@ -184,6 +187,7 @@ namespace byo {
 byo_status ws_ensure_traversal(byo_graph *g);
 byo_status ws_ensure_pagerank(byo_graph *g, hipStream_t s);
 void ws_free(byo_workspace &ws);
+void ms_release(byo_workspace &ws);
 
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);
@@ -231,6 +235,31 @@ byo_status cc_level(byo_graph *g, int variant, int32_t *label, const level_io &i
 // acc[v] = sum over u in N(v) of contrib[u] (pagerank.hip)
 byo_status pr_accumulate(byo_graph *g, const float *contrib, float *acc, hipStream_t s);
 byo_status cc_shortcut(byo_graph *g, int32_t *label, uint64_t *out_bits, byo_counters *ctr, hipStream_t s);
+
+// multi-source BFS state: per vertex W words of source bits
+struct ms_state {
+  int W;
+  const uint64_t *front;  // current frontier bits [n][W]
+  const uint64_t *seen;   // [n][W]
+  uint64_t *visit;        // push accumulation [n][W] (all zero between levels)
+};
+byo_status ms_push_level(byo_graph *g, int variant, const ms_state &ms, const level_io &io, const byo_opts &o,
+                         hipStream_t s, long long known_total);
+
+// tracing (trace.hip)
+bool trace_on();
+bool ktimer_on();
+hipEvent_t event_get();
+void event_put(hipEvent_t e);
+void trace_push(const byo_level_record &r);
+// HIP events around the launches made while the scope is alive (if enabled).
+struct ktimer_scope {
+  int family;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  ktimer_scope(int fam, hipStream_t st);
+  ~ktimer_scope();
+};
 
 // variant choice (selector.hip)
 struct level_features {

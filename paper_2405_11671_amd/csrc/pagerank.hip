@@ -22,6 +22,7 @@ namespace byo {
 
 constexpr int PR_BLOCK = 256;
 constexpr int64_t PR_HEAVY = 4096;   // chunk length and heavy-row threshold
+constexpr int PR_ILP = 8;
 
 static int64_t pr_blocks(int64_t words) { return std::max<int64_t>(1, (words + 3) / 4); }
 
@@ -120,7 +121,14 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__rest
     end = off[v + 1];
     d = (int32_t)(end - beg);
     if (d <= t_wave) {
-      for (int64_t e = beg; e < end; ++e) s += contrib[nbr[e]];
+      // ascending order, PR_ILP independent gathers per step
+      for (int64_t e = beg; e < end; e += PR_ILP) {
+        float c[PR_ILP];
+#pragma unroll
+        for (int j = 0; j < PR_ILP; ++j) c[j] = (e + j < end) ? contrib[nbr[e + j]] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < PR_ILP; ++j) s += c[j];
+      }
     } else if (d > PR_HEAVY) {
       int32_t c0 = row_chunk0[v];
       int32_t nc = (int32_t)((d + PR_HEAVY - 1) / PR_HEAVY);
@@ -134,7 +142,13 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__rest
     int64_t lb2 = (int64_t)read_lane_u64((uint64_t)beg, l);
     int64_t le = (int64_t)read_lane_u64((uint64_t)end, l);
     float part = 0.0f;
-    for (int64_t e = lb2 + lane_id(); e < le; e += BYO_WAVE) part += contrib[nbr[e]];
+    for (int64_t e = lb2 + lane_id(); e < le; e += 4 * BYO_WAVE) {
+      float c[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[j] = (e + j * BYO_WAVE < le) ? contrib[nbr[e + j * BYO_WAVE]] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) part += c[j];
+    }
     part = wave_sum(part);
     if (lane_id() == l) s = part;
   }
@@ -277,9 +291,13 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
   int cur = 0;
   for (int32_t t = 0; t < iters; ++t) {
     bool last = t + 1 == iters;
-    pr_chunk_kernel<<<(unsigned)std::max<int64_t>(w.nchunks, 1), PR_BLOCK, 0, s>>>(
+    {
+      ktimer_scope kc(BYO_K_PR_CHUNK, s);
+      pr_chunk_kernel<<<(unsigned)std::max<int64_t>(w.nchunks, 1), PR_BLOCK, 0, s>>>(
         g->nbr, w.contrib[cur], w.chunk_beg, w.chunk_row, w.nchunks, w.chunk_sum, w.dpart, nb, damping, n, w.base,
         1);
+    }
+    ktimer_scope kp(BYO_K_PR_PULL, s);
     pr_pull_kernel<0><<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->off, g->nbr, g->deg, n, w.words, w.contrib[cur],
                                                         w.row_chunk0, w.chunk_sum, w.base, (float)damping,
                                                         last ? nullptr : w.contrib[1 - cur], w.dpart,

@@ -46,9 +46,7 @@ int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) 
 
 // ---------------------------------------------------------------- small kernels
 
-__global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, uint64_t *visited, int64_t n, int64_t words,
-                                int32_t src, int32_t *ids, byo_counters *ctr, const int32_t *deg) {
-  // called with one block after the fills
+__global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, int32_t src, int32_t *ids, byo_counters *ctr) {
   if (threadIdx.x < BYO_COUNTER_SLOTS) {
     ctr[threadIdx.x].count = 0;
     ctr[threadIdx.x].degsum = 0;
@@ -58,14 +56,20 @@ __global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, uint64_t *visit
   if (threadIdx.x == 0) {
     parent[src] = src;
     depth[src] = 0;
-    uint64_t tail = (n & 63) ? (~0ull << (n & 63)) : 0ull;
-    if (words > 0 && (int64_t)(src >> 6) == words - 1)
-      visited[src >> 6] = tail | (1ull << (src & 63));
-    else {
-      visited[src >> 6] = 1ull << (src & 63);
-      if (words > 0) visited[words - 1] = tail;
-    }
     ids[0] = src;
+  }
+}
+
+// visited starts as {src} plus every degree-0 vertex (never reachable from
+// another vertex) plus the bits past n, so the pull direction can skip whole
+// 64-vertex words once their reachable members are visited.
+__global__ void bfs_visited_init_kernel(uint64_t *__restrict__ visited, const uint64_t *__restrict__ zero_bits,
+                                        int64_t n, int64_t words, int32_t src) {
+  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t x = zero_bits[w];
+    if (w == words - 1 && (n & 63)) x |= ~0ull << (n & 63);
+    if (w == (int64_t)(src >> 6)) x |= 1ull << (src & 63);
+    visited[w] = x;
   }
 }
 
@@ -110,6 +114,49 @@ static level_features features(const byo_graph *g, int64_t k, int64_t degsum, in
   return f;
 }
 
+// Optional per-level record (byo_trace_enable): events around one level.
+struct level_timer {
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit level_timer(hipStream_t st) : s(st) {
+    if (!trace_on()) return;
+    a = event_get();
+    b = event_get();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  void stop() {
+    if (b) (void)hipEventRecord(b, s);
+  }
+  void record(int algo, const byo_graph *g, const level_features &f, int variant, int64_t out_count,
+              int64_t out_degsum) {
+    if (!a || !b) return;
+    float ms = 0.f;
+    (void)hipEventSynchronize(b);
+    (void)hipEventElapsedTime(&ms, a, b);
+    byo_level_record r;
+    std::memset(&r, 0, sizeof(r));
+    r.algo = algo;
+    r.level = (int32_t)f.level;
+    r.variant = variant;
+    r.dense_in = f.dense_in ? 1 : 0;
+    r.n = g->n;
+    r.m = g->m;
+    r.k = f.k;
+    r.degsum = f.degsum;
+    r.unvisited = f.unvisited;
+    r.out_count = out_count;
+    r.out_degsum = out_degsum;
+    r.max_deg = g->max_deg;
+    r.cv = g->cv_deg;
+    r.ms = ms;
+    trace_push(r);
+  }
+  ~level_timer() {
+    event_put(a);
+    event_put(b);
+  }
+};
+
 // Frontier held in the workspace: ids[cur] and/or bits[cur].
 struct frontier {
   int cur = 0;
@@ -153,9 +200,9 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   int64_t n = g->n;
   BYO_TRY(fill_i32(d_parent, n, -1, s));
   BYO_TRY(fill_i32(d_depth, n, -1, s));
-  BYO_TRY(fill_u64(w.visited, w.words, 0ull, s));
-  bfs_init_kernel<<<1, 64, 0, s>>>(d_parent, d_depth, w.visited, n, w.words, (int32_t)src, w.ids[0], w.ctr,
-                                   g->deg);
+  bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
+      w.visited, g->zero_bits, n, w.words, (int32_t)src);
+  bfs_init_kernel<<<1, 64, 0, s>>>(d_parent, d_depth, (int32_t)src, w.ids[0], w.ctr);
   BYO_HIP(hipGetLastError());
   int32_t dsrc = 0;
   BYO_TRY(sync_read(s, g->deg + src, &dsrc, sizeof(dsrc)));
@@ -184,6 +231,7 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
     io.in_count = fr.k;
     io.ctr = w.ctr + (level % BYO_COUNTER_SLOTS);
     io.ctr_clear = w.ctr + ((level + 2) % BYO_COUNTER_SLOTS);
+    level_timer lt(s);
     if (is_pull(v)) {
       BYO_TRY(make_dense(g, fr, s));
       io.in_bits = w.bits[fr.cur];
@@ -195,9 +243,11 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
     }
     bs.level = level;
     BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
+    lt.stop();
     st.variant_count[v]++;
     byo_counters c;
     BYO_TRY(read_slot(g, level % BYO_COUNTER_SLOTS, s, &c));
+    lt.record(BYO_ALGO_BFS, g, f, v, (int64_t)c.count, (int64_t)c.degsum);
     ++level;
     if (c.count == 0) break;
     reached += (int64_t)c.count;
@@ -263,6 +313,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     io.ctr_clear = w.ctr + ((round + 2) % BYO_COUNTER_SLOTS);
     io.out_bits = w.bits[nxt];
     bool shortcut = o.cc_shortcut != 0;
+    level_timer lt(s);
     if (is_pull(v)) {
       BYO_TRY(make_dense(g, fr, s));
       io.in_bits = w.bits[fr.cur];
@@ -273,9 +324,11 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     }
     BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
     if (shortcut) BYO_TRY(cc_shortcut(g, d_label, w.bits[nxt], io.ctr, s));
+    lt.stop();
     st.variant_count[v]++;
     byo_counters c;
     BYO_TRY(read_slot(g, round % BYO_COUNTER_SLOTS, s, &c));
+    lt.record(BYO_ALGO_CC, g, f, v, (int64_t)c.count, (int64_t)c.degsum);
     ++round;
     if (c.count == 0) break;
     fr.cur = nxt;

@@ -104,6 +104,7 @@ byo_status bitmap_to_ids(const uint64_t *bits, int64_t words, int64_t n, int32_t
                          int64_t partial_cap, unsigned long long *d_count, hipStream_t s) {
   int64_t nb = compaction_blocks(words);
   BYO_CHECK(nb + 1 <= partial_cap, BYO_EINVAL, "compaction scratch too small");
+  ktimer_scope kt(BYO_K_COMPACT, s);
   compact_count_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(bits, words, n, partial);
   scan_partials_kernel<<<1, CB_THREADS, 0, s>>>(partial, nb, d_count);
   compact_write_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(bits, words, n, partial, ids);

@@ -1,0 +1,64 @@
+"""GPU parity of multi-source BFS (bit-parallel, up to 256 sources) vs the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11671_amd import gen
+from tests import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+byo = pytest.importorskip("paper_2405_11671_amd")
+
+_cache = {}
+
+
+def build(p):
+    if p.name not in _cache:
+        _cache[p.name] = (byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p))
+    return _cache[p.name]
+
+
+SUITE = [p for p in graphs.small_suite() if not p.name.startswith("path")]
+
+
+@pytest.mark.parametrize("k", [1, 7, 64, 65, 200, 256])
+@pytest.mark.parametrize("p", SUITE, ids=[p.name for p in SUITE])
+def test_msbfs_matches_single_source_oracle(p, k):
+    g, og = build(p)
+    rng = np.random.default_rng(k)
+    srcs = rng.integers(0, og.n, k)
+    srcs[0] = srcs[-1]          # a repeated source is allowed
+    D, st = byo.msbfs(g, srcs)
+    want = og.msbfs(srcs)
+    assert np.array_equal(D.cpu().numpy(), want), (p.name, k)
+    reached = int((want != 255).sum())
+    assert st["reached"] == reached
+
+
+@pytest.mark.parametrize("variant", [byo.V_PUSH_THREAD, byo.V_PUSH_WAVE, byo.V_PUSH_BUCKET, byo.V_PUSH_EDGE,
+                                     byo.V_PULL_WAVE])
+def test_msbfs_fixed_variants(variant):
+    p = gen.rmat_pairs(13, 16, seed=4)
+    g, og = build(p)
+    srcs = gen.pick_sources(p, 130, seed=5)
+    D, _ = byo.msbfs(g, srcs, selector=byo.SEL_FIXED, fixed_variant=variant)
+    assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs))
+
+
+def test_msbfs_depth_limit():
+    p = graphs.path(400)
+    g, og = build(p)
+    with pytest.raises(byo.ByoError) as e:
+        byo.msbfs(g, [0, 5])                 # distance 399 does not fit in uint8
+    assert e.value.status == -4
+    D, _ = byo.msbfs(g, [200, 210])      # every distance <= 210
+    assert np.array_equal(D.cpu().numpy(), og.msbfs(np.array([200, 210])))
+
+
+def test_msbfs_rejects_bad_arguments():
+    g, _ = build(SUITE[0])
+    with pytest.raises(byo.ByoError):
+        byo.msbfs(g, list(range(257)))
+    with pytest.raises(byo.ByoError):
+        byo.msbfs(g, [g.n])
