@@ -1,12 +1,16 @@
 """Benchmark: GTEPS of the edgeMap hot path on RMAT scale 22 (one MI355X).
 
-One step = BFS from 16 sources + PageRank (20 steps, FP32) + connectivity,
-all on the same resident graph. TEPS conventions:
-  BFS: undirected edges in the reached component per source (Graph500),
+One step = multi-source BFS from 256 sources (bit-parallel batch) + PageRank
+(20 steps, FP32) + connectivity, all on the same HBM-resident graph. TEPS
+conventions:
+  BFS: undirected edges in the reached component, summed over sources (Graph500),
   PageRank: iterations x m directed edges, connectivity: m/2 undirected edges.
-value = all traversed edges of the step / step time.
+value = all traversed edges of the timed steps / their wall time.
+The plain single-source heuristic BFS (16 sources) is timed separately and
+reported in "detail" for the batched-vs-plain comparison.
 
-Prints ONE JSON line (see the repository's measurement notes).
+Prints ONE JSON line. `--probe pr` instead runs a few PageRank steps and a
+plain 512 MiB device copy, for hardware-counter runs (bytes per dispatch).
 """
 from __future__ import annotations
 
@@ -22,6 +26,66 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+PR_SOURCE = os.path.join(ROOT, "paper_2405_11671_amd", "csrc", "pagerank.hip")
+
+
+def source_tag(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:12]
+
+
+def counter_traffic(kernel_tag):
+    """HBM bytes per launch of the PageRank pull kernel from the committed
+    counter summary, or None when it is missing or was taken on other source."""
+    path = os.path.join(PROFILES, "pr_pull_rmat22_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("pagerank.hip sha256[:12]") != kernel_tag:
+        return None
+    try:
+        return float(vals["scaled HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(pairs, srcs, args):
+    """The oracle (single-threaded C) on a bounded sample of the same workload."""
+    import oracle
+    og = oracle.Graph.from_pairs(pairs)
+    ks = list(srcs[: args.cpu_sample_sources])
+    t = time.perf_counter()
+    depths = [og.bfs(int(s))[0] for s in ks]
+    og.pagerank(0.85, args.cpu_sample_pr_iters)
+    og.cc()
+    el = time.perf_counter() - t
+    deg = og.degrees()
+    bfs_e = sum(int(deg[d >= 0].sum()) // 2 for d in depths)
+    edges = bfs_e + args.cpu_sample_pr_iters * og.m + og.m // 2
+    return {"value": round(edges / el / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{len(ks)} single-source BFS + {args.cpu_sample_pr_iters} PageRank steps (FP64) + CC "
+                      f"on the same rmat-{args.scale} graph; {el:.1f} s"}
+
+
+def probe_pr(g, n, iters):
+    import torch
+    import paper_2405_11671_amd as byo
+    rank = torch.empty(n, dtype=torch.float32, device="cuda")
+    byo.pagerank(g, 0.85, iters, rank=rank)
+    # calibration: an elementwise kernel that reads 512 MiB and writes 512 MiB
+    a = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "pr", "iters": iters, "copy_bytes": 512 << 20}), flush=True)
 
 
 def parse():
@@ -34,9 +98,10 @@ def parse():
     ap.add_argument("--pr-iters", type=int, default=20)
     ap.add_argument("--ms-sources", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-sources", type=int, default=2)
-    ap.add_argument("--cpu-sample-pr-iters", type=int, default=2)
+    ap.add_argument("--cpu-sample-sources", type=int, default=6)
+    ap.add_argument("--cpu-sample-pr-iters", type=int, default=6)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--probe", choices=["pr"], default=None)
     return ap.parse_args()
 
 
@@ -62,6 +127,9 @@ def main():
     torch.cuda.init()
     g = byo.Graph.from_csr(off, nbr)
     torch.cuda.synchronize()
+    if args.probe == "pr":
+        probe_pr(g, n, 3)
+        return
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     label = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -133,6 +201,14 @@ def main():
         "pr_pull_avg_ms": pr_avg_ms, "pr_pull_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
         "kernel_ms": {f: round(v[1] / args.steps, 3) for f, v in kt.items() if v[0]},
     }
+    traffic = counter_traffic(source_tag(PR_SOURCE))
+    achieved = pr_bytes / (pr_avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "pr_pull_kernel<0>", "achieved": round(achieved, 2),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / (pr_avg_ms * 1e-3) / 1e9, 2),
+                "alg_bytes_per_launch": pr_bytes, "avg_launch_ms": round(pr_avg_ms, 4),
+                "launches": pr_launches}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(pairs, srcs, args)
     out = {
         "metric": "GTEPS (batched BFS + PageRank + CC edgeMap traversals) on RMAT-22",
         "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -140,6 +216,8 @@ def main():
         "vs_baseline": None, "dtype": "int32+f32", "data": "synthetic",
         "config": {"workload": f"rmat-{args.scale} ef16 (0.57,0.19,0.19,0.05) symmetrized; "
                                f"msbfs x{len(ms_srcs)} + pagerank {args.pr_iters} it + cc", "n": n, "m": m},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
         "detail": {k: round(v, 4) if isinstance(v, float) else v for k, v in detail.items()},
     }
     print(json.dumps(out), flush=True)

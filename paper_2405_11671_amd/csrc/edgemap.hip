@@ -122,12 +122,17 @@ __device__ __forceinline__ void wave_count(bool pred, unsigned long long *count)
   if (lane_id() == __ffsll((long long)m) - 1) atomicAdd(count, (unsigned long long)__popcll(m));
 }
 
+// Emit v if pred. With a sparse output the wavefront reserves slots with one
+// atomic; otherwise the count stays in a register (`count`) and is added once
+// per workgroup in finish_level: same-address atomics from every wavefront of
+// a large grid serialise and would dominate the level.
 template <typename F>
-__device__ __forceinline__ void emit(const LevelArgs &a, bool pred, int32_t v, unsigned long long &degsum) {
+__device__ __forceinline__ void emit(const LevelArgs &a, bool pred, int32_t v, unsigned long long &degsum,
+                                     unsigned long long &count) {
   if (a.out_ids)
     wave_append(pred, v, a.out_ids, &a.ctr->count);
   else
-    wave_count(pred, &a.ctr->count);
+    count += pred ? 1ull : 0ull;
   if (pred) {
     if (!F::kDenseFromUpdate && a.out_bits)
       atomicOr((unsigned long long *)&a.out_bits[v >> 6], 1ull << (v & 63));
@@ -136,10 +141,13 @@ __device__ __forceinline__ void emit(const LevelArgs &a, bool pred, int32_t v, u
 }
 
 template <int BLOCK>
-__device__ __forceinline__ void finish_level(const LevelArgs &a, unsigned long long degsum) {
+__device__ __forceinline__ void finish_level(const LevelArgs &a, unsigned long long degsum,
+                                             unsigned long long count) {
   unsigned long long t = block_sum<unsigned long long, BLOCK>(degsum);
+  unsigned long long c = block_sum<unsigned long long, BLOCK>(count);
   if (threadIdx.x == 0) {
     if (t) atomicAdd(&a.ctr->degsum, t);
+    if (c) atomicAdd(&a.ctr->count, c);
     if (blockIdx.x == 0 && a.ctr_clear) {
       a.ctr_clear->count = 0;
       a.ctr_clear->degsum = 0;
@@ -153,7 +161,7 @@ __device__ __forceinline__ void finish_level(const LevelArgs &a, unsigned long l
 
 template <typename F>
 __global__ void __launch_bounds__(EM_BLOCK) push_thread_kernel(LevelArgs a, F f) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, count = 0;
   for (int64_t i = (int64_t)blockIdx.x * EM_BLOCK + threadIdx.x; i - threadIdx.x < a.k;
        i += (int64_t)gridDim.x * EM_BLOCK) {
     if (i < a.k) {
@@ -163,16 +171,16 @@ __global__ void __launch_bounds__(EM_BLOCK) push_thread_kernel(LevelArgs a, F f)
       for (int64_t e = a.off[u]; e < end; ++e) {
         int32_t v = a.nbr[e];
         bool ok = f.update(u, su, v, a.out_bits);
-        emit<F>(a, ok, v, degsum);
+        emit<F>(a, ok, v, degsum, count);
       }
     }
   }
-  finish_level<EM_BLOCK>(a, degsum);
+  finish_level<EM_BLOCK>(a, degsum, count);
 }
 
 template <typename F>
 __global__ void __launch_bounds__(EM_BLOCK) push_wave_kernel(LevelArgs a, F f) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, count = 0;
   int64_t wave = ((int64_t)blockIdx.x * EM_BLOCK + threadIdx.x) / BYO_WAVE;
   int64_t nwaves = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   for (int64_t i = wave; i < a.k; i += nwaves) {
@@ -186,10 +194,10 @@ __global__ void __launch_bounds__(EM_BLOCK) push_wave_kernel(LevelArgs a, F f) {
         v = a.nbr[e];
         ok = f.update(u, su, v, a.out_bits);
       }
-      emit<F>(a, ok, v, degsum);
+      emit<F>(a, ok, v, degsum, count);
     }
   }
-  finish_level<EM_BLOCK>(a, degsum);
+  finish_level<EM_BLOCK>(a, degsum, count);
 }
 
 // Degree-bucketed push: in each chunk of EM_BLOCK frontier vertices, those
@@ -200,7 +208,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
   __shared__ int32_t s_u[EM_BLOCK];
   __shared__ int32_t s_su[EM_BLOCK];
   __shared__ int s_nbig;
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, count = 0;
   for (int64_t c0 = (int64_t)blockIdx.x * EM_BLOCK; c0 < a.k; c0 += (int64_t)gridDim.x * EM_BLOCK) {
     int64_t i = c0 + threadIdx.x;
     int32_t u = -1, su = 0, d = 0;
@@ -228,7 +236,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
           v = a.nbr[e];
           ok = f.update(bu, bsu, v, a.out_bits);
         }
-        emit<F>(a, ok, v, degsum);
+        emit<F>(a, ok, v, degsum, count);
       }
     }
     uint64_t wm = __ballot(d >= a.t_wave && d < a.t_block);
@@ -244,7 +252,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
           v = a.nbr[e];
           ok = f.update(wu, wsu, v, a.out_bits);
         }
-        emit<F>(a, ok, v, degsum);
+        emit<F>(a, ok, v, degsum, count);
       }
     }
     if (u >= 0 && d < a.t_wave) {
@@ -252,12 +260,12 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
       for (int64_t e = beg; e < end; ++e) {
         int32_t v = a.nbr[e];
         bool ok = f.update(u, su, v, a.out_bits);
-        emit<F>(a, ok, v, degsum);
+        emit<F>(a, ok, v, degsum, count);
       }
     }
     __syncthreads();
   }
-  finish_level<EM_BLOCK>(a, degsum);
+  finish_level<EM_BLOCK>(a, degsum, count);
 }
 
 // Edge-balanced push: workgroup b owns edges [b*TILE, (b+1)*TILE) of the
@@ -276,65 +284,92 @@ __device__ __forceinline__ int64_t last_le(const long long *scan, int64_t lo, in
   return lo;
 }
 
+constexpr int PE_STAGE = 3072;   // LDS staging for emitted vertices (flushed with one atomic)
+
 template <typename F>
 __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
   __shared__ long long s_scan[PE_SEG];
   __shared__ long long s_base[PE_SEG];
   __shared__ int32_t s_u[PE_SEG];
   __shared__ int32_t s_su[PE_SEG];
+  __shared__ int32_t s_out[PE_STAGE];
   __shared__ int64_t s_lo, s_hi;
-  unsigned long long degsum = 0;
-  long long t0 = (long long)blockIdx.x * PE_TILE;
-  long long total = a.scan[a.k] < a.total ? a.scan[a.k] : a.total;  // never past the real edge count
-  long long t1 = t0 + PE_TILE < total ? t0 + PE_TILE : total;
-  if (t0 >= t1) {
-    finish_level<EM_BLOCK>(a, 0ull);
-    return;
-  }
-  if (threadIdx.x == 0) {
-    s_lo = last_le(a.scan, 0, a.k - 1, t0);
-    s_hi = last_le(a.scan, s_lo, a.k - 1, t1 - 1);
-  }
-  __syncthreads();
-  int64_t lo = s_lo, hi = s_hi;
-  int64_t seg = hi - lo + 1;
-  bool in_lds = seg <= PE_SEG;
-  if (in_lds) {
-    for (int64_t j = threadIdx.x; j < seg; j += EM_BLOCK) {
-      int32_t u = a.in_ids[lo + j];
-      long long sc = a.scan[lo + j];
-      s_scan[j] = sc;
-      s_base[j] = a.off[u] - sc;
-      s_u[j] = u;
-      s_su[j] = f.src_value(u);
+  __shared__ unsigned s_cnt;
+  __shared__ unsigned long long s_dst;
+  unsigned long long degsum = 0, count = 0;
+  const long long total = a.scan[a.k] < a.total ? a.scan[a.k] : a.total;  // never past the real edge count
+  const long long ntiles = (total + PE_TILE - 1) / PE_TILE;
+  if (threadIdx.x == 0) s_cnt = 0;
+  auto flush = [&]() {
+    __syncthreads();
+    if (threadIdx.x == 0) s_dst = s_cnt ? atomicAdd(&a.ctr->count, (unsigned long long)s_cnt) : 0ull;
+    __syncthreads();
+    unsigned c = s_cnt;
+    for (unsigned i = threadIdx.x; i < c; i += EM_BLOCK) a.out_ids[s_dst + i] = s_out[i];
+    __syncthreads();
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+  };
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    long long t0 = tile * PE_TILE;
+    long long t1 = t0 + PE_TILE < total ? t0 + PE_TILE : total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_lo = last_le(a.scan, 0, a.k - 1, t0);
+      s_hi = last_le(a.scan, s_lo, a.k - 1, t1 - 1);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int it = 0; it < PE_ITEMS; ++it) {
-    long long e = t0 + it * EM_BLOCK + threadIdx.x;
-    bool ok = false;
-    int32_t v = 0;
-    if (e < t1) {
-      int32_t u, su;
-      long long pos;
-      if (in_lds) {
-        int64_t j = last_le(s_scan, 0, seg - 1, e);
-        u = s_u[j];
-        su = s_su[j];
-        pos = s_base[j] + e;
-      } else {
-        int64_t i = last_le(a.scan, lo, hi, e);
-        u = a.in_ids[i];
-        su = f.src_value(u);
-        pos = a.off[u] + (e - a.scan[i]);
+    __syncthreads();
+    int64_t lo = s_lo, hi = s_hi;
+    int64_t seg = hi - lo + 1;
+    bool in_lds = seg <= PE_SEG;
+    if (in_lds) {
+      for (int64_t j = threadIdx.x; j < seg; j += EM_BLOCK) {
+        int32_t u = a.in_ids[lo + j];
+        long long sc = a.scan[lo + j];
+        s_scan[j] = sc;
+        s_base[j] = a.off[u] - sc;
+        s_u[j] = u;
+        s_su[j] = f.src_value(u);
       }
-      v = a.nbr[pos];
-      ok = f.update(u, su, v, a.out_bits);
     }
-    emit<F>(a, ok, v, degsum);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PE_ITEMS; ++it) {
+      long long e = t0 + it * EM_BLOCK + threadIdx.x;
+      bool ok = false;
+      int32_t v = 0;
+      if (e < t1) {
+        int32_t u, su;
+        long long pos;
+        if (in_lds) {
+          int64_t j = last_le(s_scan, 0, seg - 1, e);
+          u = s_u[j];
+          su = s_su[j];
+          pos = s_base[j] + e;
+        } else {
+          int64_t i = last_le(a.scan, lo, hi, e);
+          u = a.in_ids[i];
+          su = f.src_value(u);
+          pos = a.off[u] + (e - a.scan[i]);
+        }
+        v = a.nbr[pos];
+        ok = f.update(u, su, v, a.out_bits);
+      }
+      if (ok) {
+        if (a.out_ids) s_out[atomicAdd(&s_cnt, 1u)] = v;
+        else ++count;
+        if (!F::kDenseFromUpdate && a.out_bits)
+          atomicOr((unsigned long long *)&a.out_bits[v >> 6], 1ull << (v & 63));
+        degsum += (unsigned long long)a.deg[v];
+      }
+    }
+    if (a.out_ids) {
+      __syncthreads();
+      if (s_cnt > PE_STAGE - PE_TILE) flush();
+    }
   }
-  finish_level<EM_BLOCK>(a, degsum);
+  if (a.out_ids) flush();
+  finish_level<EM_BLOCK>(a, degsum, count);
 }
 
 // ---------------------------------------------------------------- pull kernels (BFS)
@@ -344,7 +379,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
 // wavefront owns its word of `visited` and the output bitmap, so no atomics.
 template <bool WAVE_ASSIST>
 __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, count = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < a.words; w += nwaves_total) {
@@ -411,7 +446,7 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
       a.out_bits[w] = m;
       if (m) {
         f.visited[w] = vis | m;
-        atomicAdd(&a.ctr->count, (unsigned long long)__popcll(m));
+        count += (unsigned long long)__popcll(m);
       }
     }
     if (a.out_ids) {
@@ -424,7 +459,7 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
       }
     }
   }
-  finish_level<EM_BLOCK>(a, degsum);
+  finish_level<EM_BLOCK>(a, degsum, count);
 }
 
 // ---------------------------------------------------------------- pull kernel (min-label)
@@ -434,7 +469,7 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
 // wavefront when WAVE_ASSIST.
 template <bool WAVE_ASSIST>
 __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, count = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < a.words; w += nwaves_total) {
@@ -481,10 +516,10 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
     uint64_t m = __ballot(changed);
     if (lane_id() == 0) {
       a.out_bits[w] = m;
-      if (m) atomicAdd(&a.ctr->count, (unsigned long long)__popcll(m));
+      count += (unsigned long long)__popcll(m);
     }
   }
-  finish_level<EM_BLOCK>(a, degsum);
+  finish_level<EM_BLOCK>(a, degsum, count);
 }
 
 // Pointer jumping: label[v] <- label[label[v]] until it stops decreasing.
@@ -493,7 +528,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
 __global__ void __launch_bounds__(EM_BLOCK) cc_shortcut_kernel(int32_t *label, const int32_t *__restrict__ deg,
                                                                int64_t n, int64_t words, uint64_t *out_bits,
                                                                byo_counters *ctr) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, count = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < words; w += nwaves_total) {
@@ -519,12 +554,16 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_shortcut_kernel(int32_t *label, c
       if (changed && ((fresh >> lane_id()) & 1ull)) degsum += (unsigned long long)deg[v64];
       if (lane_id() == 0) {
         out_bits[w] = old | m;
-        if (fresh) atomicAdd(&ctr->count, (unsigned long long)__popcll(fresh));
+        count += (unsigned long long)__popcll(fresh);
       }
     }
   }
   unsigned long long t = block_sum<unsigned long long, EM_BLOCK>(degsum);
-  if (threadIdx.x == 0 && t) atomicAdd(&ctr->degsum, t);
+  unsigned long long c = block_sum<unsigned long long, EM_BLOCK>(count);
+  if (threadIdx.x == 0) {
+    if (t) atomicAdd(&ctr->degsum, t);
+    if (c) atomicAdd(&ctr->count, c);
+  }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -555,7 +594,7 @@ static byo_status launch_push(int variant, const LevelArgs &a, const F &f, hipSt
       break;
     case BYO_V_PUSH_EDGE: {
       int64_t tiles = (a.total + PE_TILE - 1) / PE_TILE;
-      push_edge_kernel<F><<<capped(tiles, 1ll << 31), EM_BLOCK, 0, s>>>(a, f);
+      push_edge_kernel<F><<<capped(tiles, 2048), EM_BLOCK, 0, s>>>(a, f);
       break;
     }
     default:
@@ -587,7 +626,8 @@ static LevelArgs make_args(const byo_graph *g, const level_io &io, const byo_opt
   return a;
 }
 
-static unsigned pull_grid(int64_t words) { return capped((words + 3) / 4, 1ll << 20); }
+// dense kernels loop over words with a grid of at most 16 workgroups per CU
+static unsigned pull_grid(int64_t words) { return capped((words + 3) / 4, 4096); }
 
 // Read back scan[k] (sum of frontier degrees) for the edge-balanced variant.
 static byo_status edge_total(byo_graph *g, const level_io &io, hipStream_t s, long long *total) {

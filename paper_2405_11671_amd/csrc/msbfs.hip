@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_pull_kernel(const int64_t *__rest
                                                            const int32_t *__restrict__ deg, int64_t n,
                                                            const uint64_t *__restrict__ front, uint64_t *__restrict__ seen,
                                                            uint64_t *__restrict__ next, uint8_t *__restrict__ depth,
-                                                           int32_t k, uint8_t newdepth, int32_t *__restrict__ active,
+                                                           int32_t k, uint8_t newdepth, uint64_t *__restrict__ active_bits,
                                                            byo_counters *__restrict__ ctr, int32_t t_wave) {
   uint64_t full[W];
 #pragma unroll
@@ -49,92 +49,114 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_pull_kernel(const int64_t *__rest
     int bits = k - 64 * w;
     full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
   }
-  unsigned long long degsum = 0;
-  int64_t lb = xcd_block(blockIdx.x, gridDim.x);
-  int64_t v = lb * MS_BLOCK + threadIdx.x;
-  bool valid = v < n;
-  uint64_t sv[W], acc[W];
-  bool need = false;
-  int64_t beg = 0, end = 0;
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    sv[w] = valid ? seen[v * W + w] : full[w];
-    acc[w] = 0;
-    need |= sv[w] != full[w];
-  }
-  if (need) {
-    beg = off[v];
-    end = off[v + 1];
-    int64_t lim = end - beg > t_wave ? beg + t_wave : end;
-    for (int64_t e = beg; e < lim; e += MS_ILP) {
-      int32_t u[MS_ILP];
-#pragma unroll
-      for (int j = 0; j < MS_ILP; ++j) u[j] = (e + j < lim) ? nbr[e + j] : -1;
-#pragma unroll
-      for (int j = 0; j < MS_ILP; ++j)
-#pragma unroll
-        for (int w = 0; w < W; ++w) acc[w] |= u[j] >= 0 ? front[(int64_t)u[j] * W + w] : 0ull;
-      bool done = true;
-#pragma unroll
-      for (int w = 0; w < W; ++w) done &= (acc[w] | sv[w]) == full[w];
-      if (done) {
-        end = lim;  // no wavefront pass needed
-        break;
-      }
-    }
-  }
-  // wavefront pass over the rest of long lists
-  uint64_t pm = __ballot(need && end - beg > t_wave);
-  while (pm) {
-    int l = __ffsll((long long)pm) - 1;
-    pm &= pm - 1;
-    int64_t lo = (int64_t)read_lane_u64((uint64_t)(beg + t_wave), l);
-    int64_t hi = (int64_t)read_lane_u64((uint64_t)end, l);
-    uint64_t have[W], got[W];
+  unsigned long long degsum = 0, count = 0;
+  const int64_t stride = (int64_t)gridDim.x * MS_BLOCK;
+  for (int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * MS_BLOCK; base < n; base += stride) {
+    int64_t v = base + threadIdx.x;
+    bool valid = v < n;
+    uint64_t sv[W], acc[W];
+    bool need = false;
+    int64_t beg = 0, end = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      have[w] = read_lane_u64(sv[w] | acc[w], l);
-      got[w] = 0;
+      sv[w] = valid ? seen[v * W + w] : full[w];
+      acc[w] = 0;
+      need |= sv[w] != full[w];
     }
-    for (int64_t base = lo; base < hi; base += BYO_WAVE) {
-      int64_t e = base + lane_id();
-      int32_t u = e < hi ? nbr[e] : -1;
+    if (need) {
+      beg = off[v];
+      end = off[v + 1];
+      int64_t lim = end - beg > t_wave ? beg + t_wave : end;
+      for (int64_t e = beg; e < lim; e += MS_ILP) {
+        int32_t u[MS_ILP];
+#pragma unroll
+        for (int j = 0; j < MS_ILP; ++j) u[j] = (e + j < lim) ? nbr[e + j] : -1;
+#pragma unroll
+        for (int j = 0; j < MS_ILP; ++j)
+#pragma unroll
+          for (int w = 0; w < W; ++w) acc[w] |= u[j] >= 0 ? front[(int64_t)u[j] * W + w] : 0ull;
+        bool done = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) done &= (acc[w] | sv[w]) == full[w];
+        if (done) {
+          end = lim;  // no wavefront pass needed
+          break;
+        }
+      }
+    }
+    // wavefront pass over the rest of long lists
+    uint64_t pm = __ballot(need && end - beg > t_wave);
+    while (pm) {
+      int l = __ffsll((long long)pm) - 1;
+      pm &= pm - 1;
+      int64_t lo = (int64_t)read_lane_u64((uint64_t)(beg + t_wave), l);
+      int64_t hi = (int64_t)read_lane_u64((uint64_t)end, l);
+      uint64_t have[W], got[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        uint64_t x = u >= 0 ? front[(int64_t)u * W + w] : 0ull;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
-        got[w] |= x;
+        have[w] = read_lane_u64(sv[w] | acc[w], l);
+        got[w] = 0;
       }
-      bool done = true;
+      for (int64_t b2 = lo; b2 < hi; b2 += BYO_WAVE) {
+        int64_t e = b2 + lane_id();
+        int32_t u = e < hi ? nbr[e] : -1;
 #pragma unroll
-      for (int w = 0; w < W; ++w) done &= (got[w] | have[w]) == full[w];
-      if (done) break;
+        for (int w = 0; w < W; ++w) {
+          uint64_t x = u >= 0 ? front[(int64_t)u * W + w] : 0ull;
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) x |= __shfl_xor(x, o);
+          got[w] |= x;
+        }
+        bool done = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) done &= (got[w] | have[w]) == full[w];
+        if (done) break;
+      }
+      if (lane_id() == l) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) acc[w] |= got[w];
+      }
     }
-    if (lane_id() == l) {
-#pragma unroll
-      for (int w = 0; w < W; ++w) acc[w] |= got[w];
-    }
-  }
-  bool any = false;
-  uint64_t nb[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    nb[w] = acc[w] & ~sv[w];
-    any |= nb[w] != 0;
-  }
-  if (any) {
+    bool any = false;
+    uint64_t nb[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      next[v * W + w] = nb[w];
-      seen[v * W + w] = sv[w] | nb[w];
+      nb[w] = acc[w] & ~sv[w];
+      any |= nb[w] != 0;
     }
-    write_depths<W>(depth, v, k, nb, newdepth);
-    degsum += (unsigned long long)deg[v];
+    if (any) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        next[v * W + w] = nb[w];
+        seen[v * W + w] = sv[w] | nb[w];
+      }
+      write_depths<W>(depth, v, k, nb, newdepth);
+      degsum += (unsigned long long)deg[v];
+    }
+    // 64 consecutive vertices per wavefront: one bitmap word, no atomics
+    uint64_t am = __ballot(any);
+    if (lane_id() == 0 && v < n) {
+      active_bits[v >> 6] = am;
+      count += (unsigned long long)__popcll(am);
+    }
   }
-  wave_append(any, (int32_t)v, active, &ctr->count);
   unsigned long long t = block_sum<unsigned long long, MS_BLOCK>(degsum);
-  if (threadIdx.x == 0 && t) atomicAdd(&ctr->degsum, t);
+  unsigned long long c = block_sum<unsigned long long, MS_BLOCK>(count);
+  if (threadIdx.x == 0) {
+    if (t) atomicAdd(&ctr->degsum, t);
+    if (c) atomicAdd(&ctr->count, c);
+  }
+}
+
+// Zero the frontier words of the vertices whose bit is set in `bits`.
+template <int W>
+__global__ void ms_clear_bits_kernel(const uint64_t *__restrict__ bits, int64_t n, uint64_t *__restrict__ front) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    if ((bits[v >> 6] >> (v & 63)) & 1ull) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) front[v * W + w] = 0ull;
+    }
+  }
 }
 
 // After a push level: fold visit[v] into seen/next for every touched v.
@@ -238,10 +260,16 @@ __global__ void u8_fill_kernel(uint8_t *p, int64_t count, uint8_t value) {
 
 template <int W>
 static void launch_pull(const byo_graph *g, const uint64_t *front, uint64_t *seen, uint64_t *next, uint8_t *depth,
-                        int32_t k, uint8_t nd, int32_t *active, byo_counters *ctr, int32_t tw, hipStream_t s) {
-  unsigned nb = (unsigned)std::max<int64_t>(1, (g->n + MS_BLOCK - 1) / MS_BLOCK);
-  ms_pull_kernel<W><<<nb, MS_BLOCK, 0, s>>>(g->off, g->nbr, g->deg, g->n, front, seen, next, depth, k, nd, active,
+                        int32_t k, uint8_t nd, uint64_t *abits, byo_counters *ctr, int32_t tw, hipStream_t s) {
+  unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (g->n + MS_BLOCK - 1) / MS_BLOCK), 4096);
+  ms_pull_kernel<W><<<nb, MS_BLOCK, 0, s>>>(g->off, g->nbr, g->deg, g->n, front, seen, next, depth, k, nd, abits,
                                             ctr, tw);
+}
+
+template <int W>
+static void launch_clear_bits(const uint64_t *bits, int64_t n, uint64_t *front, hipStream_t s) {
+  unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096);
+  ms_clear_bits_kernel<W><<<nb, 256, 0, s>>>(bits, n, front);
 }
 
 template <int W>
@@ -263,6 +291,7 @@ struct ms_ws {
   int64_t n = -1;
   int W = 0;
   uint64_t *seen = nullptr, *front[2] = {nullptr, nullptr}, *visit = nullptr, *tbits = nullptr;
+  uint64_t *abits[2] = {nullptr, nullptr};
   int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr;
   byo_counters *ctr = nullptr;
   unsigned long long *tally = nullptr;
@@ -270,7 +299,7 @@ struct ms_ws {
 
 static void ms_free(ms_ws &m) {
   void *p[] = {m.seen, m.front[0], m.front[1], m.visit, m.tbits, m.touched, m.active[0], m.active[1], m.srcs,
-               m.ctr, m.tally};
+               m.ctr, m.tally, m.abits[0], m.abits[1]};
   for (void *x : p)
     if (x) (void)hipFree(x);
   m = ms_ws();
@@ -313,6 +342,8 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     BYO_HIP(hipMalloc(&mw.front[1], vb));
     BYO_HIP(hipMalloc(&mw.visit, vb));
     BYO_HIP(hipMalloc(&mw.tbits, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
+    BYO_HIP(hipMalloc(&mw.abits[0], sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
+    BYO_HIP(hipMalloc(&mw.abits[1], sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
     BYO_HIP(hipMalloc(&mw.touched, sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.active[0], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.active[1], sizeof(int32_t) * (size_t)n));
@@ -354,6 +385,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   std::memset(&st, 0, sizeof(st));
   int cur = 0;
   int level = 0;
+  bool as_list = true;  // is the current active set held as a list (else as a bitmap)?
   int32_t tw = o.t_wave > 0 ? o.t_wave : 32;
   int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
   while (acount > 0) {
@@ -369,16 +401,22 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     else
       variant = (acount + adeg > g->m / div) ? BYO_V_PULL_WAVE : BYO_V_PUSH_EDGE;
     bool pull = variant == BYO_V_PULL_THREAD || variant == BYO_V_PULL_WAVE;
+    int nx = 1 - cur;
     if (pull) {
       ktimer_scope kt(BYO_K_MSBFS_PULL, s);
       switch (W) {
-        case 1: launch_pull<1>(g, mw.front[cur], mw.seen, mw.front[1 - cur], d_depth, k, nd, mw.active[1 - cur], actr, tw, s); break;
-        case 2: launch_pull<2>(g, mw.front[cur], mw.seen, mw.front[1 - cur], d_depth, k, nd, mw.active[1 - cur], actr, tw, s); break;
-        case 3: launch_pull<3>(g, mw.front[cur], mw.seen, mw.front[1 - cur], d_depth, k, nd, mw.active[1 - cur], actr, tw, s); break;
-        default: launch_pull<4>(g, mw.front[cur], mw.seen, mw.front[1 - cur], d_depth, k, nd, mw.active[1 - cur], actr, tw, s); break;
+        case 1: launch_pull<1>(g, mw.front[cur], mw.seen, mw.front[nx], d_depth, k, nd, mw.abits[nx], actr, tw, s); break;
+        case 2: launch_pull<2>(g, mw.front[cur], mw.seen, mw.front[nx], d_depth, k, nd, mw.abits[nx], actr, tw, s); break;
+        case 3: launch_pull<3>(g, mw.front[cur], mw.seen, mw.front[nx], d_depth, k, nd, mw.abits[nx], actr, tw, s); break;
+        default: launch_pull<4>(g, mw.front[cur], mw.seen, mw.front[nx], d_depth, k, nd, mw.abits[nx], actr, tw, s); break;
       }
       BYO_HIP(hipGetLastError());
     } else {
+      if (!as_list) {
+        BYO_TRY(bitmap_to_ids(mw.abits[cur], words, n, mw.active[cur], g->ws.partial, g->ws.partial_cap,
+                              (unsigned long long *)g->ws.misc, s));
+        as_list = true;
+      }
       level_io io;
       std::memset(&io, 0, sizeof(io));
       io.in_ids = mw.active[cur];
@@ -391,19 +429,28 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
       BYO_TRY(ms_push_level(g, variant, ms, io, o, s, adeg));
       ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
       switch (W) {
-        case 1: launch_finish<1>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[1 - cur], mw.tbits, d_depth, k, nd, mw.active[1 - cur], actr, adeg, s); break;
-        case 2: launch_finish<2>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[1 - cur], mw.tbits, d_depth, k, nd, mw.active[1 - cur], actr, adeg, s); break;
-        case 3: launch_finish<3>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[1 - cur], mw.tbits, d_depth, k, nd, mw.active[1 - cur], actr, adeg, s); break;
-        default: launch_finish<4>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[1 - cur], mw.tbits, d_depth, k, nd, mw.active[1 - cur], actr, adeg, s); break;
+        case 1: launch_finish<1>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[nx], mw.tbits, d_depth, k, nd, mw.active[nx], actr, adeg, s); break;
+        case 2: launch_finish<2>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[nx], mw.tbits, d_depth, k, nd, mw.active[nx], actr, adeg, s); break;
+        case 3: launch_finish<3>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[nx], mw.tbits, d_depth, k, nd, mw.active[nx], actr, adeg, s); break;
+        default: launch_finish<4>(g, mw.touched, tctr, mw.visit, mw.seen, mw.front[nx], mw.tbits, d_depth, k, nd, mw.active[nx], actr, adeg, s); break;
       }
       BYO_HIP(hipGetLastError());
     }
-    // the spare frontier buffer must be all-zero for the next level
-    switch (W) {
-      case 1: launch_clear<1>(mw.active[cur], acount, mw.front[cur], s); break;
-      case 2: launch_clear<2>(mw.active[cur], acount, mw.front[cur], s); break;
-      case 3: launch_clear<3>(mw.active[cur], acount, mw.front[cur], s); break;
-      default: launch_clear<4>(mw.active[cur], acount, mw.front[cur], s); break;
+    // the consumed frontier buffer must be all-zero before it is reused as output
+    if (as_list) {
+      switch (W) {
+        case 1: launch_clear<1>(mw.active[cur], acount, mw.front[cur], s); break;
+        case 2: launch_clear<2>(mw.active[cur], acount, mw.front[cur], s); break;
+        case 3: launch_clear<3>(mw.active[cur], acount, mw.front[cur], s); break;
+        default: launch_clear<4>(mw.active[cur], acount, mw.front[cur], s); break;
+      }
+    } else {
+      switch (W) {
+        case 1: launch_clear_bits<1>(mw.abits[cur], n, mw.front[cur], s); break;
+        case 2: launch_clear_bits<2>(mw.abits[cur], n, mw.front[cur], s); break;
+        case 3: launch_clear_bits<3>(mw.abits[cur], n, mw.front[cur], s); break;
+        default: launch_clear_bits<4>(mw.abits[cur], n, mw.front[cur], s); break;
+      }
     }
     BYO_HIP(hipGetLastError());
     byo_counters c;
@@ -412,7 +459,8 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     ++level;
     acount = (int64_t)c.count;
     adeg = (long long)c.degsum;
-    cur = 1 - cur;
+    as_list = !pull;
+    cur = nx;
   }
   ms_tally_kernel<<<(unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096), MS_BLOCK, 0, s>>>(
       mw.seen, W, g->deg, n, mw.tally);
