@@ -290,3 +290,63 @@ def ktimer_read(family):
     n, ms = ctypes.c_int64(), ctypes.c_double()
     _lib.check(_lib.load().byo_ktimer_read(fid, ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+class Batch:
+    """Many graphs traversed together (laid out as one disjoint-union CSR on the device)."""
+
+    def __init__(self, csrs):
+        """csrs: list of (off int64[n+1], nbr int32[m]) host arrays."""
+        lib = _lib.load()
+        self._keep = [(np.ascontiguousarray(o, np.int64), np.ascontiguousarray(nb, np.int32)) for o, nb in csrs]
+        cnt = len(self._keep)
+        offs = (ctypes.c_void_p * cnt)(*[o.ctypes.data for o, _ in self._keep])
+        nbrs = (ctypes.c_void_p * cnt)(*[nb.ctypes.data if nb.size else None for _, nb in self._keep])
+        ns = np.array([o.shape[0] - 1 for o, _ in self._keep], np.int64)
+        h = ctypes.c_void_p()
+        _lib.check(lib.byo_batch_create(cnt, offs, nbrs, ns.ctypes.data, _stream(), ctypes.byref(h)))
+        self._h = h
+        self.count = cnt
+        tn, tm = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(lib.byo_batch_info(h, ctypes.byref(tn), ctypes.byref(tm)))
+        self.n, self.m = tn.value, tm.value
+        self.voff = []
+        for i in range(cnt + 1):
+            x = ctypes.c_int64()
+            _lib.check(lib.byo_batch_vertex_offset(h, i, ctypes.byref(x)))
+            self.voff.append(x.value)
+
+    @classmethod
+    def from_pairs(cls, pairs_list):
+        return cls([csr_from_pairs(p.n, p.src, p.dst) for p in pairs_list])
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                _lib.load().byo_batch_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def bfs(self, srcs, opts=None, depth=None, parent=None, **kw):
+        torch = _torch()
+        o = _opts(opts, kw)
+        srcs = np.ascontiguousarray(np.asarray(srcs, np.int64))
+        depth = torch.empty(self.n, dtype=torch.int32, device="cuda") if depth is None else depth
+        parent = torch.empty(self.n, dtype=torch.int32, device="cuda") if parent is None else parent
+        stt = _lib.RunStats()
+        _lib.check(_lib.load().byo_batch_bfs(self._h, srcs.ctypes.data, _ptr(depth), _ptr(parent), ctypes.byref(o),
+                                             _stream(), ctypes.byref(stt)))
+        return depth, parent, stt.as_dict()
+
+    def cc(self, opts=None, label=None, **kw):
+        torch = _torch()
+        o = _opts(opts, kw)
+        label = torch.empty(self.n, dtype=torch.int32, device="cuda") if label is None else label
+        stt = _lib.RunStats()
+        _lib.check(_lib.load().byo_batch_cc(self._h, _ptr(label), ctypes.byref(o), _stream(), ctypes.byref(stt)))
+        return label, stt.as_dict()
+
+    def split(self, t):
+        """Per-graph views of a concatenated result."""
+        return [t[self.voff[i]:self.voff[i + 1]] for i in range(self.count)]

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "byo.h"
 #include "byo_trace.h"
@@ -268,6 +269,10 @@ struct level_features {
   bool dense_in;
 };
 int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull);
+
+// BFS from distinct sources (traverse.hip)
+byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
+                   const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 
 }  // namespace byo

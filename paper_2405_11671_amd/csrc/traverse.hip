@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "internal.h"
 
@@ -46,18 +47,26 @@ int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) 
 
 // ---------------------------------------------------------------- small kernels
 
-__global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, int32_t src, int32_t *ids, byo_counters *ctr) {
-  if (threadIdx.x < BYO_COUNTER_SLOTS) {
+__global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, const int32_t *srcs, int64_t nsrc, int32_t *ids,
+                                byo_counters *ctr) {
+  if (blockIdx.x == 0 && threadIdx.x < BYO_COUNTER_SLOTS) {
     ctr[threadIdx.x].count = 0;
     ctr[threadIdx.x].degsum = 0;
     ctr[threadIdx.x].aux0 = 0;
     ctr[threadIdx.x].aux1 = 0;
   }
-  if (threadIdx.x == 0) {
-    parent[src] = src;
-    depth[src] = 0;
-    ids[0] = src;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsrc) {
+    int32_t s = srcs[i];
+    parent[s] = s;
+    depth[s] = 0;
+    ids[i] = s;
   }
+}
+
+__global__ void bfs_visited_sources_kernel(uint64_t *visited, const int32_t *srcs, int64_t nsrc) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsrc) atomicOr((unsigned long long *)&visited[srcs[i] >> 6], 1ull << (srcs[i] & 63));
 }
 
 // visited starts as {src} plus every degree-0 vertex (never reachable from
@@ -187,34 +196,40 @@ using namespace byo;
 
 extern "C" {
 
-byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
-                   void *stream, byo_run_stats *stats) {
-  BYO_CHECK(g && d_depth && d_parent, BYO_EINVAL, "null argument");
-  BYO_CHECK(src >= 0 && src < g->n, BYO_EINVAL, "source out of range");
-  byo_opts o;
-  byo_opts_default(&o);
-  if (opts) o = *opts;
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace byo {
+
+// BFS from a set of distinct sources (a single source, or one per graph of a
+// batch laid out as a disjoint union).
+byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
+                   const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(ws_ensure_traversal(g));
   byo_workspace &w = g->ws;
   int64_t n = g->n;
+  int64_t ns = (int64_t)srcs.size();
+  BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
   BYO_TRY(fill_i32(d_parent, n, -1, s));
   BYO_TRY(fill_i32(d_depth, n, -1, s));
+  // sources staged through the spare frontier list
+  BYO_HIP(hipMemcpyAsync(w.ids[1], srcs.data(), sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
   bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
-      w.visited, g->zero_bits, n, w.words, (int32_t)src);
-  bfs_init_kernel<<<1, 64, 0, s>>>(d_parent, d_depth, (int32_t)src, w.ids[0], w.ctr);
+      w.visited, g->zero_bits, n, w.words, srcs[0]);
+  bfs_visited_sources_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(w.visited, w.ids[1], ns);
+  bfs_init_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(d_parent, d_depth, w.ids[1], ns, w.ids[0], w.ctr);
   BYO_HIP(hipGetLastError());
-  int32_t dsrc = 0;
-  BYO_TRY(sync_read(s, g->deg + src, &dsrc, sizeof(dsrc)));
+  long long dsum = 0;
+  BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
+  BYO_TRY(sync_read(s, w.scan + ns, &dsum, sizeof(dsum)));
 
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
   frontier fr;
   fr.cur = 0;
   fr.sparse = true;
-  fr.k = 1;
-  fr.degsum = dsrc;
-  int64_t reached = 1, edges = dsrc;
+  fr.k = ns;
+  fr.degsum = dsum;
+  int64_t reached = ns, edges = dsum;
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   bfs_state bs{d_parent, d_depth, w.visited, 0};
   int32_t level = 0;
@@ -263,6 +278,21 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   st.edges = edges;
   if (stats) *stats = st;
   return BYO_OK;
+}
+
+}  // namespace byo
+
+extern "C" {
+
+byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
+                   void *stream, byo_run_stats *stats) {
+  BYO_CHECK(g && d_depth && d_parent, BYO_EINVAL, "null argument");
+  BYO_CHECK(src >= 0 && src < g->n, BYO_EINVAL, "source out of range");
+  byo_opts o;
+  byo_opts_default(&o);
+  if (opts) o = *opts;
+  std::vector<int32_t> srcs(1, (int32_t)src);
+  return bfs_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
 }
 
 byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *stream, byo_run_stats *stats) {

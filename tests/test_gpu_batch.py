@@ -1,0 +1,61 @@
+"""GPU parity of batched execution: each graph of a batch equals its own oracle run."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11671_amd import gen
+from tests import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+byo = pytest.importorskip("paper_2405_11671_amd")
+
+
+def first_non_isolated(og):
+    deg = og.degrees()
+    nz = np.flatnonzero(deg)
+    return int(nz[0]) if nz.size else 0
+
+
+def check_batch(plist, **kw):
+    B = byo.Batch.from_pairs(plist)
+    ogs = [oracle.Graph.from_pairs(p) for p in plist]
+    srcs = [first_non_isolated(og) for og in ogs]
+    depth, parent, st = B.bfs(srcs, **kw)
+    label, _ = B.cc(**kw)
+    D, P, L = B.split(depth.cpu().numpy()), B.split(parent.cpu().numpy()), B.split(label.cpu().numpy())
+    reached = 0
+    for i, og in enumerate(ogs):
+        want, _ = og.bfs(srcs[i])
+        assert np.array_equal(D[i], want), i
+        assert og.check_bfs(srcs[i], D[i], P[i]) == 0, i
+        assert np.array_equal(L[i], og.cc()), i
+        reached += int((want >= 0).sum())
+    assert st["reached"] == reached
+    return st
+
+
+def test_batch_config_64_er_graphs():
+    """The full batch: 64 ER graphs, n log-uniform in [2^10, 2^18], degree in [4, 32]."""
+    st = check_batch(gen.batch_pairs(64, seed=3))
+    assert st["levels"] >= 2
+
+
+@pytest.mark.parametrize("variant", list(range(6)))
+def test_batch_fixed_variants(variant):
+    plist = gen.batch_pairs(12, seed=7, log2_hi=13.0)
+    check_batch(plist, selector=byo.SEL_FIXED, fixed_variant=variant)
+
+
+def test_batch_mixed_shapes():
+    plist = [graphs.star(5000), graphs.path(300), graphs.pairs(1, [], [], "single"),
+             gen.grid_pairs(30, 40, 0.1, seed=2), gen.rmat_pairs(12, 8, seed=9), graphs.empty(70)]
+    check_batch(plist)
+
+
+def test_batch_rejects_bad_input():
+    with pytest.raises(byo.ByoError):
+        byo.Batch([(np.array([0, 1], np.int64), np.array([5], np.int32))])   # neighbour out of range
+    B = byo.Batch.from_pairs([graphs.path(10), graphs.path(5)])
+    with pytest.raises(byo.ByoError):
+        B.bfs([0, 5])                                                         # source outside graph 1
