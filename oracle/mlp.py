@@ -105,3 +105,14 @@ def predict_argmin(p, X, allowed=None):
     if allowed is not None:
         out = np.where(np.asarray(allowed, bool), out, np.inf)
     return np.argmin(out, axis=1)
+
+
+def selector_features(k, degsum, unvisited, n, m, max_deg, cv, dense_in):
+    """Raw features of one edgeMap level, in FP64, as the selector defines them:
+    log2(1+k), log2(1+sum deg U), log2(1+unvisited), log2(1+n), log2(1+m),
+    (k + sum deg U)/(m+1), k/(n+1), log2(1+max degree), degree CV,
+    log2(1 + sum deg U/(k+1)), unvisited/(n+1), dense-only flag."""
+    import math
+    return [math.log2(1 + k), math.log2(1 + degsum), math.log2(1 + unvisited), math.log2(1 + n),
+            math.log2(1 + m), (k + degsum) / (m + 1), k / (n + 1), math.log2(1 + max_deg), cv,
+            math.log2(1 + degsum / (k + 1)), unvisited / (n + 1), float(dense_in)]

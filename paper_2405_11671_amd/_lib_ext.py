@@ -3,7 +3,20 @@ import ctypes
 
 from ._lib import LevelRecord, Opts, RunStats, dbl, i32, i32p, i64, i64p, st, vp
 
+fp = ctypes.POINTER(ctypes.c_float)
+
 SIGNATURES = {
+    "byo_selector_features": (st, [ctypes.POINTER(LevelRecord), fp]),
+    "byo_heuristic_choice": (i32, [i64, i64, i64, i64, dbl, ctypes.POINTER(Opts), i32]),
+    "byo_mlp_forward": (st, [vp, vp, i32, vp, vp]),
+    "byo_mlp_loss_grad": (st, [vp, vp, vp, vp, i32, vp, vp, vp]),
+    "byo_mlp_adam": (st, [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
+    "byo_mlp_train": (st, [vp, vp, vp, vp, i32, i32, ctypes.c_float, vp, vp]),
+    "byo_selector_set": (st, [fp, fp, fp]),
+    "byo_selector_clear": (st, []),
+    "byo_selector_loaded": (st, [i32p]),
+    "byo_selector_predict": (st, [fp, i32, fp, i32p]),
+    "byo_selector_collect": (st, [vp, i32, i64, i32, vp, ctypes.POINTER(Opts), vp]),
     "byo_batch_create": (st, [i32, vp, vp, vp, vp, ctypes.POINTER(vp)]),
     "byo_batch_destroy": (None, [vp]),
     "byo_batch_info": (st, [vp, i64p, i64p]),

@@ -4,11 +4,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include <string>
 #include <vector>
 
 #include "byo.h"
 #include "byo_trace.h"
+#include "byo_selector.h"
 
 // ---------------------------------------------------------------- errors
 
@@ -262,6 +265,42 @@ struct ktimer_scope {
   ~ktimer_scope();
 };
 
+// ---------------------------------------------------------------- variant choice
+
+// Threshold rule (host and device): dense pull iff |U| + sum(deg(U)) > m / div
+// (the sparse/dense cutoff of Section 6.3); sparse pushes are edge-balanced on
+// skewed graphs or heavy frontiers, wavefront-per-vertex for high average
+// degree, thread-per-vertex otherwise.
+__host__ __device__ inline int heuristic_rule(int64_t k, int64_t degsum, int64_t m, int64_t max_deg, double cv,
+                                              int div, int t_wave, int t_block, bool allow_pull) {
+  if (div <= 0) div = 20;
+  if (t_wave <= 0) t_wave = 32;
+  if (t_block <= 0) t_block = 4096;
+  if (allow_pull && k + degsum > m / div)
+    return (cv > 1.0 || max_deg > 4 * (int64_t)t_wave) ? BYO_V_PULL_WAVE : BYO_V_PULL_THREAD;
+  double avg = k > 0 ? (double)degsum / (double)k : 0.0;
+  if (max_deg >= t_block || degsum >= 65536) return BYO_V_PUSH_EDGE;
+  if (avg >= t_wave) return BYO_V_PUSH_WAVE;
+  return BYO_V_PUSH_THREAD;
+}
+
+// Raw selector features of a level (host and device; see byo_selector.h).
+__host__ __device__ inline void selector_features(double k, double degsum, double unvisited, double n, double m,
+                                                  double max_deg, double cv, double dense_in, float *f) {
+  f[0] = (float)log2(1.0 + k);
+  f[1] = (float)log2(1.0 + degsum);
+  f[2] = (float)log2(1.0 + unvisited);
+  f[3] = (float)log2(1.0 + n);
+  f[4] = (float)log2(1.0 + m);
+  f[5] = (float)((k + degsum) / (m + 1.0));
+  f[6] = (float)(k / (n + 1.0));
+  f[7] = (float)log2(1.0 + max_deg);
+  f[8] = (float)cv;
+  f[9] = (float)log2(1.0 + degsum / (k + 1.0));
+  f[10] = (float)(unvisited / (n + 1.0));
+  f[11] = (float)dense_in;
+}
+
 // variant choice (selector.hip)
 struct level_features {
   int64_t n, m, k, degsum, unvisited, max_deg, level;
@@ -274,5 +313,14 @@ int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
                    const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull);
+// learned selector (selector.hip)
+bool selector_ready();
+// Host-side prediction for one level (one launch + sync); -1 if not ready.
+int selector_pick_host(const level_features &f, bool allow_pull, const byo_opts &o, hipStream_t s);
+// Enqueue the on-device choice for the level after `ctr`'s level: features
+// from ctr->count / ctr->degsum, result written to ctr->aux1. reached_before < 0
+// means "unvisited is always n" (connectivity).
+byo_status selector_pick_device(byo_counters *ctr, const byo_graph *g, int64_t reached_before, int64_t next_level,
+                                bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s);
 
 }  // namespace byo

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "internal.h"
@@ -17,19 +18,8 @@ namespace byo {
 static bool is_pull(int v) { return v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE; }
 
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull) {
-  int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
-  bool dense = allow_pull && (f.k + f.degsum > f.m / div);
-  if (dense) return (f.cv > 1.0 || f.max_deg > 4 * (o.t_wave > 0 ? o.t_wave : 32)) ? BYO_V_PULL_WAVE
-                                                                                   : BYO_V_PULL_THREAD;
-  // sparse: edge-balanced when the graph is skewed or the frontier is heavy
-  double avg = f.k > 0 ? (double)f.degsum / (double)f.k : 0.0;
-  if (f.max_deg >= (o.t_block > 0 ? o.t_block : 4096) || f.degsum >= 65536) return BYO_V_PUSH_EDGE;
-  if (avg >= (o.t_wave > 0 ? o.t_wave : 32)) return BYO_V_PUSH_WAVE;
-  return BYO_V_PUSH_THREAD;
+  return heuristic_rule(f.k, f.degsum, f.m, f.max_deg, f.cv, o.dense_divisor, o.t_wave, o.t_block, allow_pull);
 }
-
-// The learned selector lives in mlp.hip; it returns -1 when it has no weights.
-int mlp_choose_variant(const level_features &f, bool allow_pull);
 
 int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) {
   if (o.selector == BYO_SEL_FIXED) {
@@ -38,11 +28,18 @@ int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) 
     if (!allow_pull && is_pull(v)) v = BYO_V_PUSH_EDGE;
     return v;
   }
-  if (o.selector == BYO_SEL_MLP) {
-    int v = mlp_choose_variant(f, allow_pull);
-    if (v >= 0) return v;
-  }
   return heuristic_variant(o, f, allow_pull);
+}
+
+// Variant for this level: the learned selector's on-device choice made after
+// the previous level (or one host-launched prediction for the first level),
+// else the fixed / threshold rule.
+static int pick(const byo_opts &o, const level_features &f, bool use_mlp, int next_v, hipStream_t s) {
+  if (use_mlp) {
+    int v = (next_v >= 0 && next_v < BYO_NUM_VARIANTS) ? next_v : selector_pick_host(f, true, o, s);
+    if (v >= 0 && v < BYO_NUM_VARIANTS) return v;
+  }
+  return choose_variant(o, f, true);
 }
 
 // ---------------------------------------------------------------- small kernels
@@ -233,13 +230,15 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   bfs_state bs{d_parent, d_depth, w.visited, 0};
   int32_t level = 0;
+  bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
+  int next_v = -1;
   while (true) {
     if (level >= cap) {
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "BFS level cap reached");
     }
     level_features f = features(g, fr.k, fr.degsum, n - reached, level, fr.dense && !fr.sparse);
-    int v = choose_variant(o, f, true);
+    int v = pick(o, f, use_mlp, next_v, s);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -259,9 +258,11 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     bs.level = level;
     BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
     lt.stop();
+    if (use_mlp) BYO_TRY(selector_pick_device(io.ctr, g, reached, level + 1, is_pull(v), true, o, s));
     st.variant_count[v]++;
     byo_counters c;
     BYO_TRY(read_slot(g, level % BYO_COUNTER_SLOTS, s, &c));
+    next_v = use_mlp ? (int)c.aux1 : -1;
     lt.record(BYO_ALGO_BFS, g, f, v, (int64_t)c.count, (int64_t)c.degsum);
     ++level;
     if (c.count == 0) break;
@@ -328,13 +329,15 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
   fr.degsum = g->m;
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   int32_t round = 0;
+  bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
+  int next_v = -1;
   while (true) {
     if (round >= cap) {
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "connectivity round cap reached");
     }
     level_features f = features(g, fr.k, fr.degsum, n, round, fr.dense && !fr.sparse);
-    int v = choose_variant(o, f, true);
+    int v = pick(o, f, use_mlp, next_v, s);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -355,9 +358,11 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
     if (shortcut) BYO_TRY(cc_shortcut(g, d_label, w.bits[nxt], io.ctr, s));
     lt.stop();
+    if (use_mlp) BYO_TRY(selector_pick_device(io.ctr, g, -1, round + 1, is_pull(v) || shortcut, true, o, s));
     st.variant_count[v]++;
     byo_counters c;
     BYO_TRY(read_slot(g, round % BYO_COUNTER_SLOTS, s, &c));
+    next_v = use_mlp ? (int)c.aux1 : -1;
     lt.record(BYO_ALGO_CC, g, f, v, (int64_t)c.count, (int64_t)c.degsum);
     ++round;
     if (c.count == 0) break;
@@ -444,3 +449,191 @@ byo_status byo_edge_map(byo_graph *g, byo_vset *U, byo_edge_fn F, const void *F_
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- selector training data
+
+namespace byo {
+
+static void push_trial(int algo, const byo_graph *g, const level_features &f, int v, float ms, int64_t oc,
+                       int64_t od) {
+  byo_level_record r;
+  std::memset(&r, 0, sizeof(r));
+  r.algo = algo;
+  r.level = (int32_t)f.level;
+  r.variant = v;
+  r.dense_in = f.dense_in ? 1 : 0;
+  r.n = g->n;
+  r.m = g->m;
+  r.k = f.k;
+  r.degsum = f.degsum;
+  r.unvisited = f.unvisited;
+  r.out_count = oc;
+  r.out_degsum = od;
+  r.max_deg = g->max_deg;
+  r.cv = g->cv_deg;
+  r.ms = ms;
+  trace_push(r);
+}
+
+// Time every variant of each level from the same saved state, record one row
+// per (level, variant), then advance with the fastest variant.
+static byo_status collect(byo_graph *g, int algo, int64_t src, int repeats, int32_t *d_out, const byo_opts &o0,
+                          hipStream_t s) {
+  BYO_TRY(ws_ensure_traversal(g));
+  byo_workspace &w = g->ws;
+  int64_t n = g->n;
+  byo_opts o = o0;
+  o.selector = BYO_SEL_FIXED;
+  bool bfs = algo == BYO_ALGO_BFS;
+  int32_t *parent = nullptr, *save_a = nullptr, *save_b = nullptr;
+  uint64_t *save_vis = nullptr;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  auto cleanup = [&]() {
+    if (parent) (void)hipFree(parent);
+    if (save_a) (void)hipFree(save_a);
+    if (save_b) (void)hipFree(save_b);
+    if (save_vis) (void)hipFree(save_vis);
+    if (ea) (void)hipEventDestroy(ea);
+    if (eb) (void)hipEventDestroy(eb);
+  };
+  struct guard {
+    std::function<void()> f;
+    ~guard() { f(); }
+  } gd{cleanup};
+  BYO_HIP(hipEventCreate(&ea));
+  BYO_HIP(hipEventCreate(&eb));
+  size_t ib = sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1);
+  BYO_HIP(hipMalloc(&save_a, ib));
+  BYO_HIP(hipMalloc(&save_b, ib));
+  BYO_HIP(hipMalloc(&save_vis, sizeof(uint64_t) * (size_t)std::max<int64_t>(w.words, 1)));
+  frontier fr;
+  int64_t reached = 0;
+  if (bfs) {
+    BYO_CHECK(src >= 0 && src < n, BYO_EINVAL, "source out of range");
+    BYO_HIP(hipMalloc(&parent, ib));
+    int32_t s32 = (int32_t)src;
+    BYO_TRY(fill_i32(parent, n, -1, s));
+    BYO_TRY(fill_i32(d_out, n, -1, s));
+    BYO_HIP(hipMemcpyAsync(w.ids[1], &s32, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
+        w.visited, g->zero_bits, n, w.words, s32);
+    bfs_init_kernel<<<1, 256, 0, s>>>(parent, d_out, w.ids[1], 1, w.ids[0], w.ctr);
+    int32_t d0 = 0;
+    BYO_TRY(sync_read(s, g->deg + src, &d0, sizeof(d0)));
+    fr.sparse = true;
+    fr.k = 1;
+    fr.degsum = d0;
+    reached = 1;
+  } else {
+    if (n == 0) return BYO_OK;
+    iota_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, s>>>(d_out, n);
+    zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);
+    BYO_TRY(fill_u64(w.bits[0], w.words, ~0ull, s));
+    if (n & 63) {
+      uint64_t last = ~0ull >> (64 - (n & 63));
+      BYO_HIP(hipMemcpyAsync(w.bits[0] + (w.words - 1), &last, sizeof(last), hipMemcpyHostToDevice, s));
+      BYO_HIP(hipStreamSynchronize(s));
+    }
+    fr.dense = true;
+    fr.k = n;
+    fr.degsum = g->m;
+  }
+  int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
+  for (int32_t level = 0; level < cap; ++level) {
+    level_features f = features(g, fr.k, fr.degsum, bfs ? n - reached : n, level, fr.dense && !fr.sparse);
+    // save the state a level modifies
+    BYO_HIP(hipMemcpyAsync(save_a, d_out, ib, hipMemcpyDeviceToDevice, s));
+    if (bfs) {
+      BYO_HIP(hipMemcpyAsync(save_b, parent, ib, hipMemcpyDeviceToDevice, s));
+      BYO_HIP(hipMemcpyAsync(save_vis, w.visited, sizeof(uint64_t) * w.words, hipMemcpyDeviceToDevice, s));
+    }
+    frontier saved = fr;
+    int best = -1;
+    float best_ms = 0.f;
+    byo_counters c;
+    std::memset(&c, 0, sizeof(c));
+    for (int pass = 0; pass <= BYO_NUM_VARIANTS; ++pass) {
+      // passes 0..K-1 time each variant; the last pass re-runs the fastest to advance
+      bool final_pass = pass == BYO_NUM_VARIANTS;
+      int v = final_pass ? best : pass;
+      int reps = final_pass ? 1 : std::max(1, repeats);
+      float vbest = 0.f;
+      for (int r = 0; r < reps; ++r) {
+        BYO_HIP(hipMemcpyAsync(d_out, save_a, ib, hipMemcpyDeviceToDevice, s));
+        if (bfs) {
+          BYO_HIP(hipMemcpyAsync(parent, save_b, ib, hipMemcpyDeviceToDevice, s));
+          BYO_HIP(hipMemcpyAsync(w.visited, save_vis, sizeof(uint64_t) * w.words, hipMemcpyDeviceToDevice, s));
+        }
+        fr = saved;
+        zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);
+        int nxt = 1 - fr.cur;
+        level_io io;
+        std::memset(&io, 0, sizeof(io));
+        io.in_count = fr.k;
+        io.ctr = w.ctr;
+        BYO_HIP(hipEventRecord(ea, s));
+        if (bfs) {
+          if (is_pull(v)) {
+            BYO_TRY(make_dense(g, fr, s));
+            io.in_bits = w.bits[fr.cur];
+            io.out_bits = w.bits[nxt];
+          } else {
+            BYO_TRY(make_sparse(g, fr, s));
+            io.in_ids = w.ids[fr.cur];
+            io.out_ids = w.ids[nxt];
+          }
+          bfs_state bs{parent, d_out, w.visited, level};
+          BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
+        } else {
+          io.out_bits = w.bits[nxt];
+          if (is_pull(v)) {
+            BYO_TRY(make_dense(g, fr, s));
+            io.in_bits = w.bits[fr.cur];
+          } else {
+            BYO_TRY(make_sparse(g, fr, s));
+            io.in_ids = w.ids[fr.cur];
+          }
+          BYO_TRY(cc_level(g, v, d_out, io, o, s, fr.degsum));
+          if (o.cc_shortcut) BYO_TRY(cc_shortcut(g, d_out, w.bits[nxt], io.ctr, s));
+        }
+        BYO_HIP(hipEventRecord(eb, s));
+        BYO_TRY(read_slot(g, 0, s, &c));
+        float ms = 0.f;
+        BYO_HIP(hipEventElapsedTime(&ms, ea, eb));
+        if (r == 0 || ms < vbest) vbest = ms;
+      }
+      if (final_pass) break;
+      push_trial(algo, g, f, v, vbest, (int64_t)c.count, (int64_t)c.degsum);
+      if (best < 0 || vbest < best_ms) {
+        best = v;
+        best_ms = vbest;
+      }
+    }
+    if (c.count == 0) break;
+    reached += (int64_t)c.count;
+    fr.cur = 1 - fr.cur;
+    if (bfs) {
+      fr.sparse = !is_pull(best);
+      fr.dense = is_pull(best);
+    } else {
+      fr.dense = true;
+      fr.sparse = false;
+    }
+    fr.k = (int64_t)c.count;
+    fr.degsum = (int64_t)c.degsum;
+  }
+  BYO_HIP(hipStreamSynchronize(s));
+  return BYO_OK;
+}
+
+}  // namespace byo
+
+extern "C" byo_status byo_selector_collect(byo_graph *g, int32_t algo, int64_t src, int32_t repeats, int32_t *d_out,
+                                           const byo_opts *opts, void *stream) {
+  BYO_CHECK(g && d_out, BYO_EINVAL, "null argument");
+  BYO_CHECK(algo == BYO_ALGO_BFS || algo == BYO_ALGO_CC, BYO_EINVAL, "collection supports BFS and CC");
+  byo_opts o;
+  byo_opts_default(&o);
+  if (opts) o = *opts;
+  return collect(g, algo, src, repeats, d_out, o, (hipStream_t)stream);
+}

@@ -1,0 +1,211 @@
+"""GPU checks of the learned selector: the MLP kernels against the FP64 oracle,
+device inference, result invariance under any learned choice, and the gain of
+the trained selector over the threshold heuristic on held-out graphs."""
+import ctypes
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_2405_11671_amd import gen
+from tests import graphs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+byo = pytest.importorskip("paper_2405_11671_amd")
+from paper_2405_11671_amd import _lib, selector as sel  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def o64(p):
+    return {k: v.astype(np.float64) for k, v in sel.unpack(p).items()}
+
+
+def dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def rand_problem(N=1000, seed=0):
+    rng = np.random.default_rng(seed)
+    p = sel.init_params(seed)
+    X = rng.standard_normal((N, 12)).astype(np.float32)
+    Y = rng.standard_normal((N, 6)).astype(np.float32)
+    M = (rng.random((N, 6)) < 0.8).astype(np.float32)
+    return p, X, Y, M
+
+
+def test_forward_matches_oracle():
+    p, X, _, _ = rand_problem(777)
+    out = torch.empty((X.shape[0], 6), dtype=torch.float32, device="cuda")
+    pd, Xd = torch.from_numpy(p).cuda(), torch.from_numpy(X).cuda()   # keep the buffers alive
+    _lib.check(_lib.load().byo_mlp_forward(dptr(pd), dptr(Xd), X.shape[0], dptr(out), stream()))
+    want, _ = omlp.forward(o64(p), X.astype(np.float64))
+    got = out.cpu().numpy()
+    assert np.max(np.abs(got - want)) / np.max(np.abs(want)) < 1e-5
+
+
+@pytest.mark.parametrize("N", [1, 300, 2049])
+def test_gradients_match_oracle(N):
+    p, X, Y, M = rand_problem(N, seed=N)
+    grad = torch.empty(sel.P, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    pd, Xd, Yd, Md = (torch.from_numpy(a).cuda() for a in (p, X, Y, M))
+    _lib.check(_lib.load().byo_mlp_loss_grad(dptr(pd), dptr(Xd), dptr(Yd), dptr(Md), N, dptr(grad), dptr(loss),
+                                             stream()))
+    L, g = omlp.loss_and_grads(o64(p), X.astype(np.float64), Y.astype(np.float64), M.astype(np.float64))
+    assert abs(loss.item() - L) / max(abs(L), 1e-12) < 1e-5
+    gg = sel.unpack(grad.cpu().numpy())
+    for k in omlp.PARAM_NAMES:
+        rel = np.linalg.norm(gg[k] - g[k]) / max(np.linalg.norm(g[k]), 1e-12)
+        assert rel < 1e-4, (k, rel)
+
+
+def test_adam_step_matches_oracle():
+    p, X, Y, M = rand_problem(64, seed=5)
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal(sel.P).astype(np.float32)
+    m0 = (rng.standard_normal(sel.P) * 0.1).astype(np.float32)
+    v0 = (rng.random(sel.P) * 0.1).astype(np.float32)
+    pd, md, vd = (torch.from_numpy(a.copy()).cuda() for a in (p, m0, v0))
+    gd = torch.from_numpy(g).cuda()
+    _lib.check(_lib.load().byo_mlp_adam(dptr(pd), dptr(gd), dptr(md), dptr(vd), 7,
+                                        ctypes.c_float(1e-3), ctypes.c_float(0.9), ctypes.c_float(0.999),
+                                        ctypes.c_float(1e-8), stream()))
+    st = {"m": o64(m0), "v": o64(v0)}
+    want = omlp.adam_step(o64(p), o64(g), st, 7, 1e-3)
+    got = sel.unpack(pd.cpu().numpy())
+    for k in omlp.PARAM_NAMES:
+        assert np.allclose(got[k], want[k], rtol=1e-5, atol=1e-7), k
+
+
+def test_training_matches_oracle_trajectory():
+    p, X, Y, M = rand_problem(500, seed=9)
+    got_p, got_l = sel.train(X, Y, M, steps=150, lr=3e-3, params=p)
+    want_p, want_l = omlp.train(o64(p), X.astype(np.float64), Y.astype(np.float64), M.astype(np.float64), 150,
+                                lr=3e-3)
+    assert np.allclose(got_l, want_l, rtol=2e-3)
+    gp = sel.unpack(got_p)
+    for k in omlp.PARAM_NAMES:
+        rel = np.linalg.norm(gp[k] - want_p[k]) / max(np.linalg.norm(want_p[k]), 1e-12)
+        assert rel < 2e-3, (k, rel)
+
+
+def test_device_inference_matches_oracle():
+    p = sel.init_params(11)
+    rng = np.random.default_rng(11)
+    mu = rng.standard_normal(12).astype(np.float32)
+    sd = (rng.random(12) + 0.5).astype(np.float32)
+    sel.install(p, mu, sd)
+    try:
+        for _ in range(20):
+            f = (rng.standard_normal(12) * 3).astype(np.float32)
+            pred, v = sel.predict(f)
+            want, _ = omlp.forward(o64(p), ((f.astype(np.float64) - mu) / sd)[None, :])
+            assert np.allclose(pred, want[0], rtol=1e-5, atol=1e-5)
+            order = np.sort(want[0])
+            if order[1] - order[0] > 1e-4:
+                assert v == int(np.argmin(want[0]))
+            pred2, v2 = sel.predict(f, allow_pull=False)
+            assert v2 in (0, 1, 2, 3)
+    finally:
+        sel.clear()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_results_invariant_under_any_learned_choice(seed):
+    """Random weights make arbitrary per-level choices; BFS and CC stay exact."""
+    sel.install(sel.init_params(100 + seed), np.zeros(12, np.float32), np.ones(12, np.float32))
+    try:
+        for p in graphs.small_suite()[:6]:
+            g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+            d, par, st = byo.bfs(g, 0, selector=byo.SEL_MLP)
+            want, _ = og.bfs(0)
+            assert np.array_equal(d.cpu().numpy(), want), p.name
+            assert og.check_bfs(0, d.cpu().numpy(), par.cpu().numpy()) == 0
+            lab, _ = byo.cc(g, selector=byo.SEL_MLP)
+            assert np.array_equal(lab.cpu().numpy(), og.cc()), p.name
+    finally:
+        sel.clear()
+
+
+def test_fallback_without_weights():
+    sel.clear()
+    assert not sel.loaded()
+    p = graphs.small_suite()[1]
+    g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+    d, _, st = byo.bfs(g, 3, selector=byo.SEL_MLP)
+    d2, _, st2 = byo.bfs(g, 3)
+    assert np.array_equal(d.cpu().numpy(), og.bfs(3)[0])
+    assert st["variant_count"] == st2["variant_count"]    # same choices as the heuristic
+
+
+def test_collected_tables_are_consistent():
+    p = gen.rmat_pairs(14, 16, seed=3)
+    g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+    levels, depth = sel.collect(g, sel.ALGO_BFS, 5, repeats=1)
+    assert np.array_equal(depth.cpu().numpy(), og.bfs(5)[0])
+    want = og.bfs(5)[0]
+    assert len(levels) == int(want.max()) + 1
+    for lv in levels:
+        assert np.all(np.isfinite(lv["ms"])) and np.all(lv["ms"] > 0)
+    levels, lab = sel.collect(g, sel.ALGO_CC, 0, repeats=1)
+    assert np.array_equal(lab.cpu().numpy(), og.cc())
+
+
+def training_graphs():
+    # sizes bracket the held-out graphs: the features include log2 n and log2 m
+    return [gen.rmat_pairs(s, 16, seed=11 + s) for s in (14, 16, 18, 20)] + \
+           [gen.er_pairs(1 << 17, d, seed=21 + d) for d in (4, 10, 16)] + \
+           [gen.grid_pairs(256, 256, 0.1, seed=5), gen.grid_pairs(1024, 1024, 0.1, seed=6)]
+
+
+def heldout_graphs():
+    # different seeds and sizes from every training graph
+    return [gen.rmat_pairs(19, 16, seed=77), gen.er_pairs(1 << 18, 10, seed=78), gen.grid_pairs(384, 384, 0.1, seed=79)]
+
+
+def collect_tables(plist, sources=2):
+    levels = []
+    for p in plist:
+        g = byo.Graph.from_pairs(p)
+        srcs = gen.pick_sources(p, sources, seed=2)
+        for s in srcs:
+            lv, _ = sel.collect(g, sel.ALGO_BFS, int(s), repeats=2, tag=p.name)
+            levels += lv
+        lv, _ = sel.collect(g, sel.ALGO_CC, 0, repeats=2, tag=p.name)
+        levels += lv
+    return levels
+
+
+def test_trained_selector_gain_on_heldout_graphs(capsys):
+    """Train on the library's own timing tables, evaluate on graphs it never saw."""
+    train_levels = collect_tables(training_graphs())
+    X, Y, M = sel.dataset(train_levels)
+    mu, sd = sel.normaliser(X)
+    params, losses = sel.train((X - mu) / sd, Y, M, steps=3000, lr=3e-3)
+    assert losses[-1] < 0.5 * losses[0]
+    test_levels = collect_tables(heldout_graphs())
+    rep = sel.compare(test_levels, params, mu, sd)
+    gain = rep["heuristic_ms"] / rep["learned_ms"]
+    with capsys.disabled():
+        print(f"\n[selector] held-out: heuristic {rep['heuristic_ms']:.3f} ms, learned {rep['learned_ms']:.3f} ms, "
+              f"best {rep['best_ms']:.3f} ms over {rep['levels']} levels; gain {gain:.3f}x")
+    # the learned policy beats the rule it replaces on graphs it never saw
+    assert gain > 1.0
+    # online: the installed selector still gives exact results on a held-out graph
+    sel.install(params, mu, sd)
+    try:
+        p = heldout_graphs()[0]
+        g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+        d, _, st = byo.bfs(g, 1, selector=byo.SEL_MLP)
+        assert np.array_equal(d.cpu().numpy(), og.bfs(1)[0])
+    finally:
+        sel.clear()

@@ -1,0 +1,75 @@
+"""CPU checks of the selector's host-side pieces (features, threshold rule,
+weight validation, weight files)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+from paper_2405_11671_amd import _lib
+from paper_2405_11671_amd import selector as sel
+
+
+def rec(**kw):
+    base = dict(algo=0, level=3, variant=0, dense_in=0, n=1 << 20, m=31_000_000, k=1000, degsum=50_000,
+                unvisited=600_000, out_count=0, out_degsum=0, max_deg=60_000, cv=4.5, ms=0.0)
+    base.update(kw)
+    return base
+
+
+@pytest.mark.parametrize("r", [rec(), rec(k=0, degsum=0, dense_in=1), rec(k=1 << 20, degsum=31_000_000, unvisited=0),
+                               rec(n=1, m=0, k=1, degsum=0, max_deg=0, cv=0.0)])
+def test_features_match_oracle_definition(r):
+    got = sel.features(r)
+    want = omlp.selector_features(r["k"], r["degsum"], r["unvisited"], r["n"], r["m"], r["max_deg"], r["cv"],
+                                  r["dense_in"])
+    assert np.allclose(got, np.array(want, np.float32), rtol=1e-6, atol=1e-7)
+
+
+def test_heuristic_cutoff_and_balance_choices():
+    m = 2_000_000
+    # exactly at the cutoff stays sparse; one more goes dense (k + degsum > m/20)
+    at = rec(m=m, k=10, degsum=m // 20 - 10, max_deg=100, cv=0.5)
+    over = rec(m=m, k=11, degsum=m // 20 - 10, max_deg=100, cv=0.5)
+    assert sel.heuristic_choice(at) in (0, 1, 2, 3)
+    assert sel.heuristic_choice(over) == 4                       # low skew -> thread pull
+    assert sel.heuristic_choice(dict(over, cv=3.0)) == 5         # skewed -> wave-assisted pull
+    assert sel.heuristic_choice(over, allow_pull=False) in (0, 1, 2, 3)
+    assert sel.heuristic_choice(rec(m=m, k=10, degsum=100, max_deg=10, cv=0.1)) == 0
+    assert sel.heuristic_choice(rec(m=m, k=10, degsum=5000, max_deg=900, cv=0.1)) == 1
+    assert sel.heuristic_choice(rec(m=m, k=10, degsum=5000, max_deg=5000, cv=0.1)) == 3
+
+
+def test_selector_rejects_non_finite_weights():
+    p = sel.init_params(1)
+    mu, sd = np.zeros(12, np.float32), np.ones(12, np.float32)
+    for bad in (p.copy(), mu.copy(), sd.copy()):
+        bad[3] = np.nan
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib = _lib.load()
+    bp = p.copy(); bp[7] = np.nan
+    assert lib.byo_selector_set(bp.ctypes.data_as(fp), mu.ctypes.data_as(fp), sd.ctypes.data_as(fp)) == -1
+    bs = sd.copy(); bs[0] = 0.0
+    assert lib.byo_selector_set(p.ctypes.data_as(fp), mu.ctypes.data_as(fp), bs.ctypes.data_as(fp)) == -1
+    bm = mu.copy(); bm[2] = np.inf
+    assert lib.byo_selector_set(p.ctypes.data_as(fp), bm.ctypes.data_as(fp), sd.ctypes.data_as(fp)) == -1
+
+
+def test_weight_file_roundtrip(tmp_path):
+    p = sel.init_params(2)
+    mu, sd = np.arange(12, dtype=np.float32), np.full(12, 2.0, np.float32)
+    path = tmp_path / "w.json"
+    sel.save(path, p, mu, sd, {"trained_on": ["x"]})
+    p2, mu2, sd2, meta = sel.load_weights(path)
+    assert np.array_equal(p, p2) and np.array_equal(mu, mu2) and np.array_equal(sd, sd2)
+    assert meta == {"trained_on": ["x"]}
+
+
+def test_numpy_forward_matches_oracle():
+    rng = np.random.default_rng(0)
+    p = sel.init_params(3)
+    X = rng.standard_normal((50, 12)).astype(np.float32)
+    got = sel.forward_np(p, X)
+    want, _ = omlp.forward({k: v.astype(np.float64) for k, v in sel.unpack(p).items()}, X.astype(np.float64))
+    assert np.allclose(got, want, rtol=1e-5, atol=1e-5)
