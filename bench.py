@@ -1,13 +1,15 @@
 """Benchmark: GTEPS of the edgeMap hot path on RMAT scale 22 (one MI355X).
 
 One step = multi-source BFS from 256 sources (bit-parallel batch) + PageRank
-(20 steps, FP32) + connectivity, all on the same HBM-resident graph. TEPS
+(20 steps, FP32) + connectivity (learned variant selector), all on the same
+HBM-resident graph. TEPS
 conventions:
   BFS: undirected edges in the reached component, summed over sources (Graph500),
   PageRank: iterations x m directed edges, connectivity: m/2 undirected edges.
 value = all traversed edges of the timed steps / their wall time.
-The plain single-source heuristic BFS (16 sources) is timed separately and
-reported in "detail" for the batched-vs-plain comparison.
+Single-source BFS from 16 sources is timed separately, with the threshold
+heuristic ("plain") and with the learned selector, and reported in "detail"
+next to the batched rate.
 
 Prints ONE JSON line. `--probe pr` instead runs a few PageRank steps and a
 plain 512 MiB device copy, for hardware-counter runs (bytes per dispatch).
@@ -135,6 +137,11 @@ def main():
     label = torch.empty(n, dtype=torch.int32, device="cuda")
     rank = torch.empty(n, dtype=torch.float32, device="cuda")
     opts = byo.default_opts()
+    from paper_2405_11671_amd import selector as sel
+    wpath = os.path.join(ROOT, "paper_2405_11671_amd", "selector_weights.json")
+    params, mu, sd, _ = sel.load_weights(wpath)
+    sel.install(params, mu, sd)
+    mlp_opts = byo.default_opts(selector=byo.SEL_MLP)
 
     ms_srcs = gen.pick_sources(pairs, args.ms_sources, seed=2)
     ms_depth = torch.empty(n * len(ms_srcs), dtype=torch.uint8, device="cuda")
@@ -146,7 +153,7 @@ def main():
         ev[1].record()
         byo.pagerank(g, 0.85, args.pr_iters, opts=opts, rank=rank)
         ev[2].record()
-        _, cst = byo.cc(g, opts=opts, label=label)
+        _, cst = byo.cc(g, opts=mlp_opts, label=label)
         ev[3].record()
         ms_edges = mst["edges"] // 2
         if record is not None:
@@ -156,19 +163,26 @@ def main():
                            "ms_levels": mst["levels"], "cc_rounds": cst["levels"]})
         return ms_edges
 
-    def plain_bfs():
+    def single_bfs(o):
         torch.cuda.synchronize()
         t = time.perf_counter()
         e = 0
         for s_ in srcs:
-            _, _, st = byo.bfs(g, int(s_), opts=opts, depth=depth, parent=parent)
+            _, _, st = byo.bfs(g, int(s_), opts=o, depth=depth, parent=parent)
             e += st["edges"] // 2
         torch.cuda.synchronize()
         return e / (time.perf_counter() - t) / 1e9
 
+    def plain_bfs():
+        return single_bfs(opts)
+
+    def learned_bfs():
+        return single_bfs(mlp_opts)
+
     for _ in range(args.warmup):
         step()
         plain_bfs()
+        learned_bfs()
     torch.cuda.synchronize()
     rec = []
     byo.ktimer_reset()
@@ -185,6 +199,7 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = edges_total / wall / 1e9
     plain = [plain_bfs() for _ in range(3)]
+    learned = [learned_bfs() for _ in range(3)]
     ms_ms = float(np.median([r["ms_ms"] for r in rec]))
     pr_ms = float(np.median([r["pr_ms"] for r in rec]))
     cc_ms = float(np.median([r["cc_ms"] for r in rec]))
@@ -197,6 +212,8 @@ def main():
         "pr_gteps": args.pr_iters * m / (pr_ms * 1e-3) / 1e9, "pr_ms": pr_ms,
         "cc_ms": cc_ms, "cc_rounds": rec[0]["cc_rounds"],
         "plain_bfs_gteps": float(np.median(plain)),
+        "learned_bfs_gteps": float(np.median(learned)),
+        "learned_vs_plain": float(np.median(learned)) / float(np.median(plain)),
         "batched_vs_plain": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9 / float(np.median(plain)),
         "pr_pull_avg_ms": pr_avg_ms, "pr_pull_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
         "kernel_ms": {f: round(v[1] / args.steps, 3) for f, v in kt.items() if v[0]},

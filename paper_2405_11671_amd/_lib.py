@@ -135,6 +135,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_2405_11671_amd.build.build() "
                               "(the HIP library is required: there is no fallback)")
+        # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+        # Load it first so the library binds to that one runtime: device pointers
+        # and streams from torch then belong to the runtime the kernels use.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         _declare(lib, SIGNATURES)
         _declare(lib, extra_signatures())
