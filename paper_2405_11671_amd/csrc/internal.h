@@ -322,5 +322,10 @@ int selector_pick_host(const level_features &f, bool allow_pull, const byo_opts 
 // means "unvisited is always n" (connectivity).
 byo_status selector_pick_device(byo_counters *ctr, const byo_graph *g, int64_t reached_before, int64_t next_level,
                                 bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s);
+// Enqueue the choice for a first level (|U| = k known on the host, sum(deg U)
+// in device memory) and an async copy of it into *h_var (valid after the
+// caller's next stream sync).
+byo_status selector_pick_first(const byo_graph *g, int64_t k, const long long *d_degsum, int64_t unvisited,
+                               bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s, int32_t *h_var);
 
 }  // namespace byo

@@ -234,14 +234,18 @@ static byo_status loss_grad(const float *params, const float *X, const float *Y,
 struct sel_state {
   bool loaded = false;
   int device = -1;
-  float *d_w = nullptr;   // params[P], mu[F], sd[F]
+  float *d_w = nullptr;       // params[P], mu[F], sd[F]
+  int32_t *d_var = nullptr;   // result slot of host-requested predictions
 };
 static sel_state g_sel;
 static std::mutex g_sel_mu;
 
 struct pick_args {
-  // features from counters when ctr != nullptr, else from raw[]
+  // features from counters when ctr != nullptr; else from (k_fixed, *degsum_ptr)
+  // when degsum_ptr != nullptr; else from raw[]
   float raw[F];
+  const long long *degsum_ptr;
+  int64_t k_fixed;
   int64_t n, m, max_deg, reached_before;
   int64_t unvisited_fixed;  // >= 0: use this unvisited count instead of n - reached - k
   double cv;
@@ -258,10 +262,13 @@ __global__ void __launch_bounds__(64) mlp_pick_kernel(const float *__restrict__ 
   if (ctr) {
     k = (int64_t)ctr->count;
     degsum = (int64_t)ctr->degsum;
+  } else if (a.degsum_ptr) {
+    k = a.k_fixed;
+    degsum = (int64_t)*a.degsum_ptr;
   }
   if (t == 0) {
     float f[F];
-    if (ctr) {
+    if (ctr || a.degsum_ptr) {
       int64_t unv = a.unvisited_fixed >= 0 ? a.unvisited_fixed : a.n - a.reached_before - k;
       selector_features((double)k, (double)degsum, (double)(unv > 0 ? unv : 0), (double)a.n, (double)a.m,
                         (double)a.max_deg, a.cv, (double)a.dense_in, f);
@@ -356,18 +363,30 @@ int selector_pick_host(const level_features &f, bool allow_pull, const byo_opts 
   a.m = f.m;
   a.max_deg = f.max_deg;
   a.cv = f.cv;
+  a.unvisited_fixed = -1;
   a.allow_pull = allow_pull ? 1 : 0;
   a.div = o.dense_divisor;
   a.t_wave = o.t_wave;
   a.t_block = o.t_block;
-  int32_t *d_var = nullptr, h_var = -1;
-  if (hipMalloc(&d_var, sizeof(int32_t)) != hipSuccess) return -1;
-  mlp_pick_kernel<<<1, 64, 0, s>>>(g_sel.d_w, nullptr, a, nullptr, d_var);
-  if (hipMemcpyAsync(&h_var, d_var, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  int32_t h_var = -1;
+  mlp_pick_kernel<<<1, 64, 0, s>>>(g_sel.d_w, nullptr, a, nullptr, g_sel.d_var);
+  if (hipMemcpyAsync(&h_var, g_sel.d_var, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     h_var = -1;
-  (void)hipFree(d_var);
   return h_var;
+}
+
+byo_status selector_pick_first(const byo_graph *g, int64_t k, const long long *d_degsum, int64_t unvisited,
+                               bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s, int32_t *h_var) {
+  pick_args a = make_pick(g, o, allow_pull);
+  a.degsum_ptr = d_degsum;
+  a.k_fixed = k;
+  a.unvisited_fixed = unvisited;
+  a.dense_in = dense_in ? 1 : 0;
+  mlp_pick_kernel<<<1, 64, 0, s>>>(g_sel.d_w, nullptr, a, nullptr, g_sel.d_var);
+  BYO_HIP(hipGetLastError());
+  BYO_HIP(hipMemcpyAsync(h_var, g_sel.d_var, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  return BYO_OK;
 }
 
 }  // namespace byo
@@ -447,7 +466,12 @@ byo_status byo_selector_set(const float *h_params, const float *h_mu, const floa
     (void)hipFree(g_sel.d_w);
     g_sel.d_w = nullptr;
   }
+  if (g_sel.d_var && g_sel.device != dev) {
+    (void)hipFree(g_sel.d_var);
+    g_sel.d_var = nullptr;
+  }
   if (!g_sel.d_w) BYO_HIP(hipMalloc(&g_sel.d_w, sizeof(float) * (P + 2 * F)));
+  if (!g_sel.d_var) BYO_HIP(hipMalloc(&g_sel.d_var, sizeof(int32_t) * 4));
   std::vector<float> buf(P + 2 * F);
   std::memcpy(buf.data(), h_params, sizeof(float) * P);
   std::memcpy(buf.data() + P, h_mu, sizeof(float) * F);

@@ -217,7 +217,11 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   BYO_HIP(hipGetLastError());
   long long dsum = 0;
   BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
-  BYO_TRY(sync_read(s, w.scan + ns, &dsum, sizeof(dsum)));
+  bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
+  int32_t first_v = -1;
+  if (use_mlp)
+    BYO_TRY(selector_pick_first(g, ns, w.scan + ns, n - ns, false, true, o, s, &first_v));
+  BYO_TRY(sync_read(s, w.scan + ns, &dsum, sizeof(dsum)));  // also completes the first choice
 
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
@@ -230,8 +234,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   bfs_state bs{d_parent, d_depth, w.visited, 0};
   int32_t level = 0;
-  bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
-  int next_v = -1;
+  int next_v = first_v;
   while (true) {
     if (level >= cap) {
       if (stats) *stats = st;
