@@ -157,6 +157,7 @@ struct byo_workspace {
   int64_t nchunks = -1;
   int32_t pr_dpart_blocks = 0;
   void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
+  void *prseg = nullptr;             // segmented PageRank CSR (pagerank_seg.hip)
 };
 
 struct byo_graph {
@@ -192,6 +193,13 @@ byo_status ws_ensure_traversal(byo_graph *g);
 byo_status ws_ensure_pagerank(byo_graph *g, hipStream_t s);
 void ws_free(byo_workspace &ws);
 void ms_release(byo_workspace &ws);
+// segmented PageRank (pagerank_seg.hip)
+bool pr_seg_wanted(const byo_graph *g);
+byo_status pr_seg_ensure(byo_graph *g, hipStream_t s);
+void pr_seg_release(byo_workspace &w);
+byo_status pr_seg_step(byo_graph *g, const float *contrib, float damping, float *contrib_next, float *out,
+                       int64_t nparts, hipStream_t s, int64_t *nparts_out);
+float *pr_seg_dpart(byo_graph *g);
 
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);

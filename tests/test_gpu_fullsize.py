@@ -1,0 +1,64 @@
+"""Parity at the benchmark's own sizes (RMAT-22, the launch configuration bench.py
+times) and at a mid size where PageRank runs cache-blocked."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11671_amd import gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+byo = pytest.importorskip("paper_2405_11671_amd")
+
+PR_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    p = gen.rmat_pairs(22, 16, seed=1)
+    return p, byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+
+
+def pr_err(a, b):
+    return float(np.max(np.abs(a.astype(np.float64) - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("blocked", [1, 0])
+def test_pagerank_rmat21_blocked_and_plain(blocked):
+    p = gen.rmat_pairs(21, 16, seed=3)
+    g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+    r, _ = byo.pagerank(g, 0.85, 6, pr_blocked=blocked)
+    assert pr_err(r.cpu().numpy(), og.pagerank(0.85, 6)) < PR_TOL
+
+
+def test_pagerank_rmat22_full(rmat22):
+    p, g, og = rmat22
+    r, _ = byo.pagerank(g, 0.85, 20)
+    r64 = og.pagerank(0.85, 20)
+    got = r.cpu().numpy()
+    assert pr_err(got, r64) < PR_TOL
+    assert abs(got.astype(np.float64).sum() - 1.0) < 1e-4
+    r2, _ = byo.pagerank(g, 0.85, 20, pr_blocked=0)
+    assert pr_err(r2.cpu().numpy(), r64) < PR_TOL
+
+
+def test_bfs_cc_rmat22_full(rmat22):
+    p, g, og = rmat22
+    for s in gen.pick_sources(p, 2, seed=2):
+        d, par, _ = byo.bfs(g, int(s))
+        want, _ = og.bfs(int(s))
+        assert np.array_equal(d.cpu().numpy(), want)
+        assert og.check_bfs(int(s), d.cpu().numpy(), par.cpu().numpy()) == 0
+    lab, _ = byo.cc(g)
+    assert np.array_equal(lab.cpu().numpy(), og.cc())
+
+
+def test_msbfs_rmat22_sampled_columns(rmat22):
+    p, g, og = rmat22
+    srcs = gen.pick_sources(p, 256, seed=2)
+    D, st = byo.msbfs(g, srcs)
+    D = D.cpu().numpy()
+    for j in (0, 63, 64, 200, 255):
+        want, _ = og.bfs(int(srcs[j]))
+        assert np.array_equal(D[:, j], np.where(want < 0, 255, want)), j
+    assert st["reached"] == int((D != 255).sum())
