@@ -85,7 +85,7 @@ typedef struct byo_opts {
   int32_t small_frontier; /* frontiers at most this size run in the device-resident
                              single-workgroup loop (0 = off; default 0) */
   int32_t pr_blocked;     /* PageRank: 1 = cache-blocked gather by source segment when the
-                             graph qualifies (default), 0 = single-pass pull */
+                             graph qualifies, 0 = single-pass pull (default) */
   int32_t reserved[7];
 } byo_opts;
 

@@ -203,7 +203,7 @@ void byo_opts_default(byo_opts *o) {
   o->max_levels = 0;
   o->cc_shortcut = 1;
   o->small_frontier = 0;
-  o->pr_blocked = 1;
+  o->pr_blocked = 0;
 }
 
 byo_status byo_csr_from_pairs(const int32_t *src, const int32_t *dst, int64_t npairs, int64_t n, int64_t *off,

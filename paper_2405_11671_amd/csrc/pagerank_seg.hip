@@ -1,19 +1,22 @@
-// Cache-blocked PageRank pull. The gather contrib[u] over u in N(v) is split
-// by source segment: segment s holds the neighbours u with
+// Cache-blocked PageRank pull (option pr_blocked). The gather contrib[u] over
+// u in N(v) is split by source segment: segment s holds the neighbours u with
 // u >> SEG_SHIFT == s, so a pass over segment s reads only a 2 MiB slice of
-// contrib, which stays resident in every XCD's L2. Without the split the
-// 4-byte gathers over the whole array miss L2 and pull whole lines from the
-// fabric (the pull kernel fetched about 12x its compulsory bytes on RMAT-22).
+// contrib, which stays resident in every XCD's L2 (measured on RMAT-22: 94% L2
+// hits against 52% for the single-pass pull). Both versions issue one L2
+// request per gathered edge, and that request rate (about 1.2e11/s measured
+// for either) bounds them, so blocking changes time only by a few percent; it
+// is kept as an option, the single-pass pull is the default.
 //
-// Each segment keeps its own CSR (int32 offsets, int32 neighbours). A pass is
-// launched over row blocks (contiguous rows, at most SEG_ROWS rows and
-// SEG_TILE edges, or one longer row alone); block gathers are staged through
-// LDS and each row is summed in ascending order. Partial sums accumulate over
-// segments in ascending order (acc), and the last pass applies
-// p' = base + d * acc and writes the next contributions, so results are
-// deterministic. Used when the contribution array exceeds one L2 and the
-// segment count stays small (the per-segment offsets cost 4 bytes per vertex
-// per segment per step).
+// Each segment keeps its own CSR (int32 offsets, int32 neighbours). A pass
+// runs one wavefront per 64 rows: rows with at most t_wave entries in the
+// segment are summed by their lane (8 independent gathers per step), longer
+// ones by the whole wavefront, and rows above SEG_LONG entries by a workgroup
+// of their own. Partial sums accumulate over segments in ascending order
+// (acc, touched only where the row has entries in the segment), and the last
+// pass applies p' = base + d * acc and writes the next contributions. Every
+// summation order is fixed, so results are deterministic. Used when the
+// contribution array exceeds one L2 and the segment count stays small (the
+// per-segment offsets cost 4 bytes per vertex per segment per step).
 #include <algorithm>
 #include <vector>
 
@@ -22,9 +25,9 @@
 namespace byo {
 
 constexpr int SEG_SHIFT = 19;     // 2^19 vertices = 2 MiB of FP32 contributions per segment
-constexpr int SEG_TILE = 2048;    // edges staged per row block
-constexpr int SEG_ROWS = 256;     // rows per row block (= threads)
+constexpr int SEG_LONG = 4096;    // segment entries above which a row gets its own workgroup
 constexpr int SEG_BLOCK = 256;
+constexpr int SEG_ILP = 8;
 constexpr int SEG_MAX = 16;       // beyond this the offsets outweigh the saved fetches
 
 struct pr_seg {
@@ -32,11 +35,11 @@ struct pr_seg {
   int64_t n = 0;
   int32_t *seg_off = nullptr;     // [S][n + 1]
   int32_t *seg_nbr = nullptr;     // [m], segment s at [seg_start[s], seg_start[s + 1])
-  int2 *blocks = nullptr;         // row blocks of all segments
+  int32_t *long_rows = nullptr;   // per segment, the rows with more than SEG_LONG entries
   float *acc = nullptr;           // [n]
   float *dpart = nullptr;         // dangling partials (max of init and last-pass block counts)
   std::vector<int64_t> seg_start; // S + 1
-  std::vector<int64_t> blk_start; // S + 1
+  std::vector<int64_t> long_start; // S + 1
   int64_t dpart_cap = 0;
 };
 
@@ -48,7 +51,7 @@ bool pr_seg_wanted(const byo_graph *g) {
 void pr_seg_release(byo_workspace &w) {
   if (!w.prseg) return;
   pr_seg *p = (pr_seg *)w.prseg;
-  void *d[] = {p->seg_off, p->seg_nbr, p->blocks, p->acc, p->dpart};
+  void *d[] = {p->seg_off, p->seg_nbr, p->long_rows, p->acc, p->dpart};
   for (void *x : d)
     if (x) (void)hipFree(x);
   delete p;
@@ -201,33 +204,25 @@ byo_status pr_seg_ensure(byo_graph *g, hipStream_t s) {
   BYO_HIP(hipMemcpyAsync(d_start, p->seg_start.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice, s));
   seg_scatter_kernel<<<gb, 256, 0, s>>>(g->off, g->nbr, n, S, p->seg_off, d_start, p->seg_nbr);
   BYO_HIP(hipGetLastError());
-  // row blocks on the host from the segment offsets
+  // long rows per segment, found on the host from the segment offsets
   std::vector<int32_t> ho((size_t)S * (n + 1));
   BYO_HIP(hipMemcpyAsync(ho.data(), p->seg_off, sizeof(int32_t) * ho.size(), hipMemcpyDeviceToHost, s));
   BYO_HIP(hipStreamSynchronize(s));
   (void)hipFree(d_start);
-  std::vector<int2> blocks;
-  p->blk_start.assign(S + 1, 0);
+  std::vector<int32_t> lr;
+  p->long_start.assign(S + 1, 0);
   for (int k = 0; k < S; ++k) {
     const int32_t *o = ho.data() + (size_t)k * (n + 1);
-    int64_t r = 0;
-    while (r < n) {
-      int64_t r0 = r;
-      int64_t len0 = o[r + 1] - o[r];
-      if (len0 > SEG_TILE) {
-        ++r;
-      } else {
-        while (r < n && r - r0 < SEG_ROWS && (int64_t)(o[r + 1] - o[r0]) <= SEG_TILE) ++r;
-      }
-      blocks.push_back(make_int2((int)r0, (int)r));
-    }
-    p->blk_start[k + 1] = (int64_t)blocks.size();
+    for (int64_t v = 0; v < n; ++v)
+      if (o[v + 1] - o[v] > SEG_LONG) lr.push_back((int32_t)v);
+    p->long_start[k + 1] = (int64_t)lr.size();
   }
-  BYO_HIP(hipMalloc(&p->blocks, sizeof(int2) * blocks.size()));
-  BYO_HIP(hipMemcpy(p->blocks, blocks.data(), sizeof(int2) * blocks.size(), hipMemcpyHostToDevice));
-  int64_t last = p->blk_start[S] - p->blk_start[S - 1];
-  int64_t init_blocks = std::max<int64_t>(1, (w.words + 3) / 4);
-  p->dpart_cap = std::max(last, init_blocks);
+  BYO_HIP(hipMalloc(&p->long_rows, sizeof(int32_t) * std::max<size_t>(lr.size(), 1)));
+  if (!lr.empty())
+    BYO_HIP(hipMemcpy(p->long_rows, lr.data(), sizeof(int32_t) * lr.size(), hipMemcpyHostToDevice));
+  int64_t most_long = 0;
+  for (int k = 0; k < S; ++k) most_long = std::max(most_long, p->long_start[k + 1] - p->long_start[k]);
+  p->dpart_cap = std::max<int64_t>(1, (w.words + 3) / 4) + most_long;
   BYO_HIP(hipMalloc(&p->dpart, sizeof(float) * (size_t)p->dpart_cap));
   return BYO_OK;
 }
@@ -240,25 +235,24 @@ __global__ void __launch_bounds__(SEG_BLOCK) pr_base_kernel(const float *__restr
   if (threadIdx.x == 0) base[0] = (float)((1.0 - damping) / (double)n + damping * t / (double)n);
 }
 
+// Blocks [0, nlong): one long row each. Blocks [nlong, ...): one wavefront per
+// 64 consecutive rows. dpart gets one dangling partial per block (last pass).
 template <bool FIRST, bool LAST>
-__global__ void __launch_bounds__(SEG_BLOCK) pr_seg_kernel(const int2 *__restrict__ blocks,
+__global__ void __launch_bounds__(SEG_BLOCK) pr_seg_kernel(const int32_t *__restrict__ long_rows, int32_t nlong,
                                                            const int32_t *__restrict__ soff,
-                                                           const int32_t *__restrict__ snbr,
+                                                           const int32_t *__restrict__ snbr, int64_t n,
                                                            const float *__restrict__ contrib, float *__restrict__ acc,
                                                            const int32_t *__restrict__ deg,
                                                            const float *__restrict__ base, float damping,
                                                            float *__restrict__ contrib_next, float *__restrict__ out,
-                                                           float *__restrict__ dpart) {
-  __shared__ float s_c[SEG_TILE];
-  const int2 rb = blocks[blockIdx.x];
-  const int64_t r0 = rb.x, r1 = rb.y;
-  const int64_t e0 = soff[r0], e1 = soff[r1];
+                                                           float *__restrict__ dpart, int32_t t_wave) {
   float dang = 0.0f;
-  auto finish = [&](int64_t v, float sum) {
-    float tot = FIRST ? sum : acc[v] + sum;
+  auto finish = [&](int64_t v, float sum, bool has) {
     if (!LAST) {
-      acc[v] = tot;
+      if (FIRST) acc[v] = sum;
+      else if (has) acc[v] += sum;
     } else {
+      float tot = FIRST ? sum : (acc[v] + sum);
       float r = base[0] + damping * tot;
       int32_t d = deg[v];
       if (contrib_next) contrib_next[v] = d > 0 ? r / (float)d : 0.0f;
@@ -266,7 +260,9 @@ __global__ void __launch_bounds__(SEG_BLOCK) pr_seg_kernel(const int2 *__restric
       if (d == 0) dang += r;
     }
   };
-  if (r1 - r0 == 1 && e1 - e0 > SEG_TILE) {
+  if ((int32_t)blockIdx.x < nlong) {
+    int64_t v = long_rows[blockIdx.x];
+    int64_t e0 = soff[v], e1 = soff[v + 1];
     float sum = 0.0f;
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 4 * SEG_BLOCK) {
       float c[4];
@@ -276,17 +272,45 @@ __global__ void __launch_bounds__(SEG_BLOCK) pr_seg_kernel(const int2 *__restric
       for (int j = 0; j < 4; ++j) sum += c[j];
     }
     float t = block_sum<float, SEG_BLOCK>(sum);
-    if (threadIdx.x == 0) finish(r0, t);
+    if (threadIdx.x == 0) finish(v, t, true);
   } else {
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += SEG_BLOCK) s_c[e - e0] = contrib[snbr[e]];
-    __syncthreads();
-    int64_t v = r0 + threadIdx.x;
-    if (v < r1) {
-      int64_t a = soff[v] - e0, b = soff[v + 1] - e0;
-      float sum = 0.0f;
-      for (int64_t i = a; i < b; ++i) sum += s_c[i];
-      finish(v, sum);
+    int64_t lb = xcd_block(blockIdx.x - nlong, gridDim.x - nlong);
+    int64_t v = (lb * (SEG_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE) * 64 + lane_id();
+    bool valid = v < n;
+    int64_t beg = 0, end = 0;
+    float sum = 0.0f;
+    if (valid) {
+      beg = soff[v];
+      end = soff[v + 1];
+      if (end - beg <= t_wave) {
+        for (int64_t e = beg; e < end; e += SEG_ILP) {
+          float c[SEG_ILP];
+#pragma unroll
+          for (int j = 0; j < SEG_ILP; ++j) c[j] = (e + j < end) ? contrib[snbr[e + j]] : 0.0f;
+#pragma unroll
+          for (int j = 0; j < SEG_ILP; ++j) sum += c[j];
+        }
+      }
     }
+    int64_t len = end - beg;
+    uint64_t pm = __ballot(valid && len > t_wave && len <= SEG_LONG);
+    while (pm) {
+      int l = __ffsll((long long)pm) - 1;
+      pm &= pm - 1;
+      int64_t lo = (int64_t)read_lane_u64((uint64_t)beg, l);
+      int64_t hi = (int64_t)read_lane_u64((uint64_t)end, l);
+      float part = 0.0f;
+      for (int64_t e = lo + lane_id(); e < hi; e += 4 * BYO_WAVE) {
+        float c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = (e + j * BYO_WAVE < hi) ? contrib[snbr[e + j * BYO_WAVE]] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part += c[j];
+      }
+      part = wave_sum(part);
+      if (lane_id() == l) sum = part;
+    }
+    if (valid && len <= SEG_LONG) finish(v, sum, len > 0);
   }
   if (LAST) {
     float t = block_sum<float, SEG_BLOCK>(dang);
@@ -296,12 +320,15 @@ __global__ void __launch_bounds__(SEG_BLOCK) pr_seg_kernel(const int2 *__restric
 
 template <bool FIRST, bool LAST>
 static void launch_seg(const pr_seg *p, int k, const float *contrib, const int32_t *deg, const float *base,
-                       float damping, float *contrib_next, float *out, hipStream_t s) {
-  int64_t nb = p->blk_start[k + 1] - p->blk_start[k];
-  if (nb <= 0) return;
+                       float damping, float *contrib_next, float *out, int32_t t_wave, hipStream_t s,
+                       int64_t *nblocks) {
+  int32_t nlong = (int32_t)(p->long_start[k + 1] - p->long_start[k]);
+  int64_t words = (p->n + 63) / 64;
+  int64_t nb = nlong + std::max<int64_t>(1, (words + 3) / 4);
   pr_seg_kernel<FIRST, LAST><<<(unsigned)nb, SEG_BLOCK, 0, s>>>(
-      p->blocks + p->blk_start[k], p->seg_off + (int64_t)k * (p->n + 1), p->seg_nbr + p->seg_start[k], contrib,
-      p->acc, deg, base, damping, contrib_next, out, p->dpart);
+      p->long_rows + p->long_start[k], nlong, p->seg_off + (int64_t)k * (p->n + 1), p->seg_nbr + p->seg_start[k],
+      p->n, contrib, p->acc, deg, base, damping, contrib_next, out, p->dpart, t_wave);
+  *nblocks = nb;
 }
 
 // One PageRank step over the segment passes. dpart holds `nparts` dangling
@@ -312,19 +339,21 @@ byo_status pr_seg_step(byo_graph *g, const float *contrib, float damping, float 
   pr_base_kernel<<<1, SEG_BLOCK, 0, s>>>(p->dpart, nparts, (double)damping, g->n, g->ws.base);
   ktimer_scope kt(BYO_K_PR_PULL, s);
   int S = p->S;
+  int32_t tw = 32;
+  int64_t nb = 0;
   for (int k = 0; k < S; ++k) {
     bool first = k == 0, last = k == S - 1;
     if (first && last)
-      launch_seg<true, true>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, s);
+      launch_seg<true, true>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, tw, s, &nb);
     else if (first)
-      launch_seg<true, false>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, s);
+      launch_seg<true, false>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, tw, s, &nb);
     else if (last)
-      launch_seg<false, true>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, s);
+      launch_seg<false, true>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, tw, s, &nb);
     else
-      launch_seg<false, false>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, s);
+      launch_seg<false, false>(p, k, contrib, g->deg, g->ws.base, damping, contrib_next, out, tw, s, &nb);
   }
   BYO_HIP(hipGetLastError());
-  *nparts_out = p->blk_start[S] - p->blk_start[S - 1];
+  *nparts_out = nb;
   return BYO_OK;
 }
 
