@@ -75,6 +75,48 @@ def cpu_baseline(pairs, srcs, args):
                       f"on the same rmat-{args.scale} graph; {el:.1f} s"}
 
 
+def grid_workload(byo, gen, mlp_opts, side):
+    """Road-like lattice (side x side, 10% of edges deleted): BFS from the corner
+    and connectivity under the threshold heuristic, the learned selector and the
+    device-resident small-frontier loop (median of 3 runs each, ms)."""
+    import torch
+    p = gen.grid_pairs(side, side, 0.1, seed=1)
+    g = byo.Graph.from_pairs(p)
+    depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    label = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t) * 1e3)
+        return float(np.median(ts)), st
+
+    res = {"n": g.n, "m": g.m}
+    cases = {"heuristic": byo.default_opts(), "learned": mlp_opts,
+             "heuristic_device_loop": byo.default_opts(small_frontier=8192),
+             "learned_device_loop": byo.default_opts(selector=byo.SEL_MLP, small_frontier=8192)}
+    for name, o in cases.items():
+        ms, st = timed(lambda: byo.bfs(g, 0, opts=o, depth=depth, parent=parent)[2])
+        res[f"bfs_{name}_ms"] = round(ms, 3)
+        res["bfs_levels"] = st["levels"]
+    res["bfs_gteps_best"] = round(st["edges"] / 2 / (min(v for k, v in res.items() if k.startswith("bfs_") and
+                                                        k.endswith("_ms")) * 1e-3) / 1e9, 4)
+    for name, o in (("heuristic", byo.default_opts()), ("learned", mlp_opts)):
+        ms, st = timed(lambda: byo.cc(g, opts=o, label=label)[1])
+        res[f"cc_{name}_ms"] = round(ms, 3)
+        res["cc_rounds"] = st["levels"]
+    res["learned_vs_heuristic_bfs"] = round(res["bfs_heuristic_ms"] / res["bfs_learned_ms"], 3)
+    res["device_loop_vs_host_loop_bfs"] = round(res["bfs_heuristic_ms"] / res["bfs_heuristic_device_loop_ms"], 3)
+    del g
+    return res
+
+
 def probe_pr(g, n, iters):
     import torch
     import paper_2405_11671_amd as byo
@@ -104,6 +146,8 @@ def parse():
     ap.add_argument("--cpu-sample-pr-iters", type=int, default=6)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--probe", choices=["pr"], default=None)
+    ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--grid-side", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -217,7 +261,9 @@ def main():
         "batched_vs_plain": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9 / float(np.median(plain)),
         "pr_pull_avg_ms": pr_avg_ms, "pr_pull_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
         "kernel_ms": {f: round(v[1] / args.steps, 3) for f, v in kt.items() if v[0]},
+        "grid": grid,
     }
+    grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     traffic = counter_traffic(source_tag(PR_SOURCE))
     achieved = pr_bytes / (pr_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "pr_pull_kernel<0>", "achieved": round(achieved, 2),

@@ -317,6 +317,16 @@ struct level_features {
 };
 int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 
+// device-resident small-frontier BFS levels (smallloop.hip)
+struct small_loop_out {
+  int32_t levels = 0, side = 0;
+  bool empty = false;
+  int64_t count = 0, degsum = 0, reached = 0, edges = 0;
+};
+byo_status bfs_small_loop(byo_graph *g, const int32_t *in_ids, int64_t k, int32_t level, int32_t max_levels,
+                          int32_t cap_count, int64_t cap_edges, int32_t *parent, int32_t *depth, uint64_t *visited,
+                          int32_t *out0, int32_t *out1, void *d_res, hipStream_t s, small_loop_out *out);
+
 // BFS from distinct sources (traverse.hip)
 byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
                    const byo_opts &o, hipStream_t s, byo_run_stats *stats);

@@ -240,6 +240,34 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "BFS level cap reached");
     }
+    if (o.small_frontier > 0 && fr.k <= o.small_frontier && fr.k <= 8192) {
+      // run levels on the device while the frontier stays small
+      BYO_TRY(make_sparse(g, fr, s));
+      small_loop_out r;
+      int32_t budget = (int32_t)std::min<int64_t>(cap - level, 1024);
+      int64_t edge_cap = std::max<int64_t>(16 * (int64_t)o.small_frontier, 65536);
+      BYO_TRY(bfs_small_loop(g, w.ids[fr.cur], fr.k, level, budget, o.small_frontier, edge_cap, d_parent, d_depth,
+                             w.visited, w.ids[1 - fr.cur], w.ids[fr.cur], w.misc, s, &r));
+      level += r.levels;
+      st.device_levels += r.levels;
+      st.variant_count[BYO_V_PUSH_BUCKET] += r.levels;
+      reached += r.reached;
+      edges += r.edges;
+      if (r.empty) break;
+      fr.cur = r.side == 0 ? 1 - fr.cur : fr.cur;
+      fr.sparse = true;
+      fr.dense = false;
+      fr.k = r.count;
+      fr.degsum = r.degsum;
+      next_v = -1;
+      zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);  // ring slots were not advanced on the device
+      BYO_HIP(hipGetLastError());
+      if (level >= cap) {
+        if (stats) *stats = st;
+        return fail(BYO_ELIMIT, "BFS level cap reached");
+      }
+      continue;
+    }
     level_features f = features(g, fr.k, fr.degsum, n - reached, level, fr.dense && !fr.sparse);
     int v = pick(o, f, use_mlp, next_v, s);
     int nxt = 1 - fr.cur;

@@ -232,3 +232,32 @@ def test_bfs_level_cap_and_bad_source():
     with pytest.raises(byo.ByoError) as e:
         byo.bfs(g, 300)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("cap", [1, 64, 1000, 8192])
+@pytest.mark.parametrize("p", SUITE, ids=IDS)
+def test_bfs_device_resident_small_frontier(p, cap):
+    """Levels run inside one workgroup while |U| <= cap; results stay exact."""
+    g, og = build(p)
+    for s in sources(p, og):
+        depth, parent, st = byo.bfs(g, s, small_frontier=cap)
+        want, _ = og.bfs(s)
+        d = depth.cpu().numpy()
+        assert np.array_equal(d, want), (p.name, cap, s)
+        assert og.check_bfs(s, d, parent.cpu().numpy()) == 0
+        assert st["reached"] == int((want >= 0).sum())
+        assert st["levels"] == int(want.max()) + 1 if (want >= 0).sum() > 1 else True
+
+
+def test_small_frontier_runs_on_device_for_lattices():
+    from paper_2405_11671_amd import gen
+    p = gen.grid_pairs(300, 200, 0.1, seed=4)
+    g, og = build(p)
+    depth, _, st = byo.bfs(g, 0, small_frontier=4096)
+    want, _ = og.bfs(0)
+    assert np.array_equal(depth.cpu().numpy(), want)
+    assert st["device_levels"] >= st["levels"] - 2 and st["device_levels"] > 100
+    # the level cap still holds inside the device loop
+    with pytest.raises(byo.ByoError) as e:
+        byo.bfs(g, 0, small_frontier=4096, max_levels=50)
+    assert e.value.status == -4
