@@ -86,7 +86,9 @@ typedef struct byo_opts {
                              single-workgroup loop (0 = off; default 0) */
   int32_t pr_blocked;     /* PageRank: 1 = cache-blocked gather by source segment when the
                              graph qualifies, 0 = single-pass pull (default) */
-  int32_t reserved[7];
+  int32_t use_graph;      /* BFS: 1 = device-side level control replayed from a captured
+                             hipGraph (threshold rule on the device), 0 = host loop (default) */
+  int32_t reserved[6];
 } byo_opts;
 
 /* Per-call statistics (optional out-parameter; pass NULL to skip). */

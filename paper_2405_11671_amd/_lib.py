@@ -33,7 +33,8 @@ class Opts(ctypes.Structure):
                 ("dense_divisor", ctypes.c_int32), ("t_wave", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("cc_shortcut", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
-                ("pr_blocked", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("pr_blocked", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class RunStats(ctypes.Structure):

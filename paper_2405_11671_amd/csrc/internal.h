@@ -158,6 +158,7 @@ struct byo_workspace {
   int32_t pr_dpart_blocks = 0;
   void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
   void *prseg = nullptr;             // segmented PageRank CSR (pagerank_seg.hip)
+  void *gmode = nullptr;             // captured level graph (graphmode.hip)
 };
 
 struct byo_graph {
@@ -326,6 +327,14 @@ struct small_loop_out {
 byo_status bfs_small_loop(byo_graph *g, const int32_t *in_ids, int64_t k, int32_t level, int32_t max_levels,
                           int32_t cap_count, int64_t cap_edges, int32_t *parent, int32_t *depth, uint64_t *visited,
                           int32_t *out0, int32_t *out1, void *d_res, hipStream_t s, small_loop_out *out);
+
+// BFS with device-side level control replayed from a hipGraph (graphmode.hip)
+byo_status bfs_graph_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
+                         const byo_opts &o, hipStream_t s, byo_run_stats *stats);
+void gm_release(byo_workspace &w);
+// parent/depth/visited set up for BFS from d_srcs (distinct), traverse.hip
+byo_status bfs_sources_init(byo_graph *g, const int32_t *d_srcs, int64_t ns, int32_t *parent, int32_t *depth,
+                            hipStream_t s);
 
 // BFS from distinct sources (traverse.hip)
 byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,

@@ -74,7 +74,7 @@ __global__ void bfs_visited_init_kernel(uint64_t *__restrict__ visited, const ui
   for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (int64_t)gridDim.x * blockDim.x) {
     uint64_t x = zero_bits[w];
     if (w == words - 1 && (n & 63)) x |= ~0ull << (n & 63);
-    if (w == (int64_t)(src >> 6)) x |= 1ull << (src & 63);
+    if (src >= 0 && w == (int64_t)(src >> 6)) x |= 1ull << (src & 63);
     visited[w] = x;
   }
 }
@@ -196,6 +196,17 @@ extern "C" {
 }  // extern "C"
 
 namespace byo {
+
+byo_status bfs_sources_init(byo_graph *g, const int32_t *d_srcs, int64_t ns, int32_t *parent, int32_t *depth,
+                            hipStream_t s) {
+  byo_workspace &w = g->ws;
+  bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
+      w.visited, g->zero_bits, g->n, w.words, -1);
+  bfs_visited_sources_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(w.visited, d_srcs, ns);
+  bfs_init_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(parent, depth, d_srcs, ns, w.ids[0], w.ctr);
+  BYO_HIP(hipGetLastError());
+  return BYO_OK;
+}
 
 // BFS from a set of distinct sources (a single source, or one per graph of a
 // batch laid out as a disjoint union).
@@ -324,6 +335,7 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   byo_opts_default(&o);
   if (opts) o = *opts;
   std::vector<int32_t> srcs(1, (int32_t)src);
+  if (o.use_graph) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
   return bfs_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
 }
 

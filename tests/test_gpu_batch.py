@@ -59,3 +59,17 @@ def test_batch_rejects_bad_input():
     B = byo.Batch.from_pairs([graphs.path(10), graphs.path(5)])
     with pytest.raises(byo.ByoError):
         B.bfs([0, 5])                                                         # source outside graph 1
+
+
+def test_batch_graph_mode_matches_eager():
+    plist = gen.batch_pairs(64, seed=3)
+    B = byo.Batch.from_pairs(plist)
+    ogs = [oracle.Graph.from_pairs(p) for p in plist]
+    srcs = [first_non_isolated(og) for og in ogs]
+    for rep in range(3):
+        depth, parent, st = B.bfs(srcs, use_graph=1)
+        D, P = B.split(depth.cpu().numpy()), B.split(parent.cpu().numpy())
+        for i, og in enumerate(ogs):
+            want, _ = og.bfs(srcs[i])
+            assert np.array_equal(D[i], want), (rep, i)
+            assert og.check_bfs(srcs[i], D[i], P[i]) == 0

@@ -261,3 +261,30 @@ def test_small_frontier_runs_on_device_for_lattices():
     with pytest.raises(byo.ByoError) as e:
         byo.bfs(g, 0, small_frontier=4096, max_levels=50)
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("p", SUITE, ids=IDS)
+def test_bfs_graph_mode(p):
+    """Device-side level control replayed from a captured hipGraph; several
+    replays per run on deep graphs, with the eager result as reference."""
+    g, og = build(p)
+    for s in sources(p, og):
+        for rep in range(2):                                  # the cached graph is replayed
+            depth, parent, st = byo.bfs(g, s, use_graph=1)
+            want, _ = og.bfs(s)
+            d = depth.cpu().numpy()
+            assert np.array_equal(d, want), (p.name, s, rep)
+            assert og.check_bfs(s, d, parent.cpu().numpy()) == 0
+            assert st["reached"] == int((want >= 0).sum())
+        d2, _, _ = byo.bfs(g, s)                              # eager run in between
+        assert np.array_equal(d2.cpu().numpy(), want)
+
+
+def test_bfs_graph_mode_level_cap():
+    p = graphs.path(300)
+    g, og = build(p)
+    with pytest.raises(byo.ByoError) as e:
+        byo.bfs(g, 0, use_graph=1, max_levels=40)
+    assert e.value.status == -4
+    d, _, st = byo.bfs(g, 0, use_graph=1)
+    assert np.array_equal(d.cpu().numpy(), og.bfs(0)[0]) and st["levels"] == 300
