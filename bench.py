@@ -117,6 +117,57 @@ def grid_workload(byo, gen, mlp_opts, side):
     return res
 
 
+def batch_workload(byo, gen, count=64):
+    """64 Erdos-Renyi graphs (n log-uniform in [2^10, 2^18], average degree in
+    [4, 32]), BFS from the first non-isolated vertex of each: 64 separate
+    single-source runs against one batched traversal (eager level loop,
+    hipGraph-replayed device-side levels, and autotuned thresholds)."""
+    import tempfile
+    import torch
+    from paper_2405_11671_amd import autotune
+    plist = gen.batch_pairs(count, seed=3)
+    B = byo.Batch.from_pairs(plist)
+    gs = [byo.Graph.from_pairs(p) for p in plist]
+    srcs = []
+    # first non-isolated vertex of each graph, from the host CSR
+    for p in plist:
+        off, _ = byo.csr_from_pairs(p.n, p.src, p.dst)
+        nz = np.flatnonzero(np.diff(off))
+        srcs.append(int(nz[0]) if nz.size else 0)
+
+    def timed(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), st
+
+    def separate():
+        e = 0
+        for g, s_ in zip(gs, srcs):
+            e += byo.bfs(g, s_)[2]["edges"]
+        return {"edges": e}
+
+    res = {"graphs": count, "n": B.n, "m": B.m}
+    t_sep, st = timed(separate)
+    edges = st["edges"] // 2
+    t_eager, _ = timed(lambda: B.bfs(srcs)[2])
+    t_graph, _ = timed(lambda: B.bfs(srcs, use_graph=1)[2])
+    cache = os.path.join(tempfile.gettempdir(), "byo_bench_tune.json")
+    opts, rep = autotune.tune_batch(B, srcs, repeats=2, cache=cache, refresh=True)
+    t_tuned, _ = timed(lambda: B.bfs(srcs, opts=byo.default_opts(**opts))[2])
+    res.update({"separate_ms": round(t_sep * 1e3, 3), "batched_eager_ms": round(t_eager * 1e3, 3),
+                "batched_graph_ms": round(t_graph * 1e3, 3), "batched_tuned_ms": round(t_tuned * 1e3, 3),
+                "tuned_opts": opts, "separate_gteps": round(edges / t_sep / 1e9, 3),
+                "batched_best_gteps": round(edges / min(t_eager, t_graph, t_tuned) / 1e9, 3)})
+    res["batched_vs_separate"] = round(t_sep / min(t_eager, t_graph, t_tuned), 3)
+    return res
+
+
 def probe_pr(g, n, iters):
     import torch
     import paper_2405_11671_amd as byo
@@ -147,6 +198,7 @@ def parse():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--probe", choices=["pr"], default=None)
     ap.add_argument("--no-grid", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--grid-side", type=int, default=4096)
     return ap.parse_args()
 
@@ -250,6 +302,8 @@ def main():
     pr_launches, pr_kms = kt["pr_pull"]
     pr_avg_ms = pr_kms / max(pr_launches, 1)
     pr_bytes = 4 * m + 16 * n + 8          # per launch: neighbours, offsets, contrib read + write
+    grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
+    batch = None if args.no_batch else batch_workload(byo, gen)
     detail = {
         "msbfs_gteps": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9, "msbfs_ms": ms_ms,
         "msbfs_sources": len(ms_srcs), "msbfs_levels": rec[0]["ms_levels"],
@@ -262,8 +316,8 @@ def main():
         "pr_pull_avg_ms": pr_avg_ms, "pr_pull_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
         "kernel_ms": {f: round(v[1] / args.steps, 3) for f, v in kt.items() if v[0]},
         "grid": grid,
+        "batch64": batch,
     }
-    grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     traffic = counter_traffic(source_tag(PR_SOURCE))
     achieved = pr_bytes / (pr_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "pr_pull_kernel<0>", "achieved": round(achieved, 2),

@@ -1,0 +1,125 @@
+"""Autotuner for the traversal's tile and bucket thresholds.
+
+Tunes, per graph signature, the options that change only running time (the
+paper's API study, Section 6.3, shows the map variants change time, never
+results): the wavefront cutoff t_wave, the workgroup cutoff t_block, the
+sparse/dense divisor, the device-resident small-frontier cap and graph mode.
+Coordinate descent from the defaults; each candidate is timed on the device
+(median of `repeats` runs over a few sources). Results are cached in a JSON
+file keyed by a signature of the graph's size and degree distribution.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import _lib
+
+SPACE = {
+    "t_wave": [8, 16, 32, 64, 128],
+    "t_block": [1024, 4096, 16384],
+    "dense_divisor": [8, 14, 20, 32, 64],
+    "small_frontier": [0, 1024, 4096, 8192],
+    "use_graph": [0, 1],
+}
+DEFAULT_CACHE = os.environ.get("BYO_AUTOTUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "byo_autotune.json"))
+
+
+def signature(g, kind: str = "bfs") -> str:
+    st = g.stats()
+    b = lambda x: int(round(math.log2(max(x, 1))))  # noqa: E731
+    return f"{kind}:n2^{b(g.n)}:m2^{b(g.m)}:dmax2^{b(st['max_degree'])}:cv{round(st['cv_degree'], 0):g}"
+
+
+def _time(fn, repeats):
+    import torch
+    fn()
+    ts = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def tune(run, base=None, space=None, repeats=3, rounds=2, log=None):
+    """Coordinate descent: run(opts) executes the workload once. Returns (opts dict, report)."""
+    space = space or SPACE
+    cur = dict(base or {k: getattr(_lib.default_opts(), k) for k in space})
+    best_t = _time(lambda: run(_lib.default_opts(**cur)), repeats)
+    start_t = best_t
+    trials = [(dict(cur), best_t)]
+    for _ in range(rounds):
+        improved = False
+        for key, values in space.items():
+            for v in values:
+                if v == cur[key]:
+                    continue
+                cand = dict(cur, **{key: v})
+                t = _time(lambda: run(_lib.default_opts(**cand)), repeats)
+                trials.append((cand, t))
+                if log:
+                    log(f"[autotune] {key}={v}: {t * 1e3:.3f} ms")
+                if t < best_t * 0.98:
+                    best_t, cur, improved = t, cand, True
+        if not improved:
+            break
+    return cur, {"default_ms": start_t * 1e3, "tuned_ms": best_t * 1e3, "trials": len(trials)}
+
+
+def tune_bfs(g, sources, repeats=3, cache=DEFAULT_CACHE, refresh=False, log=None):
+    """Tuned options (dict) for single-source BFS on g over the given sources."""
+    from . import bfs
+    key = signature(g, "bfs")
+    db = _load(cache)
+    if key in db and not refresh:
+        return db[key]["opts"], db[key]["report"]
+
+    def run(o):
+        for s in sources:
+            bfs(g, int(s), opts=o)
+
+    opts, rep = tune(run, repeats=repeats, log=log)
+    db[key] = {"opts": opts, "report": rep}
+    _save(cache, db)
+    return opts, rep
+
+
+def tune_batch(batch, sources, repeats=3, cache=DEFAULT_CACHE, refresh=False, log=None):
+    """Tuned options for batched BFS (one source per graph)."""
+    key = f"batch:{batch.count}:n{batch.n}:m{batch.m}"
+    db = _load(cache)
+    if key in db and not refresh:
+        return db[key]["opts"], db[key]["report"]
+    space = {k: v for k, v in SPACE.items() if k != "small_frontier"}
+    opts, rep = tune(lambda o: batch.bfs(sources, opts=o), space=space, repeats=repeats, log=log)
+    db[key] = {"opts": opts, "report": rep}
+    _save(cache, db)
+    return opts, rep
+
+
+def _load(path):
+    if path and os.path.exists(path):
+        try:
+            with open(path) as f:
+                return json.load(f)
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def _save(path, db):
+    if not path:
+        return
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1)
+    os.replace(tmp, path)
