@@ -67,7 +67,9 @@ byo_status byo_selector_clear(void);
 byo_status byo_selector_loaded(int32_t *out);
 /* Predict with the installed weights on the device: raw features in,
  * per-variant predictions out (nullable) and the chosen variant (pull variants
- * excluded unless allow_pull). BYO_ESTATE if no weights are installed. Syncs. */
+ * excluded unless allow_pull; -1 if a prediction is not finite). BYO_ESTATE if
+ * no weights are installed. Syncs. Traversals with BYO_SEL_MLP make the same
+ * float computation on the host, from the level counters they read back. */
 byo_status byo_selector_predict(const float *h_features, int32_t allow_pull, float *h_pred, int32_t *variant);
 
 /* Timing collection for training: run BFS from src (algo BYO_ALGO_BFS) or

@@ -342,17 +342,9 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 // learned selector (selector.hip)
 bool selector_ready();
-// Host-side prediction for one level (one launch + sync); -1 if not ready.
-int selector_pick_host(const level_features &f, bool allow_pull, const byo_opts &o, hipStream_t s);
-// Enqueue the on-device choice for the level after `ctr`'s level: features
-// from ctr->count / ctr->degsum, result written to ctr->aux1. reached_before < 0
-// means "unvisited is always n" (connectivity).
-byo_status selector_pick_device(byo_counters *ctr, const byo_graph *g, int64_t reached_before, int64_t next_level,
-                                bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s);
-// Enqueue the choice for a first level (|U| = k known on the host, sum(deg U)
-// in device memory) and an async copy of it into *h_var (valid after the
-// caller's next stream sync).
-byo_status selector_pick_first(const byo_graph *g, int64_t k, const long long *d_degsum, int64_t unvisited,
-                               bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s, int32_t *h_var);
+// Learned choice for one level, computed on the host from the level's
+// features (the host-driven loop holds them already); -1 if no weights are
+// installed or the prediction is not finite.
+int selector_pick_cpu(const level_features &f, bool allow_pull);
 
 }  // namespace byo

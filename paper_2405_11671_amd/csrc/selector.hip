@@ -235,48 +235,23 @@ struct sel_state {
   bool loaded = false;
   int device = -1;
   float *d_w = nullptr;       // params[P], mu[F], sd[F]
-  int32_t *d_var = nullptr;   // result slot of host-requested predictions
+  std::vector<float> h_w;     // host copy of d_w for the host-driven level loop
 };
 static sel_state g_sel;
 static std::mutex g_sel_mu;
 
 struct pick_args {
-  // features from counters when ctr != nullptr; else from (k_fixed, *degsum_ptr)
-  // when degsum_ptr != nullptr; else from raw[]
   float raw[F];
-  const long long *degsum_ptr;
-  int64_t k_fixed;
-  int64_t n, m, max_deg, reached_before;
-  int64_t unvisited_fixed;  // >= 0: use this unvisited count instead of n - reached - k
-  double cv;
-  int32_t dense_in, allow_pull, div, t_wave, t_block;
+  int32_t allow_pull;
 };
 
-// One block of 64 threads: features -> normalise -> MLP -> argmin over allowed
-// variants; non-finite predictions fall back to the threshold rule.
-__global__ void __launch_bounds__(64) mlp_pick_kernel(const float *__restrict__ wts, byo_counters *ctr, pick_args a,
+// One block of 64 threads: normalise -> MLP -> argmin over the allowed
+// variants; -1 if any prediction is not finite.
+__global__ void __launch_bounds__(64) mlp_pick_kernel(const float *__restrict__ wts, pick_args a,
                                                       float *__restrict__ pred_out, int32_t *__restrict__ var_out) {
   __shared__ float x[F], h1[H], h2[H], o[K];
   int t = threadIdx.x;
-  int64_t k = 0, degsum = 0;
-  if (ctr) {
-    k = (int64_t)ctr->count;
-    degsum = (int64_t)ctr->degsum;
-  } else if (a.degsum_ptr) {
-    k = a.k_fixed;
-    degsum = (int64_t)*a.degsum_ptr;
-  }
-  if (t == 0) {
-    float f[F];
-    if (ctr || a.degsum_ptr) {
-      int64_t unv = a.unvisited_fixed >= 0 ? a.unvisited_fixed : a.n - a.reached_before - k;
-      selector_features((double)k, (double)degsum, (double)(unv > 0 ? unv : 0), (double)a.n, (double)a.m,
-                        (double)a.max_deg, a.cv, (double)a.dense_in, f);
-    } else {
-      for (int i = 0; i < F; ++i) f[i] = a.raw[i];
-    }
-    for (int i = 0; i < F; ++i) x[i] = (f[i] - wts[P + i]) / wts[P + F + i];
-  }
+  if (t < F) x[t] = (a.raw[t] - wts[P + t]) / wts[P + F + t];
   __syncthreads();
   if (t < H) {
     float z = wts[OFF_B1 + t];
@@ -294,28 +269,21 @@ __global__ void __launch_bounds__(64) mlp_pick_kernel(const float *__restrict__ 
     float z = wts[OFF_B3 + t];
     for (int i = 0; i < H; ++i) z += h2[i] * wts[OFF_W3 + i * K + t];
     o[t] = z;
-    if (pred_out) pred_out[t] = z;
+    pred_out[t] = z;
   }
   __syncthreads();
   if (t == 0) {
     int best = -1;
-    float bv = 0.f;
     for (int v = 0; v < K; ++v) {
-      bool pull = v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE;
-      if (pull && !a.allow_pull) continue;
       if (!isfinite(o[v])) {
-        best = -2;
+        best = -1;
         break;
       }
-      if (best == -1 || o[v] < bv) {
-        best = v;
-        bv = o[v];
-      }
+      bool pull = v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE;
+      if (pull && !a.allow_pull) continue;
+      if (best < 0 || o[v] < o[best]) best = v;
     }
-    if (best < 0)
-      best = heuristic_rule(k, degsum, a.m, a.max_deg, a.cv, a.div, a.t_wave, a.t_block, a.allow_pull != 0);
-    if (ctr) ctr->aux1 = (unsigned long long)best;
-    if (var_out) *var_out = best;
+    *var_out = best;
   }
 }
 
@@ -326,67 +294,41 @@ bool selector_ready() {
   return dev == g_sel.device;
 }
 
-static pick_args make_pick(const byo_graph *g, const byo_opts &o, bool allow_pull) {
-  pick_args a;
-  std::memset(&a, 0, sizeof(a));
-  a.unvisited_fixed = -1;
-  a.n = g->n;
-  a.m = g->m;
-  a.max_deg = g->max_deg;
-  a.cv = g->cv_deg;
-  a.allow_pull = allow_pull ? 1 : 0;
-  a.div = o.dense_divisor;
-  a.t_wave = o.t_wave;
-  a.t_block = o.t_block;
-  return a;
-}
-
-byo_status selector_pick_device(byo_counters *ctr, const byo_graph *g, int64_t reached_before, int64_t next_level,
-                                bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s) {
-  (void)next_level;
-  pick_args a = make_pick(g, o, allow_pull);
-  a.reached_before = reached_before < 0 ? 0 : reached_before;
-  a.unvisited_fixed = reached_before < 0 ? g->n : -1;
-  a.dense_in = dense_in ? 1 : 0;
-  mlp_pick_kernel<<<1, 64, 0, s>>>(g_sel.d_w, ctr, a, nullptr, nullptr);
-  BYO_HIP(hipGetLastError());
-  return BYO_OK;
-}
-
-int selector_pick_host(const level_features &f, bool allow_pull, const byo_opts &o, hipStream_t s) {
+// The host-driven level loop reads each level's counters anyway, so the
+// learned choice for the next level is made there: the same float network and
+// fallback as mlp_pick_kernel, a few thousand multiply-adds, no launch and no
+// extra round trip. Returns -1 when no weights are installed or the
+// prediction is not finite (the caller then applies the threshold rule).
+int selector_pick_cpu(const level_features &f, bool allow_pull) {
   if (!selector_ready()) return -1;
-  pick_args a;
-  std::memset(&a, 0, sizeof(a));
+  const float *w = g_sel.h_w.data();
+  float raw[F], x[F], h1[H], h2[H], o[K];
   selector_features((double)f.k, (double)f.degsum, (double)f.unvisited, (double)f.n, (double)f.m, (double)f.max_deg,
-                    f.cv, f.dense_in ? 1.0 : 0.0, a.raw);
-  a.n = f.n;
-  a.m = f.m;
-  a.max_deg = f.max_deg;
-  a.cv = f.cv;
-  a.unvisited_fixed = -1;
-  a.allow_pull = allow_pull ? 1 : 0;
-  a.div = o.dense_divisor;
-  a.t_wave = o.t_wave;
-  a.t_block = o.t_block;
-  int32_t h_var = -1;
-  mlp_pick_kernel<<<1, 64, 0, s>>>(g_sel.d_w, nullptr, a, nullptr, g_sel.d_var);
-  if (hipMemcpyAsync(&h_var, g_sel.d_var, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    h_var = -1;
-  return h_var;
-}
-
-byo_status selector_pick_first(const byo_graph *g, int64_t k, const long long *d_degsum, int64_t unvisited,
-                               bool dense_in, bool allow_pull, const byo_opts &o, hipStream_t s, int32_t *h_var) {
-  pick_args a = make_pick(g, o, allow_pull);
-  a.degsum_ptr = d_degsum;
-  a.k_fixed = k;
-  a.unvisited_fixed = unvisited;
-  a.dense_in = dense_in ? 1 : 0;
-  mlp_pick_kernel<<<1, 64, 0, s>>>(g_sel.d_w, nullptr, a, nullptr, g_sel.d_var);
-  BYO_HIP(hipGetLastError());
-  BYO_HIP(hipMemcpyAsync(h_var, g_sel.d_var, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  return BYO_OK;
+                    f.cv, f.dense_in ? 1.0 : 0.0, raw);
+  for (int i = 0; i < F; ++i) x[i] = (raw[i] - w[P + i]) / w[P + F + i];
+  for (int j = 0; j < H; ++j) {
+    float z = w[OFF_B1 + j];
+    for (int i = 0; i < F; ++i) z += x[i] * w[OFF_W1 + i * H + j];
+    h1[j] = z > 0.f ? z : 0.f;
+  }
+  for (int j = 0; j < H; ++j) {
+    float z = w[OFF_B2 + j];
+    for (int i = 0; i < H; ++i) z += h1[i] * w[OFF_W2 + i * H + j];
+    h2[j] = z > 0.f ? z : 0.f;
+  }
+  int best = -1;
+  for (int k = 0; k < K; ++k) {
+    float z = w[OFF_B3 + k];
+    for (int i = 0; i < H; ++i) z += h2[i] * w[OFF_W3 + i * K + k];
+    o[k] = z;
+    if (!std::isfinite(z)) return -1;
+  }
+  for (int v = 0; v < K; ++v) {
+    bool pull = v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE;
+    if (pull && !allow_pull) continue;
+    if (best < 0 || o[v] < o[best]) best = v;
+  }
+  return best;
 }
 
 }  // namespace byo
@@ -466,17 +408,13 @@ byo_status byo_selector_set(const float *h_params, const float *h_mu, const floa
     (void)hipFree(g_sel.d_w);
     g_sel.d_w = nullptr;
   }
-  if (g_sel.d_var && g_sel.device != dev) {
-    (void)hipFree(g_sel.d_var);
-    g_sel.d_var = nullptr;
-  }
   if (!g_sel.d_w) BYO_HIP(hipMalloc(&g_sel.d_w, sizeof(float) * (P + 2 * F)));
-  if (!g_sel.d_var) BYO_HIP(hipMalloc(&g_sel.d_var, sizeof(int32_t) * 4));
   std::vector<float> buf(P + 2 * F);
   std::memcpy(buf.data(), h_params, sizeof(float) * P);
   std::memcpy(buf.data() + P, h_mu, sizeof(float) * F);
   std::memcpy(buf.data() + P + F, h_sd, sizeof(float) * F);
   BYO_HIP(hipMemcpy(g_sel.d_w, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice));
+  g_sel.h_w = buf;
   g_sel.device = dev;
   g_sel.loaded = true;
   return BYO_OK;
@@ -501,12 +439,11 @@ byo_status byo_selector_predict(const float *h_features, int32_t allow_pull, flo
   std::memset(&a, 0, sizeof(a));
   std::memcpy(a.raw, h_features, sizeof(float) * F);
   a.allow_pull = allow_pull ? 1 : 0;
-  a.m = 1;
   float *d_pred = nullptr;
   int32_t *d_var = nullptr;
   BYO_HIP(hipMalloc(&d_pred, sizeof(float) * K));
   BYO_HIP(hipMalloc(&d_var, sizeof(int32_t)));
-  mlp_pick_kernel<<<1, 64, 0, nullptr>>>(g_sel.d_w, nullptr, a, d_pred, d_var);
+  mlp_pick_kernel<<<1, 64, 0, nullptr>>>(g_sel.d_w, a, d_pred, d_var);
   hipError_t e = hipGetLastError();
   float pred[K];
   int32_t v = -1;

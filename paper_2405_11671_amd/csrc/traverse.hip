@@ -31,12 +31,11 @@ int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) 
   return heuristic_variant(o, f, allow_pull);
 }
 
-// Variant for this level: the learned selector's on-device choice made after
-// the previous level (or one host-launched prediction for the first level),
-// else the fixed / threshold rule.
-static int pick(const byo_opts &o, const level_features &f, bool use_mlp, int next_v, hipStream_t s) {
+// Variant for this level: the learned selector's choice from this level's
+// features, else the fixed / threshold rule.
+static int pick(const byo_opts &o, const level_features &f, bool use_mlp) {
   if (use_mlp) {
-    int v = (next_v >= 0 && next_v < BYO_NUM_VARIANTS) ? next_v : selector_pick_host(f, true, o, s);
+    int v = selector_pick_cpu(f, true);
     if (v >= 0 && v < BYO_NUM_VARIANTS) return v;
   }
   return choose_variant(o, f, true);
@@ -229,10 +228,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   long long dsum = 0;
   BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
   bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
-  int32_t first_v = -1;
-  if (use_mlp)
-    BYO_TRY(selector_pick_first(g, ns, w.scan + ns, n - ns, false, true, o, s, &first_v));
-  BYO_TRY(sync_read(s, w.scan + ns, &dsum, sizeof(dsum)));  // also completes the first choice
+  BYO_TRY(sync_read(s, w.scan + ns, &dsum, sizeof(dsum)));
 
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
@@ -245,7 +241,6 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   bfs_state bs{d_parent, d_depth, w.visited, 0};
   int32_t level = 0;
-  int next_v = first_v;
   while (true) {
     if (level >= cap) {
       if (stats) *stats = st;
@@ -270,7 +265,6 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
       fr.dense = false;
       fr.k = r.count;
       fr.degsum = r.degsum;
-      next_v = -1;
       zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);  // ring slots were not advanced on the device
       BYO_HIP(hipGetLastError());
       if (level >= cap) {
@@ -280,7 +274,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
       continue;
     }
     level_features f = features(g, fr.k, fr.degsum, n - reached, level, fr.dense && !fr.sparse);
-    int v = pick(o, f, use_mlp, next_v, s);
+    int v = pick(o, f, use_mlp);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -300,11 +294,9 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     bs.level = level;
     BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
     lt.stop();
-    if (use_mlp) BYO_TRY(selector_pick_device(io.ctr, g, reached, level + 1, is_pull(v), true, o, s));
     st.variant_count[v]++;
     byo_counters c;
     BYO_TRY(read_slot(g, level % BYO_COUNTER_SLOTS, s, &c));
-    next_v = use_mlp ? (int)c.aux1 : -1;
     lt.record(BYO_ALGO_BFS, g, f, v, (int64_t)c.count, (int64_t)c.degsum);
     ++level;
     if (c.count == 0) break;
@@ -373,14 +365,13 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   int32_t round = 0;
   bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
-  int next_v = -1;
   while (true) {
     if (round >= cap) {
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "connectivity round cap reached");
     }
     level_features f = features(g, fr.k, fr.degsum, n, round, fr.dense && !fr.sparse);
-    int v = pick(o, f, use_mlp, next_v, s);
+    int v = pick(o, f, use_mlp);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -401,11 +392,9 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
     if (shortcut) BYO_TRY(cc_shortcut(g, d_label, w.bits[nxt], io.ctr, s));
     lt.stop();
-    if (use_mlp) BYO_TRY(selector_pick_device(io.ctr, g, -1, round + 1, is_pull(v) || shortcut, true, o, s));
     st.variant_count[v]++;
     byo_counters c;
     BYO_TRY(read_slot(g, round % BYO_COUNTER_SLOTS, s, &c));
-    next_v = use_mlp ? (int)c.aux1 : -1;
     lt.record(BYO_ALGO_CC, g, f, v, (int64_t)c.count, (int64_t)c.degsum);
     ++round;
     if (c.count == 0) break;

@@ -209,3 +209,30 @@ def test_trained_selector_gain_on_heldout_graphs(capsys):
         assert np.array_equal(d.cpu().numpy(), og.bfs(1)[0])
     finally:
         sel.clear()
+
+
+def test_traversal_choices_match_device_prediction():
+    """The host-side choice made inside BFS / CC equals the device predictor's
+    argmin on the recorded level features (levels with a clear margin)."""
+    params, mu, sd, _ = sel.load_weights(os.path.join(ROOT, "paper_2405_11671_amd", "selector_weights.json"))
+    sel.install(params, mu, sd)
+    byo.trace_enable(True)
+    try:
+        byo.trace_read()
+        for p in (gen.rmat_pairs(15, 16, seed=4), gen.grid_pairs(64, 64, 0.1, seed=4)):
+            g = byo.Graph.from_pairs(p)
+            byo.bfs(g, int(gen.pick_sources(p, 1, seed=9)[0]), selector=byo.SEL_MLP)
+            byo.cc(g, selector=byo.SEL_MLP)
+            recs = byo.trace_read()
+            assert recs
+            checked = 0
+            for r in recs:
+                pred, v = sel.predict(sel.features(r))
+                order = np.sort(pred)
+                if order[1] - order[0] > 1e-3:
+                    assert r["variant"] == v, (p.n, r["algo"], r["level"])
+                    checked += 1
+            assert checked >= len(recs) // 2
+    finally:
+        byo.trace_enable(False)
+        sel.clear()
