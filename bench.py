@@ -7,6 +7,9 @@ conventions:
   BFS: undirected edges in the reached component, summed over sources (Graph500),
   PageRank: iterations x m directed edges, connectivity: m/2 undirected edges.
 value = all traversed edges of the timed steps / their wall time.
+PageRank and the multi-source BFS run over the degree-ordered tile layout,
+built once per graph on first use and kept with it like the CSR (its build
+time is reported in "detail"; `--no-tiles` runs them over the CSR instead).
 Single-source BFS from 16 sources is timed separately, with the threshold
 heuristic ("plain") and with the learned selector, and reported in "detail"
 next to the batched rate.
@@ -29,7 +32,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
-PR_SOURCE = os.path.join(ROOT, "paper_2405_11671_amd", "csrc", "pagerank.hip")
+PR_SOURCE = os.path.join(ROOT, "paper_2405_11671_amd", "csrc", "pagerank_tile.hip")
+PR_KERNELS = "pr_tile_kernel<12> + pr_tile_apply_kernel<12> (one PageRank step)"
 
 
 def source_tag(path):
@@ -39,9 +43,9 @@ def source_tag(path):
 
 
 def counter_traffic(kernel_tag):
-    """HBM bytes per launch of the PageRank pull kernel from the committed
+    """HBM bytes per PageRank step (both tile kernels) from the committed
     counter summary, or None when it is missing or was taken on other source."""
-    path = os.path.join(PROFILES, "pr_pull_rmat22_counters.md")
+    path = os.path.join(PROFILES, "pr_tile_rmat22_counters.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -49,10 +53,10 @@ def counter_traffic(kernel_tag):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("pagerank.hip sha256[:12]") != kernel_tag:
+    if vals.get("pagerank_tile.hip sha256[:12]") != kernel_tag:
         return None
     try:
-        return float(vals["scaled HBM bytes per launch"])
+        return float(vals["scaled HBM bytes per step"])
     except (KeyError, ValueError):
         return None
 
@@ -172,7 +176,9 @@ def probe_pr(g, n, iters):
     import torch
     import paper_2405_11671_amd as byo
     rank = torch.empty(n, dtype=torch.float32, device="cuda")
-    byo.pagerank(g, 0.85, iters, rank=rank)
+    byo.pagerank(g, 0.85, 1, rank=rank, pr_blocked=1)    # builds the tile layout
+    torch.cuda.synchronize()
+    byo.pagerank(g, 0.85, iters, rank=rank, pr_blocked=1)
     # calibration: an elementwise kernel that reads 512 MiB and writes 512 MiB
     a = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -200,6 +206,8 @@ def parse():
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--grid-side", type=int, default=4096)
+    ap.add_argument("--no-tiles", action="store_true",
+                    help="PageRank and multi-source BFS over the CSR instead of the tile layout")
     return ap.parse_args()
 
 
@@ -233,6 +241,7 @@ def main():
     label = torch.empty(n, dtype=torch.int32, device="cuda")
     rank = torch.empty(n, dtype=torch.float32, device="cuda")
     opts = byo.default_opts()
+    tiled = byo.default_opts(pr_blocked=0 if args.no_tiles else 1, ms_tiled=0 if args.no_tiles else 1)
     from paper_2405_11671_amd import selector as sel
     wpath = os.path.join(ROOT, "paper_2405_11671_amd", "selector_weights.json")
     params, mu, sd, _ = sel.load_weights(wpath)
@@ -245,9 +254,9 @@ def main():
     def step(record=None):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         ev[0].record()
-        _, mst = byo.msbfs(g, ms_srcs, opts=opts, depth=ms_depth)
+        _, mst = byo.msbfs(g, ms_srcs, opts=tiled, depth=ms_depth)
         ev[1].record()
-        byo.pagerank(g, 0.85, args.pr_iters, opts=opts, rank=rank)
+        byo.pagerank(g, 0.85, args.pr_iters, opts=tiled, rank=rank)
         ev[2].record()
         _, cst = byo.cc(g, opts=mlp_opts, label=label)
         ev[3].record()
@@ -275,6 +284,13 @@ def main():
     def learned_bfs():
         return single_bfs(mlp_opts)
 
+    # the degree-ordered tile layout is built once per graph, on first use,
+    # and kept with it (like the CSR); its build time is reported, not timed
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    byo.pagerank(g, 0.85, 1, opts=tiled, rank=rank)
+    torch.cuda.synchronize()
+    layout_s = time.perf_counter() - t
     for _ in range(args.warmup):
         step()
         plain_bfs()
@@ -300,8 +316,8 @@ def main():
     pr_ms = float(np.median([r["pr_ms"] for r in rec]))
     cc_ms = float(np.median([r["cc_ms"] for r in rec]))
     pr_launches, pr_kms = kt["pr_pull"]
-    pr_avg_ms = pr_kms / max(pr_launches, 1)
-    pr_bytes = 4 * m + 16 * n + 8          # per launch: neighbours, offsets, contrib read + write
+    pr_avg_ms = (pr_kms + kt["pr_chunk"][1]) / max(pr_launches, 1)   # tile kernel + apply kernel per step
+    pr_bytes = 4 * m + 16 * n + 8          # per step: neighbours, offsets, contrib read + write, rank write
     grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     batch = None if args.no_batch else batch_workload(byo, gen)
     detail = {
@@ -313,14 +329,16 @@ def main():
         "learned_bfs_gteps": float(np.median(learned)),
         "learned_vs_plain": float(np.median(learned)) / float(np.median(plain)),
         "batched_vs_plain": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9 / float(np.median(plain)),
-        "pr_pull_avg_ms": pr_avg_ms, "pr_pull_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
+        "pr_step_avg_ms": pr_avg_ms, "pr_step_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
+        "tile_layout_build_s": layout_s, "tiled": not args.no_tiles,
         "kernel_ms": {f: round(v[1] / args.steps, 3) for f, v in kt.items() if v[0]},
         "grid": grid,
         "batch64": batch,
     }
-    traffic = counter_traffic(source_tag(PR_SOURCE))
+    traffic = counter_traffic(source_tag(PR_SOURCE)) if not args.no_tiles else None
     achieved = pr_bytes / (pr_avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "pr_pull_kernel<0>", "achieved": round(achieved, 2),
+    roofline = {"bound": "hbm", "kernel": PR_KERNELS if not args.no_tiles else "pr_chunk_kernel + pr_pull_kernel<0>",
+                "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / (pr_avg_ms * 1e-3) / 1e9, 2),
                 "alg_bytes_per_launch": pr_bytes, "avg_launch_ms": round(pr_avg_ms, 4),

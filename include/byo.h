@@ -84,11 +84,20 @@ typedef struct byo_opts {
   int32_t cc_shortcut;    /* CC: pointer-jumping pass after each round (default 1) */
   int32_t small_frontier; /* frontiers at most this size run in the device-resident
                              single-workgroup loop (0 = off; default 0) */
-  int32_t pr_blocked;     /* PageRank: 1 = cache-blocked gather by source segment when the
-                             graph qualifies, 0 = single-pass pull (default) */
+  int32_t pr_blocked;     /* PageRank layout: 0 = pull over the CSR (default); 1 = entries
+                             regrouped by destination tile of 2^14 degree-ordered vertices,
+                             exact fixed-point sums in LDS; 12..14 = tiles of 2^value.
+                             The tiled layout is used when n >= 2^16 and m >= 4n (else the
+                             pull); it is built on the host on first use (about 6 bytes per
+                             entry plus 8 per vertex of device memory) and kept with the
+                             graph. */
   int32_t use_graph;      /* BFS: 1 = device-side level control replayed from a captured
                              hipGraph (threshold rule on the device), 0 = host loop (default) */
-  int32_t reserved[6];
+  int32_t ms_tiled;       /* multi-source BFS: 1 = every level over the degree-ordered tile
+                             layout (the one PageRank's pr_blocked uses, tiles of 2^12)
+                             when n >= 2^16 and m >= 4n; 0 = push/pull over the CSR
+                             (default) */
+  int32_t reserved[5];
 } byo_opts;
 
 /* Per-call statistics (optional out-parameter; pass NULL to skip). */

@@ -133,6 +133,10 @@ struct byo_counters {
 };
 #define BYO_COUNTER_SLOTS 4
 
+namespace byo {
+struct byo_tiles;
+}
+
 struct byo_workspace {
   int64_t n = 0;
   int64_t words = 0;
@@ -157,7 +161,7 @@ struct byo_workspace {
   int64_t nchunks = -1;
   int32_t pr_dpart_blocks = 0;
   void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
-  void *prseg = nullptr;             // segmented PageRank CSR (pagerank_seg.hip)
+  byo::byo_tiles *tiles = nullptr;   // degree-ordered destination-tile layout (tiles.hip)
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
 };
 
@@ -194,13 +198,34 @@ byo_status ws_ensure_traversal(byo_graph *g);
 byo_status ws_ensure_pagerank(byo_graph *g, hipStream_t s);
 void ws_free(byo_workspace &ws);
 void ms_release(byo_workspace &ws);
-// segmented PageRank (pagerank_seg.hip)
-bool pr_seg_wanted(const byo_graph *g);
-byo_status pr_seg_ensure(byo_graph *g, hipStream_t s);
-void pr_seg_release(byo_workspace &w);
-byo_status pr_seg_step(byo_graph *g, const float *contrib, float damping, float *contrib_next, float *out,
-                       int64_t nparts, hipStream_t s, int64_t *nparts_out);
-float *pr_seg_dpart(byo_graph *g);
+// Degree-ordered destination-tile layout (tiles.hip): vertices relabelled by
+// descending degree; entries grouped by tile of 2^shift relabelled
+// destinations, ascending relabelled source inside a tile; tiles cut into
+// chunks of about equal size.
+constexpr int BYO_TILE_SHIFT = 12;
+struct byo_tiles {
+  int shift = 0;
+  int64_t n = 0, m = 0, nblk = 0, nchunks = 0;
+  int32_t *esrc = nullptr;    // [m] relabelled source of each entry
+  uint16_t *edst = nullptr;   // [m] relabelled destination minus its tile's first vertex
+  int32_t *rdeg = nullptr;    // [n] degree by relabelled vertex
+  int32_t *orig = nullptr;    // [n] original ID of each relabelled vertex
+  int64_t *cbeg = nullptr;    // [nchunks + 1] entry range of each chunk (never straddles tiles)
+  int32_t *bfirst = nullptr;  // [nblk + 1] first chunk of each tile
+  int32_t *cblk = nullptr;    // [nchunks] tile of each chunk
+  uint32_t *cflag = nullptr;  // [nchunks] per-level "chunk produced something" flags
+  void *partial = nullptr;    // chunk results, sized by the user (tiles_partial)
+  size_t partial_bytes = 0;
+  std::vector<int32_t> h_label;  // relabelled ID of each original vertex (host copy)
+};
+bool tiles_wanted(const byo_graph *g);  // n >= 2^16 and m >= 4n
+byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s);
+byo_status tiles_partial(byo_tiles *t, size_t bytes_per_chunk);
+void tiles_release(byo_workspace &w);
+// tiled PageRank step (pagerank_tile.hip); opt = byo_opts::pr_blocked
+int pr_tile_shift(int32_t opt);
+byo_status pr_tile_step(byo_graph *g, const float *contrib, float damping, float *contrib_next, float *out,
+                        hipStream_t s);
 
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);

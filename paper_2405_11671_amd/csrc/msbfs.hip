@@ -19,15 +19,63 @@ namespace byo {
 constexpr int MS_BLOCK = 256;
 constexpr int MS_ILP = 4;
 
+// Depth bytes of the sources newly seen by v (bits of nb; sv = the sources
+// seen before). When rows are 16-byte aligned (k a multiple of 16) each group
+// of 16 sources with a new bit is one 16-byte store: built from 255 (the
+// fill) when no source of the group was seen before, else from the group's
+// current bytes, all of whose loads are issued before the first is used.
+// Otherwise one byte store per new source.
 template <int W>
 __device__ __forceinline__ void write_depths(uint8_t *__restrict__ depth, int64_t v, int32_t k, const uint64_t *nb,
-                                             uint8_t d) {
+                                             const uint64_t *sv, uint8_t d) {
+  uint8_t *row = depth + v * k;
+  if ((k & 15) == 0 && ((uintptr_t)depth & 15) == 0) {
+    constexpr int G = 4 * W;
+    const uint32_t splat = 0x01010101u * d;
+    uint4 *p = (uint4 *)row;
+    uint4 val[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      uint32_t bits = (uint32_t)(nb[g >> 2] >> (16 * (g & 3))) & 0xFFFFu;
+      uint32_t old = (uint32_t)(sv[g >> 2] >> (16 * (g & 3))) & 0xFFFFu;
+      if (bits && bits != 0xFFFFu && old) val[g] = p[g];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      uint32_t bits = (uint32_t)(nb[g >> 2] >> (16 * (g & 3))) & 0xFFFFu;
+      uint32_t old = (uint32_t)(sv[g >> 2] >> (16 * (g & 3))) & 0xFFFFu;
+      if (!bits) continue;
+      uint4 x;
+      if (bits == 0xFFFFu) {
+        x.x = x.y = x.z = x.w = splat;
+      } else {
+        if (old) {
+          x = val[g];
+        } else {
+          x.x = x.y = x.z = x.w = 0xFFFFFFFFu;
+        }
+        uint32_t c[4] = {x.x, x.y, x.z, x.w};
+        while (bits) {
+          int j = __ffs(bits) - 1;
+          bits &= bits - 1;
+          uint32_t sh = 8u * (uint32_t)(j & 3);
+          c[j >> 2] = (c[j >> 2] & ~(0xFFu << sh)) | ((uint32_t)d << sh);
+        }
+        x.x = c[0];
+        x.y = c[1];
+        x.z = c[2];
+        x.w = c[3];
+      }
+      p[g] = x;
+    }
+    return;
+  }
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     uint64_t x = nb[w];
     while (x) {
       int j = __ffsll((long long)x) - 1;
-      depth[v * k + w * 64 + j] = d;
+      row[w * 64 + j] = d;
       x &= x - 1;
     }
   }
@@ -130,7 +178,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_pull_kernel(const int64_t *__rest
         next[v * W + w] = nb[w];
         seen[v * W + w] = sv[w] | nb[w];
       }
-      write_depths<W>(depth, v, k, nb, newdepth);
+      write_depths<W>(depth, v, k, nb, sv, newdepth);
       degsum += (unsigned long long)deg[v];
     }
     // 64 consecutive vertices per wavefront: one bitmap word, no atomics
@@ -176,21 +224,21 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_finish_kernel(const int32_t *__re
     int32_t v = 0;
     if (i < cnt) {
       v = touched[i];
-      uint64_t nb[W];
+      uint64_t nb[W], sv[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         uint64_t x = visit[(int64_t)v * W + w];
         visit[(int64_t)v * W + w] = 0ull;
-        uint64_t sv = seen[(int64_t)v * W + w];
-        nb[w] = x & ~sv;
+        sv[w] = seen[(int64_t)v * W + w];
+        nb[w] = x & ~sv[w];
         any |= nb[w] != 0;
         if (nb[w]) {
-          seen[(int64_t)v * W + w] = sv | nb[w];
+          seen[(int64_t)v * W + w] = sv[w] | nb[w];
           next[(int64_t)v * W + w] = nb[w];
         }
       }
       if (any) {
-        write_depths<W>(depth, v, k, nb, newdepth);
+        write_depths<W>(depth, v, k, nb, sv, newdepth);
         degsum += (unsigned long long)deg[v];
       }
       atomicAnd((unsigned long long *)&touched_bits[v >> 6], ~(1ull << (v & 63)));
@@ -258,6 +306,236 @@ __global__ void u8_fill_kernel(uint8_t *p, int64_t count, uint8_t value) {
   }
 }
 
+// ---------------------------------------------------------------- tiled levels
+//
+// With the degree-ordered tile layout (tiles.hip) every level is one pass
+// over the entries in relabelled vertex order. A workgroup takes a chunk of a
+// destination tile of 2^12 vertices, holds their W-word masks in LDS (128 KiB
+// at W = 4) and, for every entry whose source is in the frontier and whose
+// destination has not seen every source, ORs the source's frontier mask into
+// the destination's (LDS atomics; OR is order-free). The apply pass ORs a
+// vertex's chunk results, keeps the bits not seen before, and writes seen,
+// the next frontier, the frontier and "full" bitmaps, and the depths (in the
+// caller's vertex order).
+constexpr int MT_THREADS = 1024;
+constexpr int MT_ILP = 8;
+constexpr int MT_SHIFT = 12;
+
+// W-word mask of vertex u, in 16-byte loads where the words allow.
+template <int W>
+__device__ __forceinline__ void load_mask(const uint64_t *__restrict__ m, int64_t u, uint64_t *x) {
+  const uint64_t *p = m + u * W;
+  if constexpr (W == 4) {
+    ulonglong2 a = *(const ulonglong2 *)p, b = *(const ulonglong2 *)(p + 2);
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = b.x;
+    x[3] = b.y;
+  } else if constexpr (W == 2) {
+    ulonglong2 a = *(const ulonglong2 *)p;
+    x[0] = a.x;
+    x[1] = a.y;
+  } else {
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = p[w];
+  }
+}
+
+template <int W>
+__global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__restrict__ esrc,
+                                                             const uint16_t *__restrict__ edst,
+                                                             const int64_t *__restrict__ cbeg,
+                                                             const int32_t *__restrict__ cblk,
+                                                             const uint64_t *__restrict__ front,
+                                                             const uint64_t *__restrict__ abits,
+                                                             const uint64_t *__restrict__ fbits, int64_t words,
+                                                             uint64_t *__restrict__ partial,
+                                                             uint32_t *__restrict__ cflag) {
+  constexpr int B = 1 << MT_SHIFT;
+  __shared__ uint64_t acc[B * W];
+  __shared__ uint64_t need[B / 64];
+  const int t = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int64_t tile = cblk[c];
+  for (int i = t; i < B * W; i += MT_THREADS) acc[i] = 0ull;
+  if (t < B / 64) {
+    int64_t wd = (tile << (MT_SHIFT - 6)) + t;
+    need[t] = wd < words ? ~fbits[wd] : 0ull;
+  }
+  __syncthreads();
+  const int64_t beg = cbeg[c], end = cbeg[c + 1];
+  int mine = 0;
+  // the next iteration's entries are loaded while this iteration's bitmap and
+  // mask gathers are in flight
+  int32_t un[MT_ILP];
+  uint32_t dn[MT_ILP];
+#pragma unroll
+  for (int j = 0; j < MT_ILP; ++j) {
+    int64_t i = beg + t + (int64_t)j * MT_THREADS;
+    i = i < end ? i : beg;  // a chunk is never empty
+    un[j] = esrc[i];
+    dn[j] = (uint32_t)edst[i];
+  }
+  for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)MT_THREADS * MT_ILP) {
+    int32_t u[MT_ILP];
+    uint32_t d[MT_ILP];
+    uint64_t ab[MT_ILP];
+#pragma unroll
+    for (int j = 0; j < MT_ILP; ++j) {
+      u[j] = un[j];
+      d[j] = dn[j];
+    }
+#pragma unroll
+    for (int j = 0; j < MT_ILP; ++j) ab[j] = abits[u[j] >> 6];
+    const int64_t e1 = e0 + (int64_t)MT_THREADS * MT_ILP;
+#pragma unroll
+    for (int j = 0; j < MT_ILP; ++j) {
+      int64_t i = e1 + (int64_t)j * MT_THREADS;
+      i = i < end ? i : beg;
+      un[j] = esrc[i];
+      dn[j] = (uint32_t)edst[i];
+    }
+    bool ok[MT_ILP];
+    bool some = false;
+#pragma unroll
+    for (int j = 0; j < MT_ILP; ++j) {
+      ok[j] = e0 + (int64_t)j * MT_THREADS < end && ((ab[j] >> (u[j] & 63)) & 1ull) &&
+              ((need[d[j] >> 6] >> (d[j] & 63)) & 1ull);
+      some |= ok[j];
+    }
+    // sparse levels: most wavefronts have no active entry and load no masks;
+    // otherwise inactive lanes read vertex 0's mask (one shared line)
+    if (__any(some)) {
+      uint64_t x[MT_ILP][W];
+#pragma unroll
+      for (int j = 0; j < MT_ILP; ++j) load_mask<W>(front, ok[j] ? (int64_t)u[j] : 0, x[j]);
+#pragma unroll
+      for (int j = 0; j < MT_ILP; ++j)
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (ok[j] && x[j][w]) {
+            atomicOr((unsigned long long *)&acc[d[j] * W + w], (unsigned long long)x[j][w]);
+            mine = 1;
+          }
+    }
+  }
+  int any = __syncthreads_or(mine);
+  if (any) {
+    uint64_t *out = partial + ((c * B) * W);
+    for (int i = t; i < B * W; i += MT_THREADS) out[i] = acc[i];
+  }
+  if (t == 0) cflag[c] = any ? 1u : 0u;
+}
+
+template <int W>
+__global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
+    const uint64_t *__restrict__ partial, const uint32_t *__restrict__ cflag, const int32_t *__restrict__ bfirst,
+    uint64_t *__restrict__ seen, uint64_t *__restrict__ front_cur, uint64_t *__restrict__ front_next,
+    const uint64_t *__restrict__ abits_cur, uint64_t *__restrict__ abits_next, uint64_t *__restrict__ fbits,
+    const int32_t *__restrict__ rdeg, const int32_t *__restrict__ orig, uint8_t *__restrict__ depth, int32_t k,
+    uint8_t newdepth, int64_t n, byo_counters *__restrict__ ctr) {
+  constexpr int B = 1 << MT_SHIFT;
+  uint64_t full[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    int bits = k - 64 * w;
+    full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
+  }
+  const int64_t v = (int64_t)blockIdx.x * MS_BLOCK + threadIdx.x;
+  const bool valid = v < n;
+  unsigned long long degsum = 0, count = 0;
+  bool any = false, now_full = true;
+  if (valid) {
+    if ((abits_cur[v >> 6] >> (v & 63)) & 1ull) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) front_cur[v * W + w] = 0ull;  // consumed
+    }
+    now_full = (fbits[v >> 6] >> (v & 63)) & 1ull;
+    if (!now_full) {
+      const int64_t b = v >> MT_SHIFT, l = v & (B - 1);
+      uint64_t a[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) a[w] = 0ull;
+      // hub tiles have many chunks: eight chunk results in flight; results of
+      // chunks that produced nothing this level are stale and masked out
+      const int32_t c1 = bfirst[b + 1];
+      const uint64_t *pl = partial + (int64_t)l * W;
+      int32_t c = bfirst[b];
+      for (; c + 8 <= c1; c += 8) {
+        uint32_t f[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f[j] = cflag[c + j];
+        if (!(f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | f[7])) continue;
+        uint64_t x[8][W];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+          for (int w = 0; w < W; ++w) x[j][w] = pl[((int64_t)(c + j) * B) * W + w];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+          for (int w = 0; w < W; ++w) a[w] |= f[j] ? x[j][w] : 0ull;
+      }
+      for (; c < c1; ++c) {
+        if (!cflag[c]) continue;
+#pragma unroll
+        for (int w = 0; w < W; ++w) a[w] |= pl[((int64_t)c * B) * W + w];
+      }
+      bool got = false;
+#pragma unroll
+      for (int w = 0; w < W; ++w) got |= a[w] != 0;
+      uint64_t nb[W], sv[W];
+      if (got) {  // else nothing reached v and its full bit stays clear
+        now_full = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          sv[w] = seen[v * W + w];
+          nb[w] = a[w] & ~sv[w];
+          any |= nb[w] != 0;
+          now_full &= (sv[w] | nb[w]) == full[w];
+        }
+      }
+      if (any) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          seen[v * W + w] = sv[w] | nb[w];
+          front_next[v * W + w] = nb[w];
+        }
+        write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
+        degsum = (unsigned long long)rdeg[v];
+      }
+    }
+  }
+  uint64_t am = __ballot(any);
+  uint64_t fm = __ballot(now_full);  // vertices past n count as full
+  if (lane_id() == 0 && v < n) {
+    abits_next[v >> 6] = am;
+    fbits[v >> 6] = fm;
+    count = (unsigned long long)__popcll(am);
+  }
+  unsigned long long ts = block_sum<unsigned long long, MS_BLOCK>(degsum);
+  unsigned long long tc = block_sum<unsigned long long, MS_BLOCK>(count);
+  if (threadIdx.x == 0) {
+    if (ts) atomicAdd(&ctr->degsum, ts);
+    if (tc) atomicAdd(&ctr->count, tc);
+  }
+}
+
+// Sources: seen/front bits at the relabelled vertex, frontier bitmap bit,
+// depth 0 at the original vertex.
+__global__ void ms_tile_init_kernel(const int32_t *__restrict__ srcs, const int32_t *__restrict__ rsrcs, int32_t k,
+                                    int32_t W, uint64_t *seen, uint64_t *front, uint64_t *abits, uint8_t *depth) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) {
+    int64_t r = rsrcs[j];
+    unsigned long long bit = 1ull << (j & 63);
+    atomicOr((unsigned long long *)&seen[r * W + (j >> 6)], bit);
+    atomicOr((unsigned long long *)&front[r * W + (j >> 6)], bit);
+    atomicOr((unsigned long long *)&abits[r >> 6], 1ull << (r & 63));
+    depth[(int64_t)srcs[j] * k + j] = 0;
+  }
+}
+
 template <int W>
 static void launch_pull(const byo_graph *g, const uint64_t *front, uint64_t *seen, uint64_t *next, uint8_t *depth,
                         int32_t k, uint8_t nd, uint64_t *abits, byo_counters *ctr, int32_t tw, hipStream_t s) {
@@ -292,14 +570,14 @@ struct ms_ws {
   int W = 0;
   uint64_t *seen = nullptr, *front[2] = {nullptr, nullptr}, *visit = nullptr, *tbits = nullptr;
   uint64_t *abits[2] = {nullptr, nullptr};
-  int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr;
+  int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr, *rsrcs = nullptr;
   byo_counters *ctr = nullptr;
   unsigned long long *tally = nullptr;
 };
 
 static void ms_free(ms_ws &m) {
   void *p[] = {m.seen, m.front[0], m.front[1], m.visit, m.tbits, m.touched, m.active[0], m.active[1], m.srcs,
-               m.ctr, m.tally, m.abits[0], m.abits[1]};
+               m.rsrcs, m.ctr, m.tally, m.abits[0], m.abits[1]};
   for (void *x : p)
     if (x) (void)hipFree(x);
   m = ms_ws();
@@ -314,6 +592,73 @@ void ms_release(byo_workspace &w) {
   w.ms = nullptr;
 }
 
+
+template <int W>
+static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *depth, int32_t k, uint8_t nd,
+                              int64_t n, byo_counters *ctr, hipStream_t s) {
+  int64_t words = (n + 63) / 64;
+  int nx = 1 - cur;
+  {
+    ktimer_scope kt(BYO_K_MSBFS_PULL, s);
+    ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->esrc, t->edst, t->cbeg, t->cblk, mw.front[cur],
+                                                                 mw.abits[cur], mw.tbits, words,
+                                                                 (uint64_t *)t->partial, t->cflag);
+  }
+  ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
+  ms_tile_apply_kernel<W><<<(unsigned)((n + MS_BLOCK - 1) / MS_BLOCK), MS_BLOCK, 0, s>>>(
+      (const uint64_t *)t->partial, t->cflag, t->bfirst, mw.seen, mw.front[cur], mw.front[nx], mw.abits[cur],
+      mw.abits[nx], mw.tbits, t->rdeg, t->orig, depth, k, nd, n, ctr);
+}
+
+// Every level over the tile layout, in relabelled vertex order. The caller
+// has zeroed seen, both frontier buffers, the full bitmap (tbits) and the
+// counters, and filled depth with 255.
+static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, const std::vector<int32_t> &hs, int32_t k, int W,
+                               uint8_t *d_depth, hipStream_t s, byo_run_stats *stats) {
+  BYO_TRY(tiles_ensure(g, MT_SHIFT, s));
+  byo_tiles *t = g->ws.tiles;
+  BYO_TRY(tiles_partial(t, sizeof(uint64_t) * (size_t)W << MT_SHIFT));
+  const int64_t n = g->n, words = (n + 63) / 64;
+  std::vector<int32_t> rs(k);
+  for (int32_t j = 0; j < k; ++j) rs[j] = t->h_label[hs[j]];
+  BYO_HIP(hipMemcpyAsync(mw.rsrcs, rs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  BYO_HIP(hipMemsetAsync(mw.abits[0], 0, sizeof(uint64_t) * (size_t)words, s));
+  ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, mw.rsrcs, k, W, mw.seen, mw.front[0], mw.abits[0], d_depth);
+  BYO_HIP(hipGetLastError());
+  byo_run_stats st;
+  std::memset(&st, 0, sizeof(st));
+  int cur = 0, level = 0;
+  while (true) {
+    if (level + 1 >= MS_MAX_LEVELS) {
+      if (stats) *stats = st;
+      return fail(BYO_ELIMIT, "a distance reached 255 (depths are uint8)");
+    }
+    uint8_t nd = (uint8_t)(level + 1);
+    byo_counters *ctr = mw.ctr + level;
+    switch (W) {
+      case 1: launch_tile_level<1>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+      case 2: launch_tile_level<2>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+      case 3: launch_tile_level<3>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+      default: launch_tile_level<4>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+    }
+    BYO_HIP(hipGetLastError());
+    byo_counters c;
+    BYO_TRY(sync_read(s, ctr, &c, sizeof(c)));
+    st.variant_count[BYO_V_PULL_WAVE]++;
+    ++level;
+    cur = 1 - cur;
+    if (c.count == 0) break;
+  }
+  ms_tally_kernel<<<(unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096), MS_BLOCK, 0, s>>>(
+      mw.seen, W, t->rdeg, n, mw.tally);
+  unsigned long long tl[2] = {0, 0};
+  BYO_TRY(sync_read(s, mw.tally, tl, sizeof(tl)));
+  st.levels = level;
+  st.reached = (int64_t)tl[0];
+  st.edges = (int64_t)tl[1];
+  if (stats) *stats = st;
+  return BYO_OK;
+}
 }  // namespace byo
 
 using namespace byo;
@@ -348,6 +693,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     BYO_HIP(hipMalloc(&mw.active[0], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.active[1], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.srcs, sizeof(int32_t) * 256));
+    BYO_HIP(hipMalloc(&mw.rsrcs, sizeof(int32_t) * 256));
     BYO_HIP(hipMalloc(&mw.ctr, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1)));
     BYO_HIP(hipMalloc(&mw.tally, sizeof(unsigned long long) * 2));
     mw.n = n;
@@ -369,6 +715,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   std::vector<int32_t> hs(k);
   for (int32_t j = 0; j < k; ++j) hs[j] = (int32_t)h_srcs[j];
   BYO_HIP(hipMemcpyAsync(mw.srcs, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  if (o.ms_tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, hs, k, W, d_depth, s, stats);
   ms_init_kernel<<<1, 256, 0, s>>>(mw.srcs, k, W, mw.seen, mw.front[0], d_depth);
   // first active list: the distinct sources
   std::vector<int32_t> act(hs);

@@ -288,17 +288,16 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     BYO_HIP(hipGetLastError());
     return BYO_OK;
   }
-  if (o.pr_blocked && pr_seg_wanted(g)) {
-    BYO_TRY(pr_seg_ensure(g, s));
-    float *dp = pr_seg_dpart(g);
-    pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->deg, n, w.words, w.contrib[0], dp);
+  if (o.pr_blocked != 0 && tiles_wanted(g)) {
+    BYO_TRY(tiles_ensure(g, pr_tile_shift(o.pr_blocked), s));
+    // the tiled step runs in the layout's relabelled vertex order
+    pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->ws.tiles->rdeg, n, w.words, w.contrib[0], w.dpart);
     BYO_HIP(hipGetLastError());
-    int64_t nparts = nb;
     int c = 0;
     for (int32_t t = 0; t < iters; ++t) {
       bool last = t + 1 == iters;
-      BYO_TRY(pr_seg_step(g, w.contrib[c], (float)damping, last ? nullptr : w.contrib[1 - c], last ? d_rank : nullptr,
-                          nparts, s, &nparts));
+      BYO_TRY(pr_tile_step(g, w.contrib[c], (float)damping, last ? nullptr : w.contrib[1 - c], last ? d_rank : nullptr,
+                           s));
       c = 1 - c;
     }
     return BYO_OK;

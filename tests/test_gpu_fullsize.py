@@ -1,5 +1,5 @@
 """Parity at the benchmark's own sizes (RMAT-22, the launch configuration bench.py
-times) and at a mid size where PageRank runs cache-blocked."""
+times) and at a mid size, for both PageRank layouts."""
 import numpy as np
 import pytest
 
@@ -38,8 +38,9 @@ def test_pagerank_rmat22_full(rmat22):
     got = r.cpu().numpy()
     assert pr_err(got, r64) < PR_TOL
     assert abs(got.astype(np.float64).sum() - 1.0) < 1e-4
-    r2, _ = byo.pagerank(g, 0.85, 20, pr_blocked=0)
-    assert pr_err(r2.cpu().numpy(), r64) < PR_TOL
+    for layout in (0, 1):
+        r2, _ = byo.pagerank(g, 0.85, 20, pr_blocked=layout)
+        assert pr_err(r2.cpu().numpy(), r64) < PR_TOL, layout
 
 
 def test_bfs_cc_rmat22_full(rmat22):
@@ -56,9 +57,10 @@ def test_bfs_cc_rmat22_full(rmat22):
 def test_msbfs_rmat22_sampled_columns(rmat22):
     p, g, og = rmat22
     srcs = gen.pick_sources(p, 256, seed=2)
-    D, st = byo.msbfs(g, srcs)
-    D = D.cpu().numpy()
-    for j in (0, 63, 64, 200, 255):
-        want, _ = og.bfs(int(srcs[j]))
-        assert np.array_equal(D[:, j], np.where(want < 0, 255, want)), j
-    assert st["reached"] == int((D != 255).sum())
+    for tiled in (0, 1):
+        D, st = byo.msbfs(g, srcs, ms_tiled=tiled)
+        D = D.cpu().numpy()
+        for j in (0, 63, 64, 200, 255):
+            want, _ = og.bfs(int(srcs[j]))
+            assert np.array_equal(D[:, j], np.where(want < 0, 255, want)), (tiled, j)
+        assert st["reached"] == int((D != 255).sum())

@@ -46,6 +46,42 @@ def test_msbfs_fixed_variants(variant):
     assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs))
 
 
+TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7)]
+
+
+@pytest.mark.parametrize("k", [1, 7, 64, 65, 200, 256])
+@pytest.mark.parametrize("pi", range(len(TILED)))
+def test_msbfs_tiled_matches_oracle(pi, k):
+    """Tile-layout levels (degree-relabelled, 2^12-vertex tiles, several
+    chunks per hub tile, ragged last tile, isolated vertices)."""
+    p = TILED[pi]
+    g, og = build(p)
+    rng = np.random.default_rng(100 + k)
+    srcs = rng.integers(0, og.n, k)
+    srcs[0] = srcs[-1]
+    D, st = byo.msbfs(g, srcs, ms_tiled=1)
+    want = og.msbfs(srcs)
+    assert np.array_equal(D.cpu().numpy(), want), (pi, k)
+    assert st["reached"] == int((want != 255).sum())
+    D2, st2 = byo.msbfs(g, srcs)
+    assert np.array_equal(D2.cpu().numpy(), want)
+    assert st2["edges"] == st["edges"] and st2["reached"] == st["reached"]
+
+
+def test_msbfs_tiled_after_pagerank_layout_change():
+    """PageRank with another tile size rebuilds the shared layout; the next
+    tiled multi-source run rebuilds it back and stays exact."""
+    p = TILED[0]
+    g, og = build(p)
+    srcs = gen.pick_sources(p, 100, seed=3)
+    byo.pagerank(g, 0.85, 2, pr_blocked=14)
+    D, _ = byo.msbfs(g, srcs, ms_tiled=1)
+    assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs))
+    r, _ = byo.pagerank(g, 0.85, 5, pr_blocked=1)
+    r64 = og.pagerank(0.85, 5)
+    assert np.max(np.abs(r.cpu().numpy() - r64)) / np.max(np.abs(r64)) < 1e-5
+
+
 def test_msbfs_depth_limit():
     p = graphs.path(400)
     g, og = build(p)

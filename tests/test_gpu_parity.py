@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2405_11671_amd import gen
 from tests import graphs
 
 pytestmark = pytest.mark.gpu
@@ -96,6 +97,26 @@ def test_pagerank(p, iters):
     err = np.max(np.abs(r - r64)) / np.max(np.abs(r64))
     assert err < PR_TOL, (p.name, iters, err)
     assert abs(r.sum() - 1.0) < 1e-4
+
+
+@pytest.mark.parametrize("layout", [1, 12, 13, 14])
+@pytest.mark.parametrize("iters", [1, 20])
+def test_pagerank_tiled_layout(layout, iters):
+    """Destination-tiled PageRank: several tiles, chunks per tile and a ragged last tile."""
+    p = gen.rmat_pairs(16, 16, seed=12)
+    g, og = build(p)
+    assert g.n >= 1 << 16 and g.m >= 4 * g.n
+    r32, st = byo.pagerank(g, 0.85, iters, pr_blocked=layout)
+    r64 = og.pagerank(0.85, iters)
+    r = r32.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(r - r64)) / np.max(np.abs(r64)) < PR_TOL
+    assert abs(r.sum() - 1.0) < 1e-4
+    # graph with n not a multiple of the tile and isolated vertices
+    q = gen.er_pairs(70001, 10, seed=5)
+    g2, og2 = build(q)
+    r32, _ = byo.pagerank(g2, 0.85, iters, pr_blocked=layout)
+    r64 = og2.pagerank(0.85, iters)
+    assert np.max(np.abs(r32.cpu().numpy() - r64)) / np.max(np.abs(r64)) < PR_TOL
 
 
 def test_bfs_repeat_deterministic_depths():
