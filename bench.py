@@ -241,7 +241,7 @@ def main():
     label = torch.empty(n, dtype=torch.int32, device="cuda")
     rank = torch.empty(n, dtype=torch.float32, device="cuda")
     opts = byo.default_opts()
-    tiled = byo.default_opts(pr_blocked=0 if args.no_tiles else 1, ms_tiled=0 if args.no_tiles else 1)
+    tiled = byo.default_opts(pr_blocked=0 if args.no_tiles else 1, tiled=0 if args.no_tiles else 1)
     from paper_2405_11671_amd import selector as sel
     wpath = os.path.join(ROOT, "paper_2405_11671_amd", "selector_weights.json")
     params, mu, sd, _ = sel.load_weights(wpath)

@@ -93,10 +93,10 @@ typedef struct byo_opts {
                              graph. */
   int32_t use_graph;      /* BFS: 1 = device-side level control replayed from a captured
                              hipGraph (threshold rule on the device), 0 = host loop (default) */
-  int32_t ms_tiled;       /* multi-source BFS: 1 = every level over the degree-ordered tile
-                             layout (the one PageRank's pr_blocked uses, tiles of 2^12)
-                             when n >= 2^16 and m >= 4n; 0 = push/pull over the CSR
-                             (default) */
+  int32_t tiled;          /* multi-source BFS and connectivity: 1 = every level / round over
+                             the degree-ordered tile layout (the one PageRank's pr_blocked
+                             uses) when n >= 2^16 and m >= 4n; 0 = over the CSR with the
+                             selected variants (default) */
   int32_t reserved[5];
 } byo_opts;
 

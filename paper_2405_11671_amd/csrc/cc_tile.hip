@@ -1,0 +1,244 @@
+// Connectivity (minimum-ID labels) over the degree-ordered tile layout
+// (tiles.hip; option tiled = 1). Label propagation: every round each vertex
+// whose label changed in the round before offers its label to its
+// neighbours, a vertex keeps the smallest label offered, and a
+// pointer-jumping pass then replaces label x by the label of vertex x when
+// smaller. Labels only decrease and are always IDs of vertices in the same
+// component, so the fixed point is the minimum ID of each component whatever
+// the schedule.
+//
+// The round runs in the layout's vertex order, but label values are original
+// IDs, so the minimum taken is the minimum original ID. A workgroup takes a
+// chunk of a destination tile, keeps the tile's minima in LDS (atomic min is
+// order-free) and skips entries whose source is not active; the apply pass
+// takes the minimum over the tile's chunks.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+
+#include "internal.h"
+
+namespace byo {
+
+constexpr int CT_THREADS = 1024;
+constexpr int CT_ILP = 16;
+constexpr int CT_APPLY = 256;
+
+template <int SHIFT>
+__global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const int32_t *__restrict__ esrc,
+                                                             const uint16_t *__restrict__ edst,
+                                                             const int64_t *__restrict__ cbeg,
+                                                             const int32_t *__restrict__ lab,
+                                                             const uint64_t *__restrict__ abits,
+                                                             int32_t *__restrict__ partial,
+                                                             uint32_t *__restrict__ cflag) {
+  constexpr int B = 1 << SHIFT;
+  __shared__ int32_t acc[B];
+  __shared__ int s_any;
+  const int t = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  for (int i = t; i < B; i += CT_THREADS) acc[i] = INT_MAX;
+  if (t == 0) s_any = 0;
+  __syncthreads();
+  const int64_t beg = cbeg[c], end = cbeg[c + 1];
+  int mine = 0;
+  for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)CT_THREADS * CT_ILP) {
+    int32_t u[CT_ILP];
+    uint32_t d[CT_ILP];
+    uint64_t ab[CT_ILP];
+#pragma unroll
+    for (int j = 0; j < CT_ILP; ++j) {
+      int64_t i = e0 + (int64_t)j * CT_THREADS;
+      i = i < end ? i : beg;  // a chunk is never empty
+      u[j] = esrc[i];
+      d[j] = (uint32_t)edst[i];
+    }
+#pragma unroll
+    for (int j = 0; j < CT_ILP; ++j) ab[j] = abits[u[j] >> 6];
+    bool ok[CT_ILP];
+    bool some = false;
+#pragma unroll
+    for (int j = 0; j < CT_ILP; ++j) {
+      ok[j] = e0 + (int64_t)j * CT_THREADS < end && ((ab[j] >> (u[j] & 63)) & 1ull);
+      some |= ok[j];
+    }
+    if (__any(some)) {
+      int32_t x[CT_ILP];
+#pragma unroll
+      for (int j = 0; j < CT_ILP; ++j) x[j] = lab[ok[j] ? u[j] : 0];
+#pragma unroll
+      for (int j = 0; j < CT_ILP; ++j)
+        if (ok[j]) {
+          atomicMin(&acc[d[j]], x[j]);
+          mine = 1;
+        }
+    }
+  }
+  if (mine) s_any = 1;  // every writer stores the same value
+  __syncthreads();
+  const int any = s_any;
+  if (any) {
+    int32_t *out = partial + (c << SHIFT);
+    for (int i = t; i < B; i += CT_THREADS) out[i] = acc[i];
+  }
+  if (t == 0) cflag[c] = any ? 1u : 0u;
+}
+
+// Smallest label offered to w over its tile's chunks; lower lab[w] to it and
+// mark w active. One wavefront owns one word of the next active bitmap.
+template <int SHIFT>
+__global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *__restrict__ partial,
+                                                                 const uint32_t *__restrict__ cflag,
+                                                                 const int32_t *__restrict__ bfirst,
+                                                                 int32_t *__restrict__ lab,
+                                                                 uint64_t *__restrict__ abits_next, int64_t n,
+                                                                 byo_counters *__restrict__ ctr) {
+  constexpr int B = 1 << SHIFT;
+  unsigned long long count = 0;
+  // capped grid: a few thousand counter atomics per round
+  for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
+    const int64_t w = base + threadIdx.x;
+    bool changed = false;
+    if (w < n) {
+      const int64_t b = w >> SHIFT, l = w & (B - 1);
+      const int32_t *pl = partial + l;
+      const int32_t c1 = bfirst[b + 1];
+      int32_t m = INT_MAX;
+      int32_t c = bfirst[b];
+      for (; c + 8 <= c1; c += 8) {
+        uint32_t f[8];
+        int32_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) f[j] = cflag[c + j];
+        if (!(f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | f[7])) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = pl[(int64_t)(c + j) << SHIFT];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) m = (f[j] && x[j] < m) ? x[j] : m;
+      }
+      for (; c < c1; ++c)
+        if (cflag[c]) m = min(m, pl[(int64_t)c << SHIFT]);
+      if (m < lab[w]) {
+        lab[w] = m;
+        changed = true;
+      }
+    }
+    uint64_t am = __ballot(changed);
+    if (lane_id() == 0 && w < n) {
+      abits_next[w >> 6] = am;
+      count += (unsigned long long)__popcll(am);
+    }
+  }
+  unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
+  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
+}
+
+// Pointer jumping: label x of w becomes the label of vertex x when smaller
+// (x is an original ID; rlabel maps it to the layout's order). Reads of
+// labels being lowered by other threads see either value; both are IDs in
+// the component, so any interleaving is sound.
+__global__ void __launch_bounds__(CT_APPLY) cc_tile_jump_kernel(int32_t *__restrict__ lab,
+                                                                const int32_t *__restrict__ rlabel,
+                                                                uint64_t *__restrict__ abits_next, int64_t n,
+                                                                byo_counters *__restrict__ ctr) {
+  unsigned long long count = 0;
+  for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
+    const int64_t w = base + threadIdx.x;
+    bool changed = false;
+    if (w < n) {
+      int32_t x = lab[w];
+      int32_t y = lab[rlabel[x]];
+      if (y < x) {
+        lab[w] = y;
+        changed = true;
+      }
+    }
+    uint64_t am = __ballot(changed);
+    if (lane_id() == 0 && w < n && am) {
+      abits_next[w >> 6] |= am;
+      count += (unsigned long long)__popcll(am);
+    }
+  }
+  unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
+  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
+}
+
+__global__ void cc_tile_init_kernel(const int32_t *__restrict__ orig, int64_t n, int32_t *__restrict__ lab,
+                                    uint64_t *__restrict__ abits) {
+  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < n) lab[w] = orig[w];
+  int64_t words = (n + 63) / 64;
+  if (w < words) abits[w] = (w + 1) * 64 <= n ? ~0ull : (~0ull >> (64 - (n & 63)));
+}
+
+__global__ void cc_tile_out_kernel(const int32_t *__restrict__ lab, const int32_t *__restrict__ orig, int64_t n,
+                                   int32_t *__restrict__ out) {
+  int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w < n) out[orig[w]] = lab[w];
+}
+
+static unsigned apply_grid(int64_t n) {
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + CT_APPLY - 1) / CT_APPLY), 2048);
+}
+
+template <int SHIFT>
+static void cc_round(const byo_tiles *t, int32_t *lab, const uint64_t *abits, uint64_t *abits_next, bool jump,
+                     byo_counters *ctr, int64_t n, hipStream_t s) {
+  {
+    ktimer_scope kt(BYO_K_CC_PULL, s);
+    cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->esrc, t->edst, t->cbeg, lab, abits,
+                                                                     (int32_t *)t->partial, t->cflag);
+    cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>(
+        (const int32_t *)t->partial, t->cflag, t->bfirst, lab, abits_next, n, ctr);
+  }
+  if (jump) {
+    ktimer_scope kt(BYO_K_CC_SHORTCUT, s);
+    cc_tile_jump_kernel<<<apply_grid(n), CT_APPLY, 0, s>>>(lab, t->rlabel, abits_next, n, ctr);
+  }
+}
+
+byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
+  BYO_TRY(ws_ensure_traversal(g));
+  BYO_TRY(tiles_ensure(g, g->ws.tiles ? g->ws.tiles->shift : BYO_TILE_SHIFT, s));
+  byo_tiles *t = g->ws.tiles;
+  BYO_TRY(tiles_partial(t, sizeof(int32_t) << t->shift));
+  BYO_TRY(tiles_scratch(t));
+  byo_workspace &w = g->ws;
+  const int64_t n = g->n;
+  int32_t *lab = t->scratch;
+  cc_tile_init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(t->orig, n, lab, w.bits[0]);
+  BYO_HIP(hipGetLastError());
+  byo_run_stats st;
+  std::memset(&st, 0, sizeof(st));
+  int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
+  int cur = 0;
+  int32_t round = 0;
+  while (true) {
+    if (round >= cap) {
+      if (stats) *stats = st;
+      return fail(BYO_ELIMIT, "connectivity round cap reached");
+    }
+    byo_counters *ctr = w.ctr;
+    BYO_HIP(hipMemsetAsync(ctr, 0, sizeof(byo_counters), s));
+    uint64_t *an = w.bits[1 - cur];
+    switch (t->shift) {
+      case 13: cc_round<13>(t, lab, w.bits[cur], an, o.cc_shortcut != 0, ctr, n, s); break;
+      case 14: cc_round<14>(t, lab, w.bits[cur], an, o.cc_shortcut != 0, ctr, n, s); break;
+      default: cc_round<12>(t, lab, w.bits[cur], an, o.cc_shortcut != 0, ctr, n, s); break;
+    }
+    BYO_HIP(hipGetLastError());
+    byo_counters c;
+    BYO_TRY(sync_read(s, ctr, &c, sizeof(c)));
+    st.variant_count[BYO_V_PULL_WAVE]++;
+    ++round;
+    cur = 1 - cur;
+    if (c.count == 0) break;
+  }
+  cc_tile_out_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lab, t->orig, n, d_label);
+  BYO_HIP(hipGetLastError());
+  st.levels = round;
+  if (stats) *stats = st;
+  return BYO_OK;
+}
+
+}  // namespace byo

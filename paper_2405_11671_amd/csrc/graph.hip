@@ -206,7 +206,7 @@ void byo_opts_default(byo_opts *o) {
   o->small_frontier = 0;
   o->pr_blocked = 0;
   o->use_graph = 0;
-  o->ms_tiled = 0;
+  o->tiled = 0;
 }
 
 byo_status byo_csr_from_pairs(const int32_t *src, const int32_t *dst, int64_t npairs, int64_t n, int64_t *off,

@@ -214,6 +214,8 @@ struct byo_tiles {
   int32_t *bfirst = nullptr;  // [nblk + 1] first chunk of each tile
   int32_t *cblk = nullptr;    // [nchunks] tile of each chunk
   uint32_t *cflag = nullptr;  // [nchunks] per-level "chunk produced something" flags
+  int32_t *rlabel = nullptr;  // [n] relabelled ID of each original vertex
+  int32_t *scratch = nullptr; // [n] per-vertex work array (tiles_scratch)
   void *partial = nullptr;    // chunk results, sized by the user (tiles_partial)
   size_t partial_bytes = 0;
   std::vector<int32_t> h_label;  // relabelled ID of each original vertex (host copy)
@@ -221,6 +223,9 @@ struct byo_tiles {
 bool tiles_wanted(const byo_graph *g);  // n >= 2^16 and m >= 4n
 byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s);
 byo_status tiles_partial(byo_tiles *t, size_t bytes_per_chunk);
+byo_status tiles_scratch(byo_tiles *t);
+// connectivity over the tile layout (cc_tile.hip)
+byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 void tiles_release(byo_workspace &w);
 // tiled PageRank step (pagerank_tile.hip); opt = byo_opts::pr_blocked
 int pr_tile_shift(int32_t opt);

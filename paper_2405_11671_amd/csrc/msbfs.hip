@@ -354,10 +354,12 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__re
   constexpr int B = 1 << MT_SHIFT;
   __shared__ uint64_t acc[B * W];
   __shared__ uint64_t need[B / 64];
+  __shared__ int s_any;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
   const int64_t tile = cblk[c];
   for (int i = t; i < B * W; i += MT_THREADS) acc[i] = 0ull;
+  if (t == 0) s_any = 0;
   if (t < B / 64) {
     int64_t wd = (tile << (MT_SHIFT - 6)) + t;
     need[t] = wd < words ? ~fbits[wd] : 0ull;
@@ -419,7 +421,9 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__re
           }
     }
   }
-  int any = __syncthreads_or(mine);
+  if (mine) s_any = 1;  // every writer stores the same value
+  __syncthreads();
+  const int any = s_any;
   if (any) {
     uint64_t *out = partial + ((c * B) * W);
     for (int i = t; i < B * W; i += MT_THREADS) out[i] = acc[i];
@@ -441,77 +445,80 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
     int bits = k - 64 * w;
     full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
   }
-  const int64_t v = (int64_t)blockIdx.x * MS_BLOCK + threadIdx.x;
-  const bool valid = v < n;
   unsigned long long degsum = 0, count = 0;
-  bool any = false, now_full = true;
-  if (valid) {
-    if ((abits_cur[v >> 6] >> (v & 63)) & 1ull) {
+  // capped grid: a few thousand counter atomics per level, not one per 256 vertices
+  for (int64_t base = (int64_t)blockIdx.x * MS_BLOCK; base < n; base += (int64_t)gridDim.x * MS_BLOCK) {
+    const int64_t v = base + threadIdx.x;
+    const bool valid = v < n;
+    bool any = false, now_full = true;
+    if (valid) {
+      if ((abits_cur[v >> 6] >> (v & 63)) & 1ull) {
 #pragma unroll
-      for (int w = 0; w < W; ++w) front_cur[v * W + w] = 0ull;  // consumed
-    }
-    now_full = (fbits[v >> 6] >> (v & 63)) & 1ull;
-    if (!now_full) {
-      const int64_t b = v >> MT_SHIFT, l = v & (B - 1);
-      uint64_t a[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) a[w] = 0ull;
-      // hub tiles have many chunks: eight chunk results in flight; results of
-      // chunks that produced nothing this level are stale and masked out
-      const int32_t c1 = bfirst[b + 1];
-      const uint64_t *pl = partial + (int64_t)l * W;
-      int32_t c = bfirst[b];
-      for (; c + 8 <= c1; c += 8) {
-        uint32_t f[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) f[j] = cflag[c + j];
-        if (!(f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | f[7])) continue;
-        uint64_t x[8][W];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-#pragma unroll
-          for (int w = 0; w < W; ++w) x[j][w] = pl[((int64_t)(c + j) * B) * W + w];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-#pragma unroll
-          for (int w = 0; w < W; ++w) a[w] |= f[j] ? x[j][w] : 0ull;
+        for (int w = 0; w < W; ++w) front_cur[v * W + w] = 0ull;  // consumed
       }
-      for (; c < c1; ++c) {
-        if (!cflag[c]) continue;
+      now_full = (fbits[v >> 6] >> (v & 63)) & 1ull;
+      if (!now_full) {
+        const int64_t b = v >> MT_SHIFT, l = v & (B - 1);
+        uint64_t a[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) a[w] |= pl[((int64_t)c * B) * W + w];
-      }
-      bool got = false;
+        for (int w = 0; w < W; ++w) a[w] = 0ull;
+        // hub tiles have many chunks: eight chunk results in flight; results of
+        // chunks that produced nothing this level are stale and masked out
+        const int32_t c1 = bfirst[b + 1];
+        const uint64_t *pl = partial + (int64_t)l * W;
+        int32_t c = bfirst[b];
+        for (; c + 8 <= c1; c += 8) {
+          uint32_t f[8];
 #pragma unroll
-      for (int w = 0; w < W; ++w) got |= a[w] != 0;
-      uint64_t nb[W], sv[W];
-      if (got) {  // else nothing reached v and its full bit stays clear
-        now_full = true;
+          for (int j = 0; j < 8; ++j) f[j] = cflag[c + j];
+          if (!(f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | f[7])) continue;
+          uint64_t x[8][W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          sv[w] = seen[v * W + w];
-          nb[w] = a[w] & ~sv[w];
-          any |= nb[w] != 0;
-          now_full &= (sv[w] | nb[w]) == full[w];
+          for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[j][w] = pl[((int64_t)(c + j) * B) * W + w];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int w = 0; w < W; ++w) a[w] |= f[j] ? x[j][w] : 0ull;
+        }
+        for (; c < c1; ++c) {
+          if (!cflag[c]) continue;
+#pragma unroll
+          for (int w = 0; w < W; ++w) a[w] |= pl[((int64_t)c * B) * W + w];
+        }
+        bool got = false;
+#pragma unroll
+        for (int w = 0; w < W; ++w) got |= a[w] != 0;
+        uint64_t nb[W], sv[W];
+        if (got) {  // else nothing reached v and its full bit stays clear
+          now_full = true;
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            sv[w] = seen[v * W + w];
+            nb[w] = a[w] & ~sv[w];
+            any |= nb[w] != 0;
+            now_full &= (sv[w] | nb[w]) == full[w];
+          }
+        }
+        if (any) {
+#pragma unroll
+          for (int w = 0; w < W; ++w) {
+            seen[v * W + w] = sv[w] | nb[w];
+            front_next[v * W + w] = nb[w];
+          }
+          write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
+          degsum += (unsigned long long)rdeg[v];
         }
       }
-      if (any) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          seen[v * W + w] = sv[w] | nb[w];
-          front_next[v * W + w] = nb[w];
-        }
-        write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
-        degsum = (unsigned long long)rdeg[v];
-      }
     }
-  }
-  uint64_t am = __ballot(any);
-  uint64_t fm = __ballot(now_full);  // vertices past n count as full
-  if (lane_id() == 0 && v < n) {
-    abits_next[v >> 6] = am;
-    fbits[v >> 6] = fm;
-    count = (unsigned long long)__popcll(am);
+    uint64_t am = __ballot(any);
+    uint64_t fm = __ballot(now_full);  // vertices past n count as full
+    if (lane_id() == 0 && v < n) {
+      abits_next[v >> 6] = am;
+      fbits[v >> 6] = fm;
+      count += (unsigned long long)__popcll(am);
+    }
   }
   unsigned long long ts = block_sum<unsigned long long, MS_BLOCK>(degsum);
   unsigned long long tc = block_sum<unsigned long long, MS_BLOCK>(count);
@@ -605,7 +612,7 @@ static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *d
                                                                  (uint64_t *)t->partial, t->cflag);
   }
   ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
-  ms_tile_apply_kernel<W><<<(unsigned)((n + MS_BLOCK - 1) / MS_BLOCK), MS_BLOCK, 0, s>>>(
+  ms_tile_apply_kernel<W><<<(unsigned)std::min<int64_t>((n + MS_BLOCK - 1) / MS_BLOCK, 2048), MS_BLOCK, 0, s>>>(
       (const uint64_t *)t->partial, t->cflag, t->bfirst, mw.seen, mw.front[cur], mw.front[nx], mw.abits[cur],
       mw.abits[nx], mw.tbits, t->rdeg, t->orig, depth, k, nd, n, ctr);
 }
@@ -715,7 +722,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   std::vector<int32_t> hs(k);
   for (int32_t j = 0; j < k; ++j) hs[j] = (int32_t)h_srcs[j];
   BYO_HIP(hipMemcpyAsync(mw.srcs, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
-  if (o.ms_tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, hs, k, W, d_depth, s, stats);
+  if (o.tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, hs, k, W, d_depth, s, stats);
   ms_init_kernel<<<1, 256, 0, s>>>(mw.srcs, k, W, mw.seen, mw.front[0], d_depth);
   // first active list: the distinct sources
   std::vector<int32_t> act(hs);

@@ -29,7 +29,8 @@ bool tiles_wanted(const byo_graph *g) { return g->n >= (1ll << 16) && g->m >= 4 
 void tiles_release(byo_workspace &w) {
   if (!w.tiles) return;
   byo_tiles *p = w.tiles;
-  void *d[] = {p->esrc, p->edst, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->partial};
+  void *d[] = {p->esrc, p->edst, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->rlabel, p->scratch,
+               p->partial};
   for (void *x : d)
     if (x) (void)hipFree(x);
   delete p;
@@ -178,6 +179,7 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   BYO_HIP(hipMalloc(&p->bfirst, sizeof(int32_t) * bfirst.size()));
   BYO_HIP(hipMalloc(&p->cblk, sizeof(int32_t) * (size_t)nchunks));
   BYO_HIP(hipMalloc(&p->cflag, sizeof(uint32_t) * (size_t)nchunks));
+  BYO_HIP(hipMalloc(&p->rlabel, sizeof(int32_t) * (size_t)n));
   BYO_HIP(hipMemcpy(p->esrc, esrc.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->edst, edst.data(), sizeof(uint16_t) * (size_t)m, hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->rdeg, rdeg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
@@ -185,6 +187,12 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   BYO_HIP(hipMemcpy(p->cbeg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->bfirst, bfirst.data(), sizeof(int32_t) * bfirst.size(), hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->cblk, cblk.data(), sizeof(int32_t) * (size_t)nchunks, hipMemcpyHostToDevice));
+  BYO_HIP(hipMemcpy(p->rlabel, p->h_label.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+  return BYO_OK;
+}
+
+byo_status tiles_scratch(byo_tiles *t) {
+  if (!t->scratch) BYO_HIP(hipMalloc(&t->scratch, sizeof(int32_t) * (size_t)t->n));
   return BYO_OK;
 }
 

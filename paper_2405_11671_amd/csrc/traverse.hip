@@ -344,6 +344,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     if (stats) *stats = st;
     return BYO_OK;
   }
+  if (o.tiled && tiles_wanted(g)) return cc_tiled_run(g, d_label, o, s, stats);
   BYO_TRY(ws_ensure_traversal(g));
   byo_workspace &w = g->ws;
   iota_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, s>>>(d_label, n);

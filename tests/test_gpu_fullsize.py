@@ -50,15 +50,17 @@ def test_bfs_cc_rmat22_full(rmat22):
         want, _ = og.bfs(int(s))
         assert np.array_equal(d.cpu().numpy(), want)
         assert og.check_bfs(int(s), d.cpu().numpy(), par.cpu().numpy()) == 0
-    lab, _ = byo.cc(g)
-    assert np.array_equal(lab.cpu().numpy(), og.cc())
+    want = og.cc()
+    for tiled in (0, 1):
+        lab, _ = byo.cc(g, tiled=tiled)
+        assert np.array_equal(lab.cpu().numpy(), want), tiled
 
 
 def test_msbfs_rmat22_sampled_columns(rmat22):
     p, g, og = rmat22
     srcs = gen.pick_sources(p, 256, seed=2)
     for tiled in (0, 1):
-        D, st = byo.msbfs(g, srcs, ms_tiled=tiled)
+        D, st = byo.msbfs(g, srcs, tiled=tiled)
         D = D.cpu().numpy()
         for j in (0, 63, 64, 200, 255):
             want, _ = og.bfs(int(srcs[j]))

@@ -59,7 +59,7 @@ def test_msbfs_tiled_matches_oracle(pi, k):
     rng = np.random.default_rng(100 + k)
     srcs = rng.integers(0, og.n, k)
     srcs[0] = srcs[-1]
-    D, st = byo.msbfs(g, srcs, ms_tiled=1)
+    D, st = byo.msbfs(g, srcs, tiled=1)
     want = og.msbfs(srcs)
     assert np.array_equal(D.cpu().numpy(), want), (pi, k)
     assert st["reached"] == int((want != 255).sum())
@@ -75,7 +75,7 @@ def test_msbfs_tiled_after_pagerank_layout_change():
     g, og = build(p)
     srcs = gen.pick_sources(p, 100, seed=3)
     byo.pagerank(g, 0.85, 2, pr_blocked=14)
-    D, _ = byo.msbfs(g, srcs, ms_tiled=1)
+    D, _ = byo.msbfs(g, srcs, tiled=1)
     assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs))
     r, _ = byo.pagerank(g, 0.85, 5, pr_blocked=1)
     r64 = og.pagerank(0.85, 5)

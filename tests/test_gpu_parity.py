@@ -119,6 +119,29 @@ def test_pagerank_tiled_layout(layout, iters):
     assert np.max(np.abs(r32.cpu().numpy() - r64)) / np.max(np.abs(r64)) < PR_TOL
 
 
+TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7)]
+
+
+@pytest.mark.parametrize("shortcut", [1, 0])
+@pytest.mark.parametrize("pi", range(len(TILED)))
+def test_cc_tiled_matches_oracle(pi, shortcut):
+    """Connectivity over the tile layout: minimum original ID per component
+    (many components and isolated vertices in the sparse RMAT)."""
+    p = TILED[pi]
+    g, og = build(p)
+    lab, st = byo.cc(g, tiled=1, cc_shortcut=shortcut)
+    want = og.cc()
+    assert np.array_equal(lab.cpu().numpy(), want), (pi, shortcut)
+    assert st["levels"] >= 1
+
+
+def test_cc_tiled_round_cap():
+    g, _ = build(TILED[2])
+    with pytest.raises(byo.ByoError) as e:
+        byo.cc(g, tiled=1, max_levels=1, cc_shortcut=0)
+    assert e.value.status == -4
+
+
 def test_bfs_repeat_deterministic_depths():
     p = SUITE[1]
     g, og = build(p)
