@@ -1,15 +1,15 @@
 """Benchmark: GTEPS of the edgeMap hot path on RMAT scale 22 (one MI355X).
 
 One step = multi-source BFS from 256 sources (bit-parallel batch) + PageRank
-(20 steps, FP32) + connectivity (learned variant selector), all on the same
-HBM-resident graph. TEPS
+(20 steps, FP32) + connectivity, all on the same HBM-resident graph. TEPS
 conventions:
   BFS: undirected edges in the reached component, summed over sources (Graph500),
   PageRank: iterations x m directed edges, connectivity: m/2 undirected edges.
 value = all traversed edges of the timed steps / their wall time.
-PageRank and the multi-source BFS run over the degree-ordered tile layout,
-built once per graph on first use and kept with it like the CSR (its build
-time is reported in "detail"; `--no-tiles` runs them over the CSR instead).
+PageRank, the multi-source BFS and connectivity run over the degree-ordered
+tile layout, built once per graph on first use and kept with it like the CSR
+(its build time is reported in "detail"; `--no-tiles` runs them over the CSR
+instead, connectivity then with the learned variant selector).
 Single-source BFS from 16 sources is timed separately, with the threshold
 heuristic ("plain") and with the learned selector, and reported in "detail"
 next to the batched rate.
@@ -258,7 +258,7 @@ def main():
         ev[1].record()
         byo.pagerank(g, 0.85, args.pr_iters, opts=tiled, rank=rank)
         ev[2].record()
-        _, cst = byo.cc(g, opts=mlp_opts, label=label)
+        _, cst = byo.cc(g, opts=tiled if not args.no_tiles else mlp_opts, label=label)
         ev[3].record()
         ms_edges = mst["edges"] // 2
         if record is not None:
