@@ -345,7 +345,7 @@ def main():
                 "launches": pr_launches}
     cpu = None if args.no_cpu_baseline else cpu_baseline(pairs, srcs, args)
     out = {
-        "metric": "GTEPS (batched BFS + PageRank + CC edgeMap traversals) on RMAT-22",
+        "metric": f"GTEPS (batched BFS + PageRank + CC edgeMap traversals) on RMAT-{args.scale}",
         "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32+f32", "data": "synthetic",

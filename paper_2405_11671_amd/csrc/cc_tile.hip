@@ -25,19 +25,19 @@ constexpr int CT_ILP = 16;
 constexpr int CT_APPLY = 256;
 
 template <int SHIFT>
-__global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const int32_t *__restrict__ esrc,
-                                                             const uint16_t *__restrict__ edst,
+__global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const uint32_t *__restrict__ ent,
+                                                             const int32_t *__restrict__ anchor,
                                                              const int64_t *__restrict__ cbeg,
                                                              const int32_t *__restrict__ lab,
                                                              const uint64_t *__restrict__ abits,
                                                              int32_t *__restrict__ partial,
                                                              uint32_t *__restrict__ cflag) {
   constexpr int B = 1 << SHIFT;
-  __shared__ int32_t acc[B];
+  __shared__ int32_t acc[B + 1];  // slot B takes the padding entries
   __shared__ int s_any;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
-  for (int i = t; i < B; i += CT_THREADS) acc[i] = INT_MAX;
+  for (int i = t; i <= B; i += CT_THREADS) acc[i] = INT_MAX;
   if (t == 0) s_any = 0;
   __syncthreads();
   const int64_t beg = cbeg[c], end = cbeg[c + 1];
@@ -50,8 +50,7 @@ __global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const int32_t *__re
     for (int j = 0; j < CT_ILP; ++j) {
       int64_t i = e0 + (int64_t)j * CT_THREADS;
       i = i < end ? i : beg;  // a chunk is never empty
-      u[j] = esrc[i];
-      d[j] = (uint32_t)edst[i];
+      tile_entry(ent, anchor, i, u[j], d[j]);
     }
 #pragma unroll
     for (int j = 0; j < CT_ILP; ++j) ab[j] = abits[u[j] >> 6];
@@ -186,7 +185,7 @@ static void cc_round(const byo_tiles *t, int32_t *lab, const uint64_t *abits, ui
                      byo_counters *ctr, int64_t n, hipStream_t s) {
   {
     ktimer_scope kt(BYO_K_CC_PULL, s);
-    cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->esrc, t->edst, t->cbeg, lab, abits,
+    cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, lab, abits,
                                                                      (int32_t *)t->partial, t->cflag);
     cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>(
         (const int32_t *)t->partial, t->cflag, t->bfirst, lab, abits_next, n, ctr);

@@ -205,12 +205,16 @@ void ms_release(byo_workspace &ws);
 constexpr int BYO_TILE_SHIFT = 12;
 struct byo_tiles {
   int shift = 0;
-  int64_t n = 0, m = 0, nblk = 0, nchunks = 0;
-  int32_t *esrc = nullptr;    // [m] relabelled source of each entry
-  uint16_t *edst = nullptr;   // [m] relabelled destination minus its tile's first vertex
+  int64_t n = 0, m = 0, mp = 0, nblk = 0, nchunks = 0;
+  // mp entries in 64-entry groups (a group's sources lie within 2^16 of its
+  // anchor; unused places are padding with destination 2^shift, a slot no
+  // vertex uses). Entry e: source = anchor[e / 64] + (ent[e] & 0xffff),
+  // tile-local destination = ent[e] >> 16; sources ascend inside a tile.
+  uint32_t *ent = nullptr;    // [mp]
+  int32_t *anchor = nullptr;  // [mp / 64]
   int32_t *rdeg = nullptr;    // [n] degree by relabelled vertex
   int32_t *orig = nullptr;    // [n] original ID of each relabelled vertex
-  int64_t *cbeg = nullptr;    // [nchunks + 1] entry range of each chunk (never straddles tiles)
+  int64_t *cbeg = nullptr;    // [nchunks + 1] entry range of each chunk (whole groups, never straddles tiles)
   int32_t *bfirst = nullptr;  // [nblk + 1] first chunk of each tile
   int32_t *cblk = nullptr;    // [nchunks] tile of each chunk
   uint32_t *cflag = nullptr;  // [nchunks] per-level "chunk produced something" flags
@@ -220,6 +224,16 @@ struct byo_tiles {
   size_t partial_bytes = 0;
   std::vector<int32_t> h_label;  // relabelled ID of each original vertex (host copy)
 };
+// Relabelled source and tile-local destination of entry e. The caller's
+// wavefront reads one whole group (e / 64 is the same in every lane), so the
+// anchor is fetched once, through the scalar unit.
+__device__ __forceinline__ void tile_entry(const uint32_t *__restrict__ ent, const int32_t *__restrict__ anchor,
+                                           int64_t e, int32_t &src, uint32_t &dst) {
+  const uint32_t x = ent[e];
+  const int32_t g = __builtin_amdgcn_readfirstlane((int32_t)(e >> 6));
+  dst = x >> 16;
+  src = anchor[g] + (int32_t)(x & 0xffffu);
+}
 bool tiles_wanted(const byo_graph *g);  // n >= 2^16 and m >= 4n
 byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s);
 byo_status tiles_partial(byo_tiles *t, size_t bytes_per_chunk);

@@ -342,8 +342,8 @@ __device__ __forceinline__ void load_mask(const uint64_t *__restrict__ m, int64_
 }
 
 template <int W>
-__global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__restrict__ esrc,
-                                                             const uint16_t *__restrict__ edst,
+__global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__restrict__ ent,
+                                                             const int32_t *__restrict__ anchor,
                                                              const int64_t *__restrict__ cbeg,
                                                              const int32_t *__restrict__ cblk,
                                                              const uint64_t *__restrict__ front,
@@ -353,16 +353,16 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__re
                                                              uint32_t *__restrict__ cflag) {
   constexpr int B = 1 << MT_SHIFT;
   __shared__ uint64_t acc[B * W];
-  __shared__ uint64_t need[B / 64];
+  __shared__ uint64_t need[B / 64 + 1];  // word B / 64 (padding entries) stays 0
   __shared__ int s_any;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
   const int64_t tile = cblk[c];
   for (int i = t; i < B * W; i += MT_THREADS) acc[i] = 0ull;
   if (t == 0) s_any = 0;
-  if (t < B / 64) {
+  if (t <= B / 64) {
     int64_t wd = (tile << (MT_SHIFT - 6)) + t;
-    need[t] = wd < words ? ~fbits[wd] : 0ull;
+    need[t] = (t < B / 64 && wd < words) ? ~fbits[wd] : 0ull;
   }
   __syncthreads();
   const int64_t beg = cbeg[c], end = cbeg[c + 1];
@@ -375,8 +375,7 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__re
   for (int j = 0; j < MT_ILP; ++j) {
     int64_t i = beg + t + (int64_t)j * MT_THREADS;
     i = i < end ? i : beg;  // a chunk is never empty
-    un[j] = esrc[i];
-    dn[j] = (uint32_t)edst[i];
+    tile_entry(ent, anchor, i, un[j], dn[j]);
   }
   for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)MT_THREADS * MT_ILP) {
     int32_t u[MT_ILP];
@@ -394,8 +393,7 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const int32_t *__re
     for (int j = 0; j < MT_ILP; ++j) {
       int64_t i = e1 + (int64_t)j * MT_THREADS;
       i = i < end ? i : beg;
-      un[j] = esrc[i];
-      dn[j] = (uint32_t)edst[i];
+      tile_entry(ent, anchor, i, un[j], dn[j]);
     }
     bool ok[MT_ILP];
     bool some = false;
@@ -607,7 +605,8 @@ static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *d
   int nx = 1 - cur;
   {
     ktimer_scope kt(BYO_K_MSBFS_PULL, s);
-    ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->esrc, t->edst, t->cbeg, t->cblk, mw.front[cur],
+    ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, t->cblk,
+                                                                 mw.front[cur],
                                                                  mw.abits[cur], mw.tbits, words,
                                                                  (uint64_t *)t->partial, t->cflag);
   }

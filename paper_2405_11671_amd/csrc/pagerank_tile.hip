@@ -36,18 +36,18 @@ __device__ __forceinline__ unsigned long long to_fixed(float x) {
 // partials of the previous apply (or of the initialisation) into
 // base = (1-d)/n + d*D/n, in double and in a fixed order.
 template <int SHIFT>
-__global__ void __launch_bounds__(PT_THREADS) pr_tile_kernel(const int32_t *__restrict__ esrc,
-                                                             const uint16_t *__restrict__ edst,
+__global__ void __launch_bounds__(PT_THREADS) pr_tile_kernel(const uint32_t *__restrict__ ent,
+                                                             const int32_t *__restrict__ anchor,
                                                              const int64_t *__restrict__ cbeg,
                                                              const float *__restrict__ contrib,
                                                              unsigned long long *__restrict__ partial,
                                                              const float *__restrict__ dpart, int64_t nparts,
                                                              double damping, int64_t n, float *__restrict__ base) {
   constexpr int B = 1 << SHIFT;
-  __shared__ unsigned long long acc[B];
+  __shared__ unsigned long long acc[B + 1];  // slot B takes the padding entries
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
-  for (int i = t; i < B; i += PT_THREADS) acc[i] = 0ull;
+  for (int i = t; i <= B; i += PT_THREADS) acc[i] = 0ull;
   if (c == 0) {
     double s = 0.0;
     for (int64_t i = t; i < nparts; i += PT_THREADS) s += (double)dpart[i];
@@ -69,8 +69,7 @@ __global__ void __launch_bounds__(PT_THREADS) pr_tile_kernel(const int32_t *__re
     for (int j = 0; j < PT_ILP; ++j) {
       int64_t i = e0 + (int64_t)j * PT_THREADS;
       i = i < end ? i : beg;
-      u[j] = esrc[i];
-      d[j] = (uint32_t)edst[i];
+      tile_entry(ent, anchor, i, u[j], d[j]);
     }
 #pragma unroll
     for (int j = 0; j < PT_ILP; ++j) x[j] = contrib[u[j]];
@@ -132,7 +131,7 @@ static void launch_step(const byo_tiles *p, const byo_graph *g, const float *con
   {
     ktimer_scope kt(BYO_K_PR_PULL, s);
     pr_tile_kernel<SHIFT><<<(unsigned)p->nchunks, PT_THREADS, 0, s>>>(
-        p->esrc, p->edst, p->cbeg, contrib, (unsigned long long *)p->partial, dpart, nparts, (double)damping, g->n,
+        p->ent, p->anchor, p->cbeg, contrib, (unsigned long long *)p->partial, dpart, nparts, (double)damping, g->n,
         base);
   }
   ktimer_scope ka(BYO_K_PR_CHUNK, s);

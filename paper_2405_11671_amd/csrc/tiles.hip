@@ -14,8 +14,10 @@
 //    chunks over the graph), one workgroup each.
 // A workgroup keeps its tile's accumulators in LDS; its lanes read
 // consecutive entries, whose sources are close together, so a wavefront's
-// gathers fall in few cache lines. An entry costs a 4-byte source and a
-// 2-byte tile-local destination, streamed.
+// gathers fall in few cache lines. An entry is one 32-bit word: a 16-bit
+// offset of its source from its 64-entry group's anchor and its 16-bit
+// tile-local destination; a wavefront's load is one group, so the anchor is
+// one scalar load.
 #include <algorithm>
 #include <thread>
 #include <vector>
@@ -29,8 +31,8 @@ bool tiles_wanted(const byo_graph *g) { return g->n >= (1ll << 16) && g->m >= 4 
 void tiles_release(byo_workspace &w) {
   if (!w.tiles) return;
   byo_tiles *p = w.tiles;
-  void *d[] = {p->esrc, p->edst, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->rlabel, p->scratch,
-               p->partial};
+  void *d[] = {p->ent, p->anchor, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->rlabel,
+               p->scratch, p->partial};
   for (void *x : d)
     if (x) (void)hipFree(x);
   delete p;
@@ -146,33 +148,92 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   build_tiles_host(off, nbr, n, shift, esrc, edst, tile_off, rdeg, orig, label);
   std::vector<int32_t>().swap(nbr);
   const int64_t nblk = (int64_t)tile_off.size() - 1;
-  const int64_t target = std::max<int64_t>(1 << 16, (m + 511) / 512);
+  // Pack each tile into 64-entry groups. A group holds up to 64 consecutive
+  // entries whose sources lie within 2^16 of the first (the group's anchor);
+  // the rest of a group that cannot take the next entry is padding pointing
+  // at the dummy slot 2^shift. Each entry is one word: its source's 16-bit
+  // offset from the anchor and its 16-bit tile-local destination.
+  const uint32_t dummy = 1u << shift;
+  unsigned T = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+  if (m < (1 << 20)) T = 1;
+  std::vector<int64_t> b0(T + 1, nblk);  // tile ranges of about m / T entries
+  b0[0] = 0;
+  for (unsigned t = 1; t < T; ++t)
+    b0[t] = std::upper_bound(tile_off.begin(), tile_off.end(), m * (int64_t)t / (int64_t)T) - tile_off.begin() - 1;
+  for (unsigned t = 1; t <= T; ++t) b0[t] = std::max(b0[t], b0[t - 1]);
+  auto run = [&](auto fn) {
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < T; ++t) th.emplace_back(fn, t);
+    for (auto &x : th) x.join();
+  };
+  // end of the group that starts at entry i of a tile ending at hi
+  auto group_end = [&](int64_t i, int64_t hi) {
+    const int64_t lim = std::min(hi, i + 64);
+    const int32_t a = esrc[(size_t)i];
+    int64_t j = i + 1;
+    while (j < lim && (int64_t)esrc[(size_t)j] - a <= 65535) ++j;
+    return j;
+  };
+  std::vector<int64_t> ngrp((size_t)nblk, 0);
+  run([&](unsigned t) {
+    for (int64_t b = b0[t]; b < b0[t + 1]; ++b)
+      for (int64_t i = tile_off[b]; i < tile_off[b + 1]; i = group_end(i, tile_off[b + 1])) ngrp[(size_t)b]++;
+  });
+  std::vector<int64_t> ptile((size_t)nblk + 1, 0);
+  for (int64_t b = 0; b < nblk; ++b) ptile[b + 1] = ptile[b] + 64 * ngrp[(size_t)b];
+  const int64_t mp = ptile[nblk], ngroups = mp / 64;
+  BYO_CHECK(ngroups < ((int64_t)1 << 31), BYO_EINVAL, "too many entry groups");
+  std::vector<uint32_t> ent((size_t)mp);
+  std::vector<int32_t> anchor((size_t)ngroups);
+  run([&](unsigned t) {
+    for (int64_t b = b0[t]; b < b0[t + 1]; ++b) {
+      int64_t q = ptile[b];
+      for (int64_t i = tile_off[b], hi = tile_off[b + 1]; i < hi;) {
+        const int64_t j = group_end(i, hi);
+        const int32_t a = esrc[(size_t)i];
+        anchor[(size_t)(q / 64)] = a;
+        for (int64_t r = 0; r < 64; ++r) {
+          const int64_t x = i + r;
+          ent[(size_t)(q + r)] = x < j ? ((uint32_t)(esrc[(size_t)x] - a) | ((uint32_t)edst[(size_t)x] << 16))
+                                       : (dummy << 16);
+        }
+        q += 64;
+        i = j;
+      }
+    }
+  });
+  std::vector<int32_t>().swap(esrc);
+  std::vector<uint16_t>().swap(edst);
+  // chunks: about 512 over the whole entry set, each tile cut into equal
+  // pieces of whole groups
+  const int64_t target = std::max<int64_t>(1 << 16, (mp + 511) / 512);
   std::vector<int64_t> cbeg;
   std::vector<int32_t> bfirst((size_t)nblk + 1), cblk;
   for (int64_t b = 0; b < nblk; ++b) {
     bfirst[b] = (int32_t)cbeg.size();
-    int64_t lo = tile_off[b], hi = tile_off[b + 1], len = hi - lo;
-    if (len == 0) continue;
-    int64_t k = (len + target - 1) / target;
+    int64_t lo = ptile[b], groups = (ptile[b + 1] - lo) / 64;
+    if (groups == 0) continue;
+    int64_t k = (groups * 64 + target - 1) / target;
     for (int64_t i = 0; i < k; ++i) {
-      cbeg.push_back(lo + len * i / k);
+      cbeg.push_back(lo + 64 * (groups * i / k));
       cblk.push_back((int32_t)b);
     }
   }
   bfirst[nblk] = (int32_t)cbeg.size();
   const int64_t nchunks = (int64_t)cbeg.size();
-  cbeg.push_back(m);
+  cbeg.push_back(mp);
 
   byo_tiles *p = new byo_tiles();
   p->shift = shift;
   p->n = n;
   p->m = m;
+  p->mp = mp;
   p->nblk = nblk;
   p->nchunks = nchunks;
   p->h_label = std::move(label);
   w.tiles = p;
-  BYO_HIP(hipMalloc(&p->esrc, sizeof(int32_t) * (size_t)m));
-  BYO_HIP(hipMalloc(&p->edst, sizeof(uint16_t) * (size_t)m));
+  BYO_HIP(hipMalloc(&p->ent, sizeof(uint32_t) * (size_t)mp));
+  BYO_HIP(hipMalloc(&p->anchor, sizeof(int32_t) * (size_t)ngroups));
   BYO_HIP(hipMalloc(&p->rdeg, sizeof(int32_t) * (size_t)n));
   BYO_HIP(hipMalloc(&p->orig, sizeof(int32_t) * (size_t)n));
   BYO_HIP(hipMalloc(&p->cbeg, sizeof(int64_t) * cbeg.size()));
@@ -180,8 +241,8 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   BYO_HIP(hipMalloc(&p->cblk, sizeof(int32_t) * (size_t)nchunks));
   BYO_HIP(hipMalloc(&p->cflag, sizeof(uint32_t) * (size_t)nchunks));
   BYO_HIP(hipMalloc(&p->rlabel, sizeof(int32_t) * (size_t)n));
-  BYO_HIP(hipMemcpy(p->esrc, esrc.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->edst, edst.data(), sizeof(uint16_t) * (size_t)m, hipMemcpyHostToDevice));
+  BYO_HIP(hipMemcpy(p->ent, ent.data(), sizeof(uint32_t) * (size_t)mp, hipMemcpyHostToDevice));
+  BYO_HIP(hipMemcpy(p->anchor, anchor.data(), sizeof(int32_t) * (size_t)ngroups, hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->rdeg, rdeg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->orig, orig.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->cbeg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice));
