@@ -81,6 +81,70 @@ __device__ __forceinline__ void write_depths(uint8_t *__restrict__ depth, int64_
   }
 }
 
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+  uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Wavefront-cooperative form of write_depths, called by every lane of the
+// wavefront with its own vertex's row index, new bits nb (all zero when the
+// vertex gained nothing) and previously seen bits sv. Rows are written four at
+// a time, sixteen lanes per row and one 16-source group per lane, so a store
+// instruction covers four 256-byte rows instead of 64 scattered 16-byte
+// pieces. Needs k a multiple of 16 (k <= 256) and a 16-byte aligned array.
+template <int W>
+__device__ void write_depths_wave(uint8_t *__restrict__ depth, int32_t k, int64_t row, const uint64_t *nb,
+                                  const uint64_t *sv, uint8_t d) {
+  bool mine = false;
+#pragma unroll
+  for (int w = 0; w < W; ++w) mine |= nb[w] != 0;
+  const uint64_t anym = __ballot(mine);
+  if (!anym) return;
+  const int lane = lane_id(), g = lane & 15, q = lane >> 4;
+  const uint32_t splat = 0x01010101u * d;
+  for (int r = 0; r < 16; ++r) {
+    if (!((anym >> (4 * r)) & 0xFull)) continue;  // none of these four rows gained anything
+    const int sl = 4 * r + q;
+    uint64_t nw = 0, so = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t a = shfl_u64(nb[w], sl), b = shfl_u64(sv[w], sl);
+      if ((g >> 2) == w) {
+        nw = a;
+        so = b;
+      }
+    }
+    const int64_t rw = (int64_t)shfl_u64((uint64_t)row, sl);
+    uint32_t bits = (uint32_t)(nw >> (16 * (g & 3))) & 0xFFFFu;
+    if (!bits || 16 * g >= k) continue;
+    const uint32_t old = (uint32_t)(so >> (16 * (g & 3))) & 0xFFFFu;
+    uint4 *p = (uint4 *)(depth + rw * k + 16 * g);
+    uint4 x;
+    if (bits == 0xFFFFu) {
+      x.x = x.y = x.z = x.w = splat;
+    } else {
+      if (old) {
+        x = *p;
+      } else {
+        x.x = x.y = x.z = x.w = 0xFFFFFFFFu;
+      }
+      uint32_t c[4] = {x.x, x.y, x.z, x.w};
+      while (bits) {
+        int j = __ffs(bits) - 1;
+        bits &= bits - 1;
+        uint32_t sh = 8u * (uint32_t)(j & 3);
+        c[j >> 2] = (c[j >> 2] & ~(0xFFu << sh)) | ((uint32_t)d << sh);
+      }
+      x.x = c[0];
+      x.y = c[1];
+      x.z = c[2];
+      x.w = c[3];
+    }
+    *p = x;
+  }
+}
+
 // Dense level: every vertex that has not seen all sources ORs its
 // neighbours' frontier masks (serial with ILP for short lists, wavefront-
 // parallel beyond t_wave), stopping once its mask is full.
@@ -444,11 +508,16 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
     full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
   }
   unsigned long long degsum = 0, count = 0;
+  const bool vec_depth = (k & 15) == 0 && ((uintptr_t)depth & 15) == 0;
   // capped grid: a few thousand counter atomics per level, not one per 256 vertices
   for (int64_t base = (int64_t)blockIdx.x * MS_BLOCK; base < n; base += (int64_t)gridDim.x * MS_BLOCK) {
     const int64_t v = base + threadIdx.x;
     const bool valid = v < n;
     bool any = false, now_full = true;
+    uint64_t nb[W], sv[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) nb[w] = sv[w] = 0ull;
+    int64_t row = 0;
     if (valid) {
       if ((abits_cur[v >> 6] >> (v & 63)) & 1ull) {
 #pragma unroll
@@ -488,7 +557,6 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
         bool got = false;
 #pragma unroll
         for (int w = 0; w < W; ++w) got |= a[w] != 0;
-        uint64_t nb[W], sv[W];
         if (got) {  // else nothing reached v and its full bit stays clear
           now_full = true;
 #pragma unroll
@@ -505,11 +573,18 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
             seen[v * W + w] = sv[w] | nb[w];
             front_next[v * W + w] = nb[w];
           }
-          write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
+          row = orig[v];
           degsum += (unsigned long long)rdeg[v];
+        } else {
+#pragma unroll
+          for (int w = 0; w < W; ++w) nb[w] = 0ull;
         }
       }
     }
+    if (vec_depth)
+      write_depths_wave<W>(depth, k, row, nb, sv, newdepth);  // every lane of the wavefront
+    else if (any)
+      write_depths<W>(depth, row, k, nb, sv, newdepth);
     uint64_t am = __ballot(any);
     uint64_t fm = __ballot(now_full);  // vertices past n count as full
     if (lane_id() == 0 && v < n) {

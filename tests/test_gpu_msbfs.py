@@ -49,7 +49,7 @@ def test_msbfs_fixed_variants(variant):
 TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7)]
 
 
-@pytest.mark.parametrize("k", [1, 7, 64, 65, 200, 256])
+@pytest.mark.parametrize("k", [1, 7, 64, 65, 150, 200, 256])
 @pytest.mark.parametrize("pi", range(len(TILED)))
 def test_msbfs_tiled_matches_oracle(pi, k):
     """Tile-layout levels (degree-relabelled, 2^12-vertex tiles, several
