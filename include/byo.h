@@ -82,8 +82,10 @@ typedef struct byo_opts {
   int32_t t_block;        /* PUSH_BUCKET: degree >= t_block goes to a workgroup (default 4096) */
   int32_t max_levels;     /* BFS level / CC round cap; 0 = n + 1 */
   int32_t cc_shortcut;    /* CC: pointer-jumping pass after each round (default 1) */
-  int32_t small_frontier; /* frontiers at most this size run in the device-resident
-                             single-workgroup loop (0 = off; default 0) */
+  int32_t small_frontier; /* BFS: frontiers of at most this many vertices (and at most
+                             max(16 x this, 2^16) edges, capped at 2^17) run in the
+                             device-resident loop: one cooperative kernel of 64
+                             workgroups, grid barriers between levels (0 = off; default 0) */
   int32_t pr_blocked;     /* PageRank layout: 0 = pull over the CSR (default); 1 = entries
                              regrouped by destination tile of 2^14 degree-ordered vertices,
                              exact fixed-point sums in LDS; 12..14 = tiles of 2^value.

@@ -154,6 +154,7 @@ void ws_free(byo_workspace &w) {
   ms_release(w);
   tiles_release(w);
   gm_release(w);
+  dl_release(w);
   w = byo_workspace();
 }
 

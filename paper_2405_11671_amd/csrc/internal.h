@@ -163,6 +163,7 @@ struct byo_workspace {
   void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
   byo::byo_tiles *tiles = nullptr;   // degree-ordered destination-tile layout (tiles.hip)
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
+  void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
 };
 
 struct byo_graph {
@@ -368,9 +369,12 @@ struct small_loop_out {
   bool empty = false;
   int64_t count = 0, degsum = 0, reached = 0, edges = 0;
 };
-byo_status bfs_small_loop(byo_graph *g, const int32_t *in_ids, int64_t k, int32_t level, int32_t max_levels,
-                          int32_t cap_count, int64_t cap_edges, int32_t *parent, int32_t *depth, uint64_t *visited,
-                          int32_t *out0, int32_t *out1, void *d_res, hipStream_t s, small_loop_out *out);
+constexpr int64_t BYO_DLOOP_QCAP = 1 << 17;  // frontier and per-level edge cap of the device-resident loop
+bool bfs_small_loop_usable(byo_graph *g);
+byo_status bfs_small_loop(byo_graph *g, const int32_t *in_ids, int64_t k, int64_t in_degsum, int32_t level,
+                          int32_t max_levels, int64_t cap_count, int64_t cap_edges, int32_t *parent, int32_t *depth,
+                          uint64_t *visited, int32_t *out, hipStream_t s, small_loop_out *res_out);
+void dl_release(byo_workspace &w);
 
 // BFS with device-side level control replayed from a hipGraph (graphmode.hip)
 byo_status bfs_graph_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,

@@ -246,14 +246,16 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "BFS level cap reached");
     }
-    if (o.small_frontier > 0 && fr.k <= o.small_frontier && fr.k <= 8192) {
+    const int64_t dl_edges = std::min<int64_t>(std::max<int64_t>(16 * (int64_t)o.small_frontier, 65536),
+                                               BYO_DLOOP_QCAP);
+    if (o.small_frontier > 0 && fr.k <= o.small_frontier && fr.k <= BYO_DLOOP_QCAP && fr.degsum <= dl_edges &&
+        bfs_small_loop_usable(g)) {
       // run levels on the device while the frontier stays small
       BYO_TRY(make_sparse(g, fr, s));
       small_loop_out r;
-      int32_t budget = (int32_t)std::min<int64_t>(cap - level, 1024);
-      int64_t edge_cap = std::max<int64_t>(16 * (int64_t)o.small_frontier, 65536);
-      BYO_TRY(bfs_small_loop(g, w.ids[fr.cur], fr.k, level, budget, o.small_frontier, edge_cap, d_parent, d_depth,
-                             w.visited, w.ids[1 - fr.cur], w.ids[fr.cur], w.misc, s, &r));
+      int32_t budget = (int32_t)std::min<int64_t>(cap - level, 1 << 20);
+      BYO_TRY(bfs_small_loop(g, w.ids[fr.cur], fr.k, fr.degsum, level, budget, o.small_frontier, dl_edges, d_parent,
+                             d_depth, w.visited, w.ids[1 - fr.cur], s, &r));
       level += r.levels;
       st.device_levels += r.levels;
       st.variant_count[BYO_V_PUSH_BUCKET] += r.levels;

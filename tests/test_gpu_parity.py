@@ -281,7 +281,7 @@ def test_bfs_level_cap_and_bad_source():
 @pytest.mark.parametrize("cap", [1, 64, 1000, 8192])
 @pytest.mark.parametrize("p", SUITE, ids=IDS)
 def test_bfs_device_resident_small_frontier(p, cap):
-    """Levels run inside one workgroup while |U| <= cap; results stay exact."""
+    """Levels run in the device-resident loop while |U| <= cap; results stay exact."""
     g, og = build(p)
     for s in sources(p, og):
         depth, parent, st = byo.bfs(g, s, small_frontier=cap)
