@@ -31,6 +31,17 @@ def two_hubs(n=20000, hub_deg=9000, seed=11):
     return pairs(n, np.concatenate([a, bg.src]), np.concatenate([b, bg.dst]), "two_hubs")
 
 
+def hub_over_er(leaves=70000, avg_degree=8.0, seed=13):
+    """A star with `leaves` leaves on top of an ER graph over the leaves: one
+    vertex above the 16-bit tile-local range of entries, and m >= 4n, so the
+    degree-ordered tile layout applies."""
+    n = leaves + 1
+    bg = gen.er_pairs(leaves, avg_degree, seed=seed)
+    src = np.concatenate([np.zeros(leaves, np.int64), bg.src.astype(np.int64) + 1])
+    dst = np.concatenate([np.arange(1, n), bg.dst.astype(np.int64) + 1])
+    return pairs(n, src, dst, f"hub{leaves}_er{avg_degree:g}")
+
+
 def small_suite():
     """Graphs that finish in the oracle in well under a second."""
     return [

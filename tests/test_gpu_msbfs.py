@@ -46,7 +46,8 @@ def test_msbfs_fixed_variants(variant):
     assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs))
 
 
-TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7)]
+TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7),
+         graphs.hub_over_er()]
 
 
 @pytest.mark.parametrize("k", [1, 7, 64, 65, 150, 200, 256])

@@ -119,7 +119,8 @@ def test_pagerank_tiled_layout(layout, iters):
     assert np.max(np.abs(r32.cpu().numpy() - r64)) / np.max(np.abs(r64)) < PR_TOL
 
 
-TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7)]
+TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.rmat_pairs(17, 4, seed=7),
+         graphs.hub_over_er()]
 
 
 @pytest.mark.parametrize("shortcut", [1, 0])
