@@ -221,6 +221,8 @@ struct byo_tiles {
   uint32_t *cflag = nullptr;  // [nchunks] per-level "chunk produced something" flags
   int32_t *rlabel = nullptr;  // [n] relabelled ID of each original vertex
   int32_t *scratch = nullptr; // [n] per-vertex work array (tiles_scratch)
+  int64_t *roff = nullptr;    // [n + 1] CSR in relabelled IDs: row w is row orig[w]
+  int32_t *rnbr = nullptr;    // [m] its neighbours, relabelled
   void *partial = nullptr;    // chunk results, sized by the user (tiles_partial)
   size_t partial_bytes = 0;
   std::vector<int32_t> h_label;  // relabelled ID of each original vertex (host copy)

@@ -650,6 +650,7 @@ struct ms_ws {
   int W = 0;
   uint64_t *seen = nullptr, *front[2] = {nullptr, nullptr}, *visit = nullptr, *tbits = nullptr;
   uint64_t *abits[2] = {nullptr, nullptr};
+  uint64_t *fbits = nullptr;  // tiled levels: vertices that have seen every source
   int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr, *rsrcs = nullptr;
   byo_counters *ctr = nullptr;
   unsigned long long *tally = nullptr;
@@ -657,7 +658,7 @@ struct ms_ws {
 
 static void ms_free(ms_ws &m) {
   void *p[] = {m.seen, m.front[0], m.front[1], m.visit, m.tbits, m.touched, m.active[0], m.active[1], m.srcs,
-               m.rsrcs, m.ctr, m.tally, m.abits[0], m.abits[1]};
+               m.rsrcs, m.ctr, m.tally, m.abits[0], m.abits[1], m.fbits};
   for (void *x : p)
     if (x) (void)hipFree(x);
   m = ms_ws();
@@ -673,6 +674,103 @@ void ms_release(byo_workspace &w) {
 }
 
 
+// After a push level in the layout's order: fold visit[v] into seen and the
+// next frontier for every touched v, write depths in the caller's order, set
+// the frontier and "full" bitmaps, clear the touched bits, count.
+template <int W>
+__global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
+    const int32_t *__restrict__ touched, const byo_counters *__restrict__ tctr, const int32_t *__restrict__ rdeg,
+    const int32_t *__restrict__ orig, uint64_t *__restrict__ visit, uint64_t *__restrict__ seen,
+    uint64_t *__restrict__ front_next, uint64_t *__restrict__ touched_bits, uint64_t *__restrict__ abits_next,
+    uint64_t *__restrict__ fbits, uint8_t *__restrict__ depth, int32_t k, uint8_t newdepth,
+    byo_counters *__restrict__ ctr) {
+  uint64_t full[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    int bits = k - 64 * w;
+    full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
+  }
+  const int64_t cnt = (int64_t)tctr->count;
+  unsigned long long degsum = 0, count = 0;
+  for (int64_t i = (int64_t)blockIdx.x * MS_BLOCK + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * MS_BLOCK) {
+    const int32_t v = touched[i];
+    uint64_t nb[W], sv[W];
+    bool any = false, now_full = true;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t x = visit[(int64_t)v * W + w];
+      visit[(int64_t)v * W + w] = 0ull;
+      sv[w] = seen[(int64_t)v * W + w];
+      nb[w] = x & ~sv[w];
+      any |= nb[w] != 0;
+      now_full &= (sv[w] | nb[w]) == full[w];
+    }
+    const uint64_t bit = 1ull << (v & 63);
+    if (any) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        seen[(int64_t)v * W + w] = sv[w] | nb[w];
+        front_next[(int64_t)v * W + w] = nb[w];
+      }
+      write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
+      degsum += (unsigned long long)rdeg[v];
+      count += 1;
+      atomicOr((unsigned long long *)&abits_next[v >> 6], (unsigned long long)bit);
+      if (now_full) atomicOr((unsigned long long *)&fbits[v >> 6], (unsigned long long)bit);
+    }
+    atomicAnd((unsigned long long *)&touched_bits[v >> 6], ~(unsigned long long)bit);
+  }
+  const unsigned long long ts = block_sum<unsigned long long, MS_BLOCK>(degsum);
+  const unsigned long long tc = block_sum<unsigned long long, MS_BLOCK>(count);
+  if (threadIdx.x == 0) {
+    if (ts) atomicAdd(&ctr->degsum, ts);
+    if (tc) atomicAdd(&ctr->count, tc);
+  }
+}
+
+// The layout's relabelled CSR seen as a graph, for the push kernels. It shares
+// the graph's workspace and is never destroyed or grown.
+static byo_graph relabelled_view(const byo_graph *g, const byo_tiles *t) {
+  byo_graph r = *g;
+  r.off = t->roff;
+  r.nbr = t->rnbr;
+  r.deg = t->rdeg;
+  return r;
+}
+
+template <int W>
+static byo_status launch_tile_push(byo_graph *g, const byo_tiles *t, ms_ws &mw, int cur, int64_t acount,
+                                   long long adeg, uint8_t *depth, int32_t k, uint8_t nd, byo_counters *tctr,
+                                   byo_counters *ctr, const byo_opts &o, hipStream_t s) {
+  const int64_t n = g->n, words = (n + 63) / 64;
+  const int nx = 1 - cur;
+  byo_workspace &w = g->ws;
+  // active list from the frontier bitmap, then push over the relabelled CSR
+  BYO_TRY(bitmap_to_ids(mw.abits[cur], words, n, mw.active[cur], w.partial, w.partial_cap,
+                        (unsigned long long *)w.misc, s));
+  byo_graph rg = relabelled_view(g, t);
+  level_io io;
+  std::memset(&io, 0, sizeof(io));
+  io.in_ids = mw.active[cur];
+  io.in_count = acount;
+  io.out_ids = mw.touched;
+  io.out_bits = mw.tbits;
+  io.ctr = tctr;
+  ms_state ms{W, mw.front[cur], mw.seen, mw.visit};
+  BYO_TRY(ms_push_level(&rg, BYO_V_PUSH_EDGE, ms, io, o, s, adeg));
+  BYO_TRY(fill_u64(mw.abits[nx], words, 0ull, s));
+  {
+    ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
+    const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (adeg + MS_BLOCK - 1) / MS_BLOCK), 2048);
+    ms_tile_finish_kernel<W><<<nb, MS_BLOCK, 0, s>>>(mw.touched, tctr, t->rdeg, t->orig, mw.visit, mw.seen,
+                                                     mw.front[nx], mw.tbits, mw.abits[nx], mw.fbits, depth, k, nd,
+                                                     ctr);
+  }
+  launch_clear<W>(mw.active[cur], acount, mw.front[cur], s);  // consumed frontier back to zero
+  BYO_HIP(hipGetLastError());
+  return BYO_OK;
+}
+
 template <int W>
 static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *depth, int32_t k, uint8_t nd,
                               int64_t n, byo_counters *ctr, hipStream_t s) {
@@ -682,20 +780,22 @@ static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *d
     ktimer_scope kt(BYO_K_MSBFS_PULL, s);
     ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, t->cblk,
                                                                  mw.front[cur],
-                                                                 mw.abits[cur], mw.tbits, words,
+                                                                 mw.abits[cur], mw.fbits, words,
                                                                  (uint64_t *)t->partial, t->cflag);
   }
   ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
   ms_tile_apply_kernel<W><<<(unsigned)std::min<int64_t>((n + MS_BLOCK - 1) / MS_BLOCK, 2048), MS_BLOCK, 0, s>>>(
       (const uint64_t *)t->partial, t->cflag, t->bfirst, mw.seen, mw.front[cur], mw.front[nx], mw.abits[cur],
-      mw.abits[nx], mw.tbits, t->rdeg, t->orig, depth, k, nd, n, ctr);
+      mw.abits[nx], mw.fbits, t->rdeg, t->orig, depth, k, nd, n, ctr);
 }
 
-// Every level over the tile layout, in relabelled vertex order. The caller
-// has zeroed seen, both frontier buffers, the full bitmap (tbits) and the
-// counters, and filled depth with 255.
+// Levels in the layout's vertex order, direction-optimising like the CSR
+// path: a push over the relabelled CSR while |U| + sum(deg U) <= m / div,
+// else a pass over the tiles. The caller has zeroed seen, both frontier
+// buffers, the touched and full bitmaps and the counters, and filled depth
+// with 255.
 static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, const std::vector<int32_t> &hs, int32_t k, int W,
-                               uint8_t *d_depth, hipStream_t s, byo_run_stats *stats) {
+                               uint8_t *d_depth, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(tiles_ensure(g, MT_SHIFT, s));
   byo_tiles *t = g->ws.tiles;
   BYO_TRY(tiles_partial(t, sizeof(uint64_t) * (size_t)W << MT_SHIFT));
@@ -706,29 +806,54 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, const std::vector<int32_
   BYO_HIP(hipMemsetAsync(mw.abits[0], 0, sizeof(uint64_t) * (size_t)words, s));
   ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, mw.rsrcs, k, W, mw.seen, mw.front[0], mw.abits[0], d_depth);
   BYO_HIP(hipGetLastError());
+  // first frontier: the distinct sources and their degree sum
+  std::vector<int32_t> act(rs);
+  std::sort(act.begin(), act.end());
+  act.erase(std::unique(act.begin(), act.end()), act.end());
+  int64_t acount = (int64_t)act.size();
+  long long adeg = 0;
+  {
+    byo_graph rg = relabelled_view(g, t);
+    BYO_HIP(hipMemcpyAsync(mw.active[0], act.data(), sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, s));
+    BYO_TRY(frontier_degree_scan(&rg, mw.active[0], acount, g->ws.scan, g->ws.partial, g->ws.partial_cap, s));
+    BYO_TRY(sync_read(s, g->ws.scan + acount, &adeg, sizeof(adeg)));
+  }
+  const int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
   int cur = 0, level = 0;
-  while (true) {
+  while (acount > 0) {
     if (level + 1 >= MS_MAX_LEVELS) {
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "a distance reached 255 (depths are uint8)");
     }
-    uint8_t nd = (uint8_t)(level + 1);
-    byo_counters *ctr = mw.ctr + level;
-    switch (W) {
-      case 1: launch_tile_level<1>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
-      case 2: launch_tile_level<2>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
-      case 3: launch_tile_level<3>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
-      default: launch_tile_level<4>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+    const uint8_t nd = (uint8_t)(level + 1);
+    byo_counters *tctr = mw.ctr + 2 * level, *ctr = mw.ctr + 2 * level + 1;
+    const bool fixed_pull = o.fixed_variant == BYO_V_PULL_THREAD || o.fixed_variant == BYO_V_PULL_WAVE;
+    const bool push = o.selector == BYO_SEL_FIXED ? !fixed_pull : acount + adeg <= g->m / div;
+    if (push) {
+      switch (W) {
+        case 1: BYO_TRY(launch_tile_push<1>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
+        case 2: BYO_TRY(launch_tile_push<2>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
+        case 3: BYO_TRY(launch_tile_push<3>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
+        default: BYO_TRY(launch_tile_push<4>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
+      }
+    } else {
+      switch (W) {
+        case 1: launch_tile_level<1>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+        case 2: launch_tile_level<2>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+        case 3: launch_tile_level<3>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+        default: launch_tile_level<4>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+      }
     }
     BYO_HIP(hipGetLastError());
     byo_counters c;
     BYO_TRY(sync_read(s, ctr, &c, sizeof(c)));
-    st.variant_count[BYO_V_PULL_WAVE]++;
+    st.variant_count[push ? BYO_V_PUSH_EDGE : BYO_V_PULL_WAVE]++;
     ++level;
     cur = 1 - cur;
-    if (c.count == 0) break;
+    acount = (int64_t)c.count;
+    adeg = (long long)c.degsum;
   }
   ms_tally_kernel<<<(unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096), MS_BLOCK, 0, s>>>(
       mw.seen, W, t->rdeg, n, mw.tally);
@@ -770,6 +895,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     BYO_HIP(hipMalloc(&mw.tbits, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
     BYO_HIP(hipMalloc(&mw.abits[0], sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
     BYO_HIP(hipMalloc(&mw.abits[1], sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
+    BYO_HIP(hipMalloc(&mw.fbits, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1)));
     BYO_HIP(hipMalloc(&mw.touched, sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.active[0], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.active[1], sizeof(int32_t) * (size_t)n));
@@ -786,6 +912,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   BYO_HIP(hipMemsetAsync(mw.front[1], 0, vb, s));
   BYO_HIP(hipMemsetAsync(mw.visit, 0, vb, s));
   BYO_HIP(hipMemsetAsync(mw.tbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
+  BYO_HIP(hipMemsetAsync(mw.fbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
   BYO_HIP(hipMemsetAsync(mw.ctr, 0, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1), s));
   BYO_HIP(hipMemsetAsync(mw.tally, 0, sizeof(unsigned long long) * 2, s));
   {
@@ -796,7 +923,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   std::vector<int32_t> hs(k);
   for (int32_t j = 0; j < k; ++j) hs[j] = (int32_t)h_srcs[j];
   BYO_HIP(hipMemcpyAsync(mw.srcs, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
-  if (o.tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, hs, k, W, d_depth, s, stats);
+  if (o.tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, hs, k, W, d_depth, o, s, stats);
   ms_init_kernel<<<1, 256, 0, s>>>(mw.srcs, k, W, mw.seen, mw.front[0], d_depth);
   // first active list: the distinct sources
   std::vector<int32_t> act(hs);

@@ -32,7 +32,7 @@ void tiles_release(byo_workspace &w) {
   if (!w.tiles) return;
   byo_tiles *p = w.tiles;
   void *d[] = {p->ent, p->anchor, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->rlabel,
-               p->scratch, p->partial};
+               p->scratch, p->partial, p->roff, p->rnbr};
   for (void *x : d)
     if (x) (void)hipFree(x);
   delete p;
@@ -146,7 +146,6 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   std::vector<uint16_t> edst;
   std::vector<int64_t> tile_off;
   build_tiles_host(off, nbr, n, shift, esrc, edst, tile_off, rdeg, orig, label);
-  std::vector<int32_t>().swap(nbr);
   const int64_t nblk = (int64_t)tile_off.size() - 1;
   // Pack each tile into 64-entry groups. A group holds up to 64 consecutive
   // entries whose sources lie within 2^16 of the first (the group's anchor);
@@ -249,6 +248,29 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   BYO_HIP(hipMemcpy(p->bfirst, bfirst.data(), sizeof(int32_t) * bfirst.size(), hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->cblk, cblk.data(), sizeof(int32_t) * (size_t)nchunks, hipMemcpyHostToDevice));
   BYO_HIP(hipMemcpy(p->rlabel, p->h_label.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+  // the CSR in relabelled IDs (row w = row orig[w], neighbours relabelled), for
+  // push levels that run in the layout's order
+  {
+    std::vector<int64_t> roff((size_t)n + 1, 0);
+    for (int64_t x = 0; x < n; ++x) roff[(size_t)x + 1] = roff[(size_t)x] + rdeg[(size_t)x];
+    std::vector<int32_t> rnbr((size_t)m);
+    const std::vector<int32_t> &lab = p->h_label;
+    std::vector<int64_t> r0(T + 1, n);  // relabelled row ranges of about m / T entries
+    r0[0] = 0;
+    for (unsigned t = 1; t < T; ++t)
+      r0[t] = std::lower_bound(roff.begin(), roff.end(), m * (int64_t)t / (int64_t)T) - roff.begin();
+    for (unsigned t = 1; t <= T; ++t) r0[t] = std::max(r0[t], r0[t - 1]);
+    run([&](unsigned t) {
+      for (int64_t x = r0[t]; x < r0[t + 1]; ++x) {
+        const int64_t u = orig[(size_t)x], o = off[(size_t)u], d = off[(size_t)u + 1] - o;
+        for (int64_t i = 0; i < d; ++i) rnbr[(size_t)(roff[(size_t)x] + i)] = lab[(size_t)nbr[(size_t)(o + i)]];
+      }
+    });
+    BYO_HIP(hipMalloc(&p->roff, sizeof(int64_t) * (size_t)(n + 1)));
+    BYO_HIP(hipMalloc(&p->rnbr, sizeof(int32_t) * (size_t)m));
+    BYO_HIP(hipMemcpy(p->roff, roff.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice));
+    BYO_HIP(hipMemcpy(p->rnbr, rnbr.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
+  }
   return BYO_OK;
 }
 
