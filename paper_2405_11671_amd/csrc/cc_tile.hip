@@ -90,10 +90,11 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
                                                                  const uint32_t *__restrict__ cflag,
                                                                  const int32_t *__restrict__ bfirst,
                                                                  int32_t *__restrict__ lab,
+                                                                 const int32_t *__restrict__ rdeg,
                                                                  uint64_t *__restrict__ abits_next, int64_t n,
                                                                  byo_counters *__restrict__ ctr) {
   constexpr int B = 1 << SHIFT;
-  unsigned long long count = 0;
+  unsigned long long count = 0, degsum = 0;
   // capped grid: a few thousand counter atomics per round
   for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
     const int64_t w = base + threadIdx.x;
@@ -120,6 +121,7 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
       if (m < lab[w]) {
         lab[w] = m;
         changed = true;
+        degsum += (unsigned long long)rdeg[w];
       }
     }
     uint64_t am = __ballot(changed);
@@ -129,37 +131,51 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
     }
   }
   unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
-  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
+  unsigned long long td = block_sum<unsigned long long, CT_APPLY>(degsum);
+  if (threadIdx.x == 0) {
+    if (tc) atomicAdd(&ctr->count, tc);
+    if (td) atomicAdd(&ctr->degsum, td);
+  }
 }
 
 // Pointer jumping: label x of w becomes the label of vertex x when smaller
 // (x is an original ID; rlabel maps it to the layout's order). Reads of
 // labels being lowered by other threads see either value; both are IDs in
-// the component, so any interleaving is sound.
+// the component, so any interleaving is sound. Vertices it lowers join the
+// next round's frontier; the count covers only bits not already set, so it
+// stays equal to the frontier bitmap's population.
 __global__ void __launch_bounds__(CT_APPLY) cc_tile_jump_kernel(int32_t *__restrict__ lab,
                                                                 const int32_t *__restrict__ rlabel,
+                                                                const int32_t *__restrict__ rdeg,
                                                                 uint64_t *__restrict__ abits_next, int64_t n,
                                                                 byo_counters *__restrict__ ctr) {
-  unsigned long long count = 0;
+  unsigned long long count = 0, degsum = 0;
   for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
     const int64_t w = base + threadIdx.x;
-    bool changed = false;
+    // a vertex already marked this round is counted once: only fresh bits count
+    const uint64_t oldw = w < n ? abits_next[w >> 6] : 0ull;
+    bool fresh = false;
     if (w < n) {
       int32_t x = lab[w];
       int32_t y = lab[rlabel[x]];
       if (y < x) {
         lab[w] = y;
-        changed = true;
+        fresh = !((oldw >> (w & 63)) & 1ull);
+        if (fresh) degsum += (unsigned long long)rdeg[w];
       }
     }
-    uint64_t am = __ballot(changed);
+    const uint64_t am = __ballot(fresh);
     if (lane_id() == 0 && w < n && am) {
-      abits_next[w >> 6] |= am;
+      abits_next[w >> 6] = oldw | am;
       count += (unsigned long long)__popcll(am);
     }
   }
   unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
-  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
+  unsigned long long td = block_sum<unsigned long long, CT_APPLY>(degsum);
+  if (threadIdx.x == 0) {
+    if (tc) atomicAdd(&ctr->count, tc);
+    if (td) atomicAdd(&ctr->degsum, td);
+  }
 }
 
 __global__ void cc_tile_init_kernel(const int32_t *__restrict__ orig, int64_t n, int32_t *__restrict__ lab,
@@ -181,21 +197,19 @@ static unsigned apply_grid(int64_t n) {
 }
 
 template <int SHIFT>
-static void cc_round(const byo_tiles *t, int32_t *lab, const uint64_t *abits, uint64_t *abits_next, bool jump,
-                     byo_counters *ctr, int64_t n, hipStream_t s) {
-  {
-    ktimer_scope kt(BYO_K_CC_PULL, s);
-    cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, lab, abits,
-                                                                     (int32_t *)t->partial, t->cflag);
-    cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>(
-        (const int32_t *)t->partial, t->cflag, t->bfirst, lab, abits_next, n, ctr);
-  }
-  if (jump) {
-    ktimer_scope kt(BYO_K_CC_SHORTCUT, s);
-    cc_tile_jump_kernel<<<apply_grid(n), CT_APPLY, 0, s>>>(lab, t->rlabel, abits_next, n, ctr);
-  }
+static void cc_tile_pass(const byo_tiles *t, int32_t *lab, const uint64_t *abits, uint64_t *abits_next,
+                         byo_counters *ctr, int64_t n, hipStream_t s) {
+  ktimer_scope kt(BYO_K_CC_PULL, s);
+  cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, lab, abits,
+                                                                   (int32_t *)t->partial, t->cflag);
+  cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>((const int32_t *)t->partial, t->cflag, t->bfirst,
+                                                                 lab, t->rdeg, abits_next, n, ctr);
 }
 
+// Rounds in the layout's order, direction-optimising like the CSR path: a
+// push over the relabelled CSR while |changed| + sum(deg changed) <= m / div
+// (the push kernels with the atomic-min functor), else a pass over the tiles;
+// each round ends with the pointer-jumping pass when enabled.
 byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(ws_ensure_traversal(g));
   BYO_TRY(tiles_ensure(g, g->ws.tiles ? g->ws.tiles->shift : BYO_TILE_SHIFT, s));
@@ -203,13 +217,17 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
   BYO_TRY(tiles_partial(t, sizeof(int32_t) << t->shift));
   BYO_TRY(tiles_scratch(t));
   byo_workspace &w = g->ws;
-  const int64_t n = g->n;
+  const int64_t n = g->n, words = (n + 63) / 64;
   int32_t *lab = t->scratch;
   cc_tile_init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(t->orig, n, lab, w.bits[0]);
   BYO_HIP(hipGetLastError());
+  byo_graph rg = tiles_view(g, t);
+  const int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
+  int64_t acount = n;
+  long long adeg = g->m;
   int cur = 0;
   int32_t round = 0;
   while (true) {
@@ -220,17 +238,36 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
     byo_counters *ctr = w.ctr;
     BYO_HIP(hipMemsetAsync(ctr, 0, sizeof(byo_counters), s));
     uint64_t *an = w.bits[1 - cur];
-    switch (t->shift) {
-      case 13: cc_round<13>(t, lab, w.bits[cur], an, o.cc_shortcut != 0, ctr, n, s); break;
-      case 14: cc_round<14>(t, lab, w.bits[cur], an, o.cc_shortcut != 0, ctr, n, s); break;
-      default: cc_round<12>(t, lab, w.bits[cur], an, o.cc_shortcut != 0, ctr, n, s); break;
+    const bool push = acount + adeg <= g->m / div;
+    if (push) {
+      BYO_TRY(bitmap_to_ids(w.bits[cur], words, n, w.ids[cur], w.partial, w.partial_cap,
+                            (unsigned long long *)w.misc, s));
+      level_io io;
+      std::memset(&io, 0, sizeof(io));
+      io.in_ids = w.ids[cur];
+      io.in_count = acount;
+      io.out_bits = an;
+      io.ctr = ctr;
+      BYO_TRY(cc_level(&rg, BYO_V_PUSH_EDGE, lab, io, o, s, adeg));
+    } else {
+      switch (t->shift) {
+        case 13: cc_tile_pass<13>(t, lab, w.bits[cur], an, ctr, n, s); break;
+        case 14: cc_tile_pass<14>(t, lab, w.bits[cur], an, ctr, n, s); break;
+        default: cc_tile_pass<12>(t, lab, w.bits[cur], an, ctr, n, s); break;
+      }
+    }
+    if (o.cc_shortcut) {
+      ktimer_scope kt(BYO_K_CC_SHORTCUT, s);
+      cc_tile_jump_kernel<<<apply_grid(n), CT_APPLY, 0, s>>>(lab, t->rlabel, t->rdeg, an, n, ctr);
     }
     BYO_HIP(hipGetLastError());
     byo_counters c;
     BYO_TRY(sync_read(s, ctr, &c, sizeof(c)));
-    st.variant_count[BYO_V_PULL_WAVE]++;
+    st.variant_count[push ? BYO_V_PUSH_EDGE : BYO_V_PULL_WAVE]++;
     ++round;
     cur = 1 - cur;
+    acount = (int64_t)c.count;
+    adeg = (long long)c.degsum;
     if (c.count == 0) break;
   }
   cc_tile_out_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lab, t->orig, n, d_label);

@@ -241,6 +241,9 @@ bool tiles_wanted(const byo_graph *g);  // n >= 2^16 and m >= 4n
 byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s);
 byo_status tiles_partial(byo_tiles *t, size_t bytes_per_chunk);
 byo_status tiles_scratch(byo_tiles *t);
+// The layout's relabelled CSR seen as a graph, for the CSR push kernels: same
+// sizes and statistics, shares g's workspace; never destroyed or grown.
+byo_graph tiles_view(const byo_graph *g, const byo_tiles *t);
 // connectivity over the tile layout (cc_tile.hip)
 byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 void tiles_release(byo_workspace &w);

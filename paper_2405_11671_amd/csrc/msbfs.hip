@@ -728,16 +728,6 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
   }
 }
 
-// The layout's relabelled CSR seen as a graph, for the push kernels. It shares
-// the graph's workspace and is never destroyed or grown.
-static byo_graph relabelled_view(const byo_graph *g, const byo_tiles *t) {
-  byo_graph r = *g;
-  r.off = t->roff;
-  r.nbr = t->rnbr;
-  r.deg = t->rdeg;
-  return r;
-}
-
 template <int W>
 static byo_status launch_tile_push(byo_graph *g, const byo_tiles *t, ms_ws &mw, int cur, int64_t acount,
                                    long long adeg, uint8_t *depth, int32_t k, uint8_t nd, byo_counters *tctr,
@@ -748,7 +738,7 @@ static byo_status launch_tile_push(byo_graph *g, const byo_tiles *t, ms_ws &mw, 
   // active list from the frontier bitmap, then push over the relabelled CSR
   BYO_TRY(bitmap_to_ids(mw.abits[cur], words, n, mw.active[cur], w.partial, w.partial_cap,
                         (unsigned long long *)w.misc, s));
-  byo_graph rg = relabelled_view(g, t);
+  byo_graph rg = tiles_view(g, t);
   level_io io;
   std::memset(&io, 0, sizeof(io));
   io.in_ids = mw.active[cur];
@@ -813,7 +803,7 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, const std::vector<int32_
   int64_t acount = (int64_t)act.size();
   long long adeg = 0;
   {
-    byo_graph rg = relabelled_view(g, t);
+    byo_graph rg = tiles_view(g, t);
     BYO_HIP(hipMemcpyAsync(mw.active[0], act.data(), sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, s));
     BYO_TRY(frontier_degree_scan(&rg, mw.active[0], acount, g->ws.scan, g->ws.partial, g->ws.partial_cap, s));
     BYO_TRY(sync_read(s, g->ws.scan + acount, &adeg, sizeof(adeg)));

@@ -274,6 +274,14 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
   return BYO_OK;
 }
 
+byo_graph tiles_view(const byo_graph *g, const byo_tiles *t) {
+  byo_graph r = *g;
+  r.off = t->roff;
+  r.nbr = t->rnbr;
+  r.deg = t->rdeg;
+  return r;
+}
+
 byo_status tiles_scratch(byo_tiles *t) {
   if (!t->scratch) BYO_HIP(hipMalloc(&t->scratch, sizeof(int32_t) * (size_t)t->n));
   return BYO_OK;
