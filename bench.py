@@ -50,8 +50,8 @@ def counter_traffic(kernel_tag):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and line.startswith("- "):
-            k, v = line[2:].split(":", 1)
+        if ": " in line and line.startswith("- "):
+            k, v = line[2:].split(": ", 1)
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("pagerank_tile.hip sha256[:12]") != kernel_tag:
         return None

@@ -90,11 +90,10 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
                                                                  const uint32_t *__restrict__ cflag,
                                                                  const int32_t *__restrict__ bfirst,
                                                                  int32_t *__restrict__ lab,
-                                                                 const int32_t *__restrict__ rdeg,
                                                                  uint64_t *__restrict__ abits_next, int64_t n,
                                                                  byo_counters *__restrict__ ctr) {
   constexpr int B = 1 << SHIFT;
-  unsigned long long count = 0, degsum = 0;
+  unsigned long long count = 0;
   // capped grid: a few thousand counter atomics per round
   for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
     const int64_t w = base + threadIdx.x;
@@ -121,7 +120,6 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
       if (m < lab[w]) {
         lab[w] = m;
         changed = true;
-        degsum += (unsigned long long)rdeg[w];
       }
     }
     uint64_t am = __ballot(changed);
@@ -131,11 +129,7 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
     }
   }
   unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
-  unsigned long long td = block_sum<unsigned long long, CT_APPLY>(degsum);
-  if (threadIdx.x == 0) {
-    if (tc) atomicAdd(&ctr->count, tc);
-    if (td) atomicAdd(&ctr->degsum, td);
-  }
+  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
 }
 
 // Pointer jumping: label x of w becomes the label of vertex x when smaller
@@ -146,10 +140,9 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
 // stays equal to the frontier bitmap's population.
 __global__ void __launch_bounds__(CT_APPLY) cc_tile_jump_kernel(int32_t *__restrict__ lab,
                                                                 const int32_t *__restrict__ rlabel,
-                                                                const int32_t *__restrict__ rdeg,
                                                                 uint64_t *__restrict__ abits_next, int64_t n,
                                                                 byo_counters *__restrict__ ctr) {
-  unsigned long long count = 0, degsum = 0;
+  unsigned long long count = 0;
   for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
     const int64_t w = base + threadIdx.x;
     // a vertex already marked this round is counted once: only fresh bits count
@@ -161,7 +154,6 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_jump_kernel(int32_t *__restr
       if (y < x) {
         lab[w] = y;
         fresh = !((oldw >> (w & 63)) & 1ull);
-        if (fresh) degsum += (unsigned long long)rdeg[w];
       }
     }
     const uint64_t am = __ballot(fresh);
@@ -171,11 +163,7 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_jump_kernel(int32_t *__restr
     }
   }
   unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
-  unsigned long long td = block_sum<unsigned long long, CT_APPLY>(degsum);
-  if (threadIdx.x == 0) {
-    if (tc) atomicAdd(&ctr->count, tc);
-    if (td) atomicAdd(&ctr->degsum, td);
-  }
+  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
 }
 
 __global__ void cc_tile_init_kernel(const int32_t *__restrict__ orig, int64_t n, int32_t *__restrict__ lab,
@@ -203,13 +191,14 @@ static void cc_tile_pass(const byo_tiles *t, int32_t *lab, const uint64_t *abits
   cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, lab, abits,
                                                                    (int32_t *)t->partial, t->cflag);
   cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>((const int32_t *)t->partial, t->cflag, t->bfirst,
-                                                                 lab, t->rdeg, abits_next, n, ctr);
+                                                                 lab, abits_next, n, ctr);
 }
 
-// Rounds in the layout's order, direction-optimising like the CSR path: a
-// push over the relabelled CSR while |changed| + sum(deg changed) <= m / div
-// (the push kernels with the atomic-min functor), else a pass over the tiles;
-// each round ends with the pointer-jumping pass when enabled.
+// Rounds in the layout's order, direction-optimising: a push over the
+// relabelled CSR (the push kernels with the atomic-min functor) while the
+// changed vertices number at most n / div, the sparse/dense rule at average
+// degree, else a pass over the tiles; each round ends with the
+// pointer-jumping pass when enabled.
 byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(ws_ensure_traversal(g));
   BYO_TRY(tiles_ensure(g, g->ws.tiles ? g->ws.tiles->shift : BYO_TILE_SHIFT, s));
@@ -227,7 +216,6 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
   std::memset(&st, 0, sizeof(st));
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   int64_t acount = n;
-  long long adeg = g->m;
   int cur = 0;
   int32_t round = 0;
   while (true) {
@@ -238,7 +226,7 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
     byo_counters *ctr = w.ctr;
     BYO_HIP(hipMemsetAsync(ctr, 0, sizeof(byo_counters), s));
     uint64_t *an = w.bits[1 - cur];
-    const bool push = acount + adeg <= g->m / div;
+    const bool push = acount <= n / div;
     if (push) {
       BYO_TRY(bitmap_to_ids(w.bits[cur], words, n, w.ids[cur], w.partial, w.partial_cap,
                             (unsigned long long *)w.misc, s));
@@ -248,7 +236,7 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
       io.in_count = acount;
       io.out_bits = an;
       io.ctr = ctr;
-      BYO_TRY(cc_level(&rg, BYO_V_PUSH_EDGE, lab, io, o, s, adeg));
+      BYO_TRY(cc_level(&rg, BYO_V_PUSH_EDGE, lab, io, o, s, -1));  // -1: the push measures its edge total
     } else {
       switch (t->shift) {
         case 13: cc_tile_pass<13>(t, lab, w.bits[cur], an, ctr, n, s); break;
@@ -258,7 +246,7 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
     }
     if (o.cc_shortcut) {
       ktimer_scope kt(BYO_K_CC_SHORTCUT, s);
-      cc_tile_jump_kernel<<<apply_grid(n), CT_APPLY, 0, s>>>(lab, t->rlabel, t->rdeg, an, n, ctr);
+      cc_tile_jump_kernel<<<apply_grid(n), CT_APPLY, 0, s>>>(lab, t->rlabel, an, n, ctr);
     }
     BYO_HIP(hipGetLastError());
     byo_counters c;
@@ -267,7 +255,6 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
     ++round;
     cur = 1 - cur;
     acount = (int64_t)c.count;
-    adeg = (long long)c.degsum;
     if (c.count == 0) break;
   }
   cc_tile_out_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(lab, t->orig, n, d_label);
