@@ -335,7 +335,8 @@ def main():
         "grid": grid,
         "batch64": batch,
     }
-    traffic = counter_traffic(source_tag(PR_SOURCE)) if not args.no_tiles else None
+    # the committed counters were taken on the RMAT-22 workload with the tile layout
+    traffic = counter_traffic(source_tag(PR_SOURCE)) if (not args.no_tiles and args.scale == 22) else None
     achieved = pr_bytes / (pr_avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": PR_KERNELS if not args.no_tiles else "pr_chunk_kernel + pr_pull_kernel<0>",
                 "achieved": round(achieved, 2),

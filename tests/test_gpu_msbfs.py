@@ -69,6 +69,15 @@ def test_msbfs_tiled_matches_oracle(pi, k):
     assert st2["edges"] == st["edges"] and st2["reached"] == st["reached"]
 
 
+@pytest.mark.parametrize("p", SUITE, ids=[p.name for p in SUITE])
+def test_msbfs_tiled_falls_back_below_size_cut(p):
+    """tiled = 1 on graphs the layout does not take runs over the CSR."""
+    g, og = build(p)
+    srcs = np.random.default_rng(3).integers(0, og.n, 65)
+    D, _ = byo.msbfs(g, srcs, tiled=1)
+    assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs))
+
+
 def test_msbfs_tiled_after_pagerank_layout_change():
     """PageRank with another tile size rebuilds the shared layout; the next
     tiled multi-source run rebuilds it back and stays exact."""

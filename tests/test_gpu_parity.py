@@ -136,6 +136,20 @@ def test_cc_tiled_matches_oracle(pi, shortcut):
     assert st["levels"] >= 1
 
 
+@pytest.mark.parametrize("p", SUITE, ids=IDS)
+def test_tiled_options_fall_back_below_size_cut(p):
+    """tiled / pr_blocked on graphs the layout does not take (n < 2^16 or
+    m < 4n) run over the CSR and stay exact."""
+    g, og = build(p)
+    if g.n >= 1 << 16 and g.m >= 4 * g.n:
+        pytest.skip("graph qualifies for the layout")
+    lab, _ = byo.cc(g, tiled=1)
+    assert np.array_equal(lab.cpu().numpy(), og.cc())
+    r, _ = byo.pagerank(g, 0.85, 5, pr_blocked=1)
+    r64 = og.pagerank(0.85, 5)
+    assert np.max(np.abs(r.cpu().numpy() - r64)) / np.max(np.abs(r64)) < PR_TOL
+
+
 def test_cc_tiled_round_cap():
     g, _ = build(TILED[2])
     with pytest.raises(byo.ByoError) as e:
