@@ -49,6 +49,12 @@ byo_status byo_trace_enable(int32_t on);
 byo_status byo_trace_read(byo_level_record *out, int64_t cap, int64_t *count);
 byo_status byo_trace_pending(int64_t *count);
 
+/* Kernel families timed by the kernel timers. The dense pass of each
+ * algorithm counts under *_PULL whether it runs over the CSR or over the tile
+ * layout: BYO_K_PR_PULL is the pull kernel or the tile kernel of a PageRank
+ * step, BYO_K_PR_CHUNK its heavy-row chunk kernel or tile apply kernel;
+ * BYO_K_MSBFS_FINISH the fold after a multi-source push or the tile apply;
+ * BYO_K_CC_PULL the pull or the tile pass (tile kernel + apply). */
 typedef enum {
   BYO_K_BFS_PUSH = 0, BYO_K_BFS_PULL = 1, BYO_K_CC_PUSH = 2, BYO_K_CC_PULL = 3,
   BYO_K_PR_PULL = 4, BYO_K_PR_CHUNK = 5, BYO_K_MSBFS_PUSH = 6, BYO_K_MSBFS_PULL = 7,
