@@ -74,7 +74,14 @@ def cpu_baseline(pairs, srcs, args):
     deg = og.degrees()
     bfs_e = sum(int(deg[d >= 0].sum()) // 2 for d in depths)
     edges = bfs_e + args.cpu_sample_pr_iters * og.m + og.m // 2
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(edges / el / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "host": f"{model}; {os.cpu_count()} logical CPUs visible; the oracle uses one thread",
             "sample": f"{len(ks)} single-source BFS + {args.cpu_sample_pr_iters} PageRank steps (FP64) + CC "
                       f"on the same rmat-{args.scale} graph; {el:.1f} s"}
 
@@ -109,8 +116,12 @@ def grid_workload(byo, gen, mlp_opts, side):
         ms, st = timed(lambda: byo.bfs(g, 0, opts=o, depth=depth, parent=parent)[2])
         res[f"bfs_{name}_ms"] = round(ms, 3)
         res["bfs_levels"] = st["levels"]
-    res["bfs_gteps_best"] = round(st["edges"] / 2 / (min(v for k, v in res.items() if k.startswith("bfs_") and
-                                                        k.endswith("_ms")) * 1e-3) / 1e9, 4)
+    centre = (side // 2) * side + side // 2
+    for name in ("heuristic", "heuristic_device_loop"):
+        ms, stc = timed(lambda: byo.bfs(g, centre, opts=cases[name], depth=depth, parent=parent)[2])
+        res[f"bfs_centre_{name}_ms"] = round(ms, 3)
+        res["bfs_centre_levels"] = stc["levels"]
+    res["bfs_gteps_best"] = round(st["edges"] / 2 / (min(res[f"bfs_{c}_ms"] for c in cases) * 1e-3) / 1e9, 4)
     for name, o in (("heuristic", byo.default_opts()), ("learned", mlp_opts)):
         ms, st = timed(lambda: byo.cc(g, opts=o, label=label)[1])
         res[f"cc_{name}_ms"] = round(ms, 3)
@@ -268,13 +279,16 @@ def main():
                            "ms_levels": mst["levels"], "cc_rounds": cst["levels"]})
         return ms_edges
 
-    def single_bfs(o):
+    def single_bfs(o, per_source=None):
         torch.cuda.synchronize()
         t = time.perf_counter()
         e = 0
         for s_ in srcs:
+            t1 = time.perf_counter()
             _, _, st = byo.bfs(g, int(s_), opts=o, depth=depth, parent=parent)
             e += st["edges"] // 2
+            if per_source is not None:  # Graph500 per-source rate (the call returns after its last level sync)
+                per_source.append(st["edges"] / 2 / (time.perf_counter() - t1) / 1e9)
         torch.cuda.synchronize()
         return e / (time.perf_counter() - t) / 1e9
 
@@ -312,6 +326,10 @@ def main():
     value = edges_total / wall / 1e9
     plain = [plain_bfs() for _ in range(3)]
     learned = [learned_bfs() for _ in range(3)]
+    per_plain, per_learned = [], []
+    single_bfs(opts, per_plain)
+    single_bfs(mlp_opts, per_learned)
+    hmean = lambda xs: len(xs) / sum(1.0 / x for x in xs)  # noqa: E731
     ms_ms = float(np.median([r["ms_ms"] for r in rec]))
     pr_ms = float(np.median([r["pr_ms"] for r in rec]))
     cc_ms = float(np.median([r["cc_ms"] for r in rec]))
@@ -326,6 +344,9 @@ def main():
         "pr_gteps": args.pr_iters * m / (pr_ms * 1e-3) / 1e9, "pr_ms": pr_ms,
         "cc_ms": cc_ms, "cc_rounds": rec[0]["cc_rounds"],
         "plain_bfs_gteps": float(np.median(plain)),
+        "plain_bfs_gteps_hmean": hmean(per_plain), "learned_bfs_gteps_hmean": hmean(per_learned),
+        "step_ms_median": float(np.median([r["ms_ms"] + r["pr_ms"] + r["cc_ms"] for r in rec])),
+        "step_ms_mean": float(np.mean([r["ms_ms"] + r["pr_ms"] + r["cc_ms"] for r in rec])),
         "learned_bfs_gteps": float(np.median(learned)),
         "learned_vs_plain": float(np.median(learned)) / float(np.median(plain)),
         "batched_vs_plain": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9 / float(np.median(plain)),

@@ -98,8 +98,7 @@ def tune_batch(batch, sources, repeats=3, cache=DEFAULT_CACHE, refresh=False, lo
     db = _load(cache)
     if key in db and not refresh:
         return db[key]["opts"], db[key]["report"]
-    space = {k: v for k, v in SPACE.items() if k != "small_frontier"}
-    opts, rep = tune(lambda o: batch.bfs(sources, opts=o), space=space, repeats=repeats, log=log)
+    opts, rep = tune(lambda o: batch.bfs(sources, opts=o), repeats=repeats, log=log)
     db[key] = {"opts": opts, "report": rep}
     _save(cache, db)
     return opts, rep

@@ -73,3 +73,20 @@ def test_batch_graph_mode_matches_eager():
             want, _ = og.bfs(srcs[i])
             assert np.array_equal(D[i], want), (rep, i)
             assert og.check_bfs(srcs[i], D[i], P[i]) == 0
+
+
+@pytest.mark.parametrize("cap", [1024, 8192])
+def test_batch_device_resident_loop(cap):
+    """Batched BFS with small frontiers in the device-resident loop (64
+    sources in one frontier; hand-back to the host loop when it grows)."""
+    plist = gen.batch_pairs(64, seed=3)
+    B = byo.Batch.from_pairs(plist)
+    ogs = [oracle.Graph.from_pairs(p) for p in plist]
+    srcs = [first_non_isolated(og) for og in ogs]
+    depth, parent, st = B.bfs(srcs, small_frontier=cap)
+    D, P = B.split(depth.cpu().numpy()), B.split(parent.cpu().numpy())
+    for i, og in enumerate(ogs):
+        want, _ = og.bfs(srcs[i])
+        assert np.array_equal(D[i], want), i
+        assert og.check_bfs(srcs[i], D[i], P[i]) == 0
+    assert st["device_levels"] >= 1
