@@ -207,9 +207,9 @@ constexpr int BYO_TILE_SHIFT = 12;
 struct byo_tiles {
   int shift = 0;
   int64_t n = 0, m = 0, mp = 0, nblk = 0, nchunks = 0;
-  // mp entries in 64-entry groups (a group's sources lie within 2^16 of its
-  // anchor; unused places are padding with destination 2^shift, a slot no
-  // vertex uses). Entry e: source = anchor[e / 64] + (ent[e] & 0xffff),
+  // mp entries in 64-entry groups (a group's sources lie in one 2^16-aligned
+  // window, whose base is the group's anchor; unused places are padding
+  // with destination 2^shift, a slot no vertex uses). Entry e: source = anchor[e / 64] + (ent[e] & 0xffff),
   // tile-local destination = ent[e] >> 16; sources ascend inside a tile.
   uint32_t *ent = nullptr;    // [mp]
   int32_t *anchor = nullptr;  // [mp / 64]
@@ -225,7 +225,6 @@ struct byo_tiles {
   int32_t *rnbr = nullptr;    // [m] its neighbours, relabelled
   void *partial = nullptr;    // chunk results, sized by the user (tiles_partial)
   size_t partial_bytes = 0;
-  std::vector<int32_t> h_label;  // relabelled ID of each original vertex (host copy)
 };
 // Relabelled source and tile-local destination of entry e. The caller's
 // wavefront reads one whole group (e / 64 is the same in every lane), so the

@@ -603,11 +603,11 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
 
 // Sources: seen/front bits at the relabelled vertex, frontier bitmap bit,
 // depth 0 at the original vertex.
-__global__ void ms_tile_init_kernel(const int32_t *__restrict__ srcs, const int32_t *__restrict__ rsrcs, int32_t k,
+__global__ void ms_tile_init_kernel(const int32_t *__restrict__ srcs, const int32_t *__restrict__ rlabel, int32_t k,
                                     int32_t W, uint64_t *seen, uint64_t *front, uint64_t *abits, uint8_t *depth) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j < k) {
-    int64_t r = rsrcs[j];
+    int64_t r = rlabel[srcs[j]];
     unsigned long long bit = 1ull << (j & 63);
     atomicOr((unsigned long long *)&seen[r * W + (j >> 6)], bit);
     atomicOr((unsigned long long *)&front[r * W + (j >> 6)], bit);
@@ -651,14 +651,14 @@ struct ms_ws {
   uint64_t *seen = nullptr, *front[2] = {nullptr, nullptr}, *visit = nullptr, *tbits = nullptr;
   uint64_t *abits[2] = {nullptr, nullptr};
   uint64_t *fbits = nullptr;  // tiled levels: vertices that have seen every source
-  int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr, *rsrcs = nullptr;
+  int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr;
   byo_counters *ctr = nullptr;
   unsigned long long *tally = nullptr;
 };
 
 static void ms_free(ms_ws &m) {
   void *p[] = {m.seen, m.front[0], m.front[1], m.visit, m.tbits, m.touched, m.active[0], m.active[1], m.srcs,
-               m.rsrcs, m.ctr, m.tally, m.abits[0], m.abits[1], m.fbits};
+               m.ctr, m.tally, m.abits[0], m.abits[1], m.fbits};
   for (void *x : p)
     if (x) (void)hipFree(x);
   m = ms_ws();
@@ -784,27 +784,26 @@ static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *d
 // else a pass over the tiles. The caller has zeroed seen, both frontier
 // buffers, the touched and full bitmaps and the counters, and filled depth
 // with 255.
-static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, const std::vector<int32_t> &hs, int32_t k, int W,
+static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
                                uint8_t *d_depth, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(tiles_ensure(g, MT_SHIFT, s));
   byo_tiles *t = g->ws.tiles;
   BYO_TRY(tiles_partial(t, sizeof(uint64_t) * (size_t)W << MT_SHIFT));
   const int64_t n = g->n, words = (n + 63) / 64;
-  std::vector<int32_t> rs(k);
-  for (int32_t j = 0; j < k; ++j) rs[j] = t->h_label[hs[j]];
-  BYO_HIP(hipMemcpyAsync(mw.rsrcs, rs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
   BYO_HIP(hipMemsetAsync(mw.abits[0], 0, sizeof(uint64_t) * (size_t)words, s));
-  ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, mw.rsrcs, k, W, mw.seen, mw.front[0], mw.abits[0], d_depth);
+  ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, t->rlabel, k, W, mw.seen, mw.front[0], mw.abits[0], d_depth);
   BYO_HIP(hipGetLastError());
-  // first frontier: the distinct sources and their degree sum
-  std::vector<int32_t> act(rs);
-  std::sort(act.begin(), act.end());
-  act.erase(std::unique(act.begin(), act.end()), act.end());
-  int64_t acount = (int64_t)act.size();
+  // first frontier: the distinct sources (from the frontier bitmap) and their
+  // degree sum
+  int64_t acount = 0;
   long long adeg = 0;
   {
+    unsigned long long cnt = 0;
+    BYO_TRY(bitmap_to_ids(mw.abits[0], words, n, mw.active[0], g->ws.partial, g->ws.partial_cap,
+                          (unsigned long long *)g->ws.misc, s));
+    BYO_TRY(sync_read(s, g->ws.misc, &cnt, sizeof(cnt)));
+    acount = (int64_t)cnt;
     byo_graph rg = tiles_view(g, t);
-    BYO_HIP(hipMemcpyAsync(mw.active[0], act.data(), sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, s));
     BYO_TRY(frontier_degree_scan(&rg, mw.active[0], acount, g->ws.scan, g->ws.partial, g->ws.partial_cap, s));
     BYO_TRY(sync_read(s, g->ws.scan + acount, &adeg, sizeof(adeg)));
   }
@@ -890,7 +889,6 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     BYO_HIP(hipMalloc(&mw.active[0], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.active[1], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.srcs, sizeof(int32_t) * 256));
-    BYO_HIP(hipMalloc(&mw.rsrcs, sizeof(int32_t) * 256));
     BYO_HIP(hipMalloc(&mw.ctr, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1)));
     BYO_HIP(hipMalloc(&mw.tally, sizeof(unsigned long long) * 2));
     mw.n = n;
@@ -913,7 +911,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   std::vector<int32_t> hs(k);
   for (int32_t j = 0; j < k; ++j) hs[j] = (int32_t)h_srcs[j];
   BYO_HIP(hipMemcpyAsync(mw.srcs, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
-  if (o.tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, hs, k, W, d_depth, o, s, stats);
+  if (o.tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, k, W, d_depth, o, s, stats);
   ms_init_kernel<<<1, 256, 0, s>>>(mw.srcs, k, W, mw.seen, mw.front[0], d_depth);
   // first active list: the distinct sources
   std::vector<int32_t> act(hs);

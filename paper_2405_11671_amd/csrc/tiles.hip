@@ -1,6 +1,7 @@
 // Degree-ordered destination-tile layout of the edge set, shared by the
-// tiled PageRank step and the tiled multi-source BFS level. Built once per
-// graph (and tile size) on first use, kept with the graph.
+// tiled PageRank step, the tiled multi-source BFS level and the tiled
+// connectivity round. Built on the device once per graph (and tile size) on
+// first use, kept with the graph.
 //
 // Dense pull levels gather a per-vertex value (a contribution, a frontier
 // mask) for every edge at a random address; one L2 request per edge bounds
@@ -15,12 +16,17 @@
 // A workgroup keeps its tile's accumulators in LDS; its lanes read
 // consecutive entries, whose sources are close together, so a wavefront's
 // gathers fall in few cache lines. An entry is one 32-bit word: a 16-bit
-// offset of its source from its 64-entry group's anchor and its 16-bit
-// tile-local destination; a wavefront's load is one group, so the anchor is
-// one scalar load.
+// offset of its source from its 64-entry group's anchor (the base of the
+// 2^16-aligned source window the group lies in) and its 16-bit tile-local
+// destination; a wavefront's load is one group, so the anchor is one scalar
+// load.
+#include <cstring>
+
 #include <algorithm>
-#include <thread>
 #include <vector>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "internal.h"
 
@@ -28,189 +34,266 @@ namespace byo {
 
 bool tiles_wanted(const byo_graph *g) { return g->n >= (1ll << 16) && g->m >= 4 * g->n && g->m > 0; }
 
-void tiles_release(byo_workspace &w) {
-  if (!w.tiles) return;
-  byo_tiles *p = w.tiles;
+static void tiles_free(byo_tiles *p) {
   void *d[] = {p->ent, p->anchor, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->rlabel,
                p->scratch, p->partial, p->roff, p->rnbr};
   for (void *x : d)
     if (x) (void)hipFree(x);
   delete p;
+}
+
+void tiles_release(byo_workspace &w) {
+  if (!w.tiles) return;
+  tiles_free(w.tiles);
   w.tiles = nullptr;
 }
 
-// Host construction of the tile layout. The relabelling is a counting sort
-// by degree, descending, stable in ID. Relabelled rows are then split into
-// contiguous ranges of about equal entry count, one per thread; each thread
-// counts its entries per tile, the counts become per-thread write cursors
-// (tile-major, thread order inside a tile), and each thread copies its
-// entries in relabelled row order, so every tile is ordered by source.
-static void build_tiles_host(const std::vector<int64_t> &off, const std::vector<int32_t> &nbr, int64_t n, int shift,
-                             std::vector<int32_t> &esrc, std::vector<uint16_t> &edst, std::vector<int64_t> &tile_off,
-                             std::vector<int32_t> &rdeg, std::vector<int32_t> &orig, std::vector<int32_t> &label) {
-  const int64_t m = off[n];
-  int64_t max_deg = 0;
-  for (int64_t v = 0; v < n; ++v) max_deg = std::max(max_deg, off[v + 1] - off[v]);
-  const int64_t nblk = (n + (1ll << shift) - 1) >> shift;
-  const uint32_t mask = (1u << shift) - 1;
-  // relabel: label[v] = position of v in (degree desc, ID asc) order
-  std::vector<int64_t> start((size_t)max_deg + 2, 0);
-  for (int64_t v = 0; v < n; ++v) start[(size_t)(max_deg - (off[v + 1] - off[v]))]++;
-  int64_t acc = 0;
-  for (auto &x : start) {
-    int64_t c = x;
-    x = acc;
-    acc += c;
-  }
-  label.resize((size_t)n);
-  orig.resize((size_t)n);
-  rdeg.resize((size_t)n);
-  for (int64_t v = 0; v < n; ++v) {
-    int32_t d = (int32_t)(off[v + 1] - off[v]);
-    int64_t w = start[(size_t)(max_deg - d)]++;
-    label[v] = (int32_t)w;
-    orig[w] = (int32_t)v;
-    rdeg[w] = d;
-  }
-  unsigned T = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-  if (m < (1 << 20)) T = 1;
-  // relabelled row ranges of about m / T entries each (degrees descend, so
-  // the prefix of rdeg is walked once)
-  std::vector<int64_t> row0(T + 1, n);
-  row0[0] = 0;
-  {
-    int64_t sum = 0;
-    unsigned t = 1;
-    for (int64_t w = 0; w < n && t < T; ++w) {
-      while (t < T && sum >= m * (int64_t)t / (int64_t)T) row0[t++] = w;
-      sum += rdeg[w];
-    }
-  }
-  std::vector<std::vector<int64_t>> cnt(T, std::vector<int64_t>((size_t)nblk, 0));
-  auto run = [&](auto fn) {
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < T; ++t) th.emplace_back(fn, t);
-    for (auto &x : th) x.join();
-  };
-  run([&](unsigned t) {
-    std::vector<int64_t> &c = cnt[t];
-    for (int64_t w = row0[t]; w < row0[t + 1]; ++w) {
-      int64_t u = orig[w];
-      for (int64_t e = off[u]; e < off[u + 1]; ++e) c[(size_t)(label[nbr[e]] >> shift)]++;
-    }
-  });
-  tile_off.assign((size_t)nblk + 1, 0);
-  for (int64_t b = 0; b < nblk; ++b) {
-    int64_t s = 0;
-    for (unsigned t = 0; t < T; ++t) s += cnt[t][b];
-    tile_off[b + 1] = tile_off[b] + s;
-  }
-  for (int64_t b = 0; b < nblk; ++b) {
-    int64_t pos = tile_off[b];
-    for (unsigned t = 0; t < T; ++t) {
-      int64_t c = cnt[t][b];
-      cnt[t][b] = pos;
-      pos += c;
-    }
-  }
-  esrc.resize((size_t)m);
-  edst.resize((size_t)m);
-  run([&](unsigned t) {
-    std::vector<int64_t> &cur = cnt[t];
-    for (int64_t w = row0[t]; w < row0[t + 1]; ++w) {
-      int64_t u = orig[w];
-      for (int64_t e = off[u]; e < off[u + 1]; ++e) {
-        int32_t x = label[nbr[e]];
-        int64_t p = cur[(size_t)(x >> shift)]++;
-        esrc[p] = (int32_t)w;
-        edst[p] = (uint16_t)((uint32_t)x & mask);
-      }
-    }
-  });
+// Device construction of the tile layout, all on the caller's stream:
+//  1. stable radix sort of the vertices by descending degree (ties keep ID
+//     order): orig, then rlabel and rdeg by scatter;
+//  2. roff = exclusive scan of rdeg; row[p], the relabelled row of CSR slot p,
+//     is a max-scan of the row starts;
+//  3. one pass over the slots writes the relabelled CSR and, per entry, the
+//     destination tile (key) and (source << 16 | tile-local destination);
+//  4. a stable radix sort by tile keeps the sources ascending inside a tile;
+//  5. packing: a group never crosses a 2^16-aligned source window, so its
+//     anchor is the window base, and a (tile, window) segment is cut into
+//     plain 64-entry groups, the last one padded. Segments come from a scan
+//     of "segment starts here" flags, group offsets from a scan of the
+//     per-segment group counts; every entry is then placed independently.
+namespace {
+
+constexpr int TL_THREADS = 256;
+
+unsigned tl_blocks(int64_t count) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((count + TL_THREADS - 1) / TL_THREADS, 1 << 16));
 }
 
-byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
-  byo_workspace &w = g->ws;
-  BYO_CHECK(shift >= 12 && shift <= 14, BYO_EINVAL, "tile size must be 2^12 .. 2^14");
-  if (w.tiles && w.tiles->shift == shift) return BYO_OK;
-  tiles_release(w);
-  const int64_t n = g->n, m = g->m;
-  BYO_CHECK(tiles_wanted(g), BYO_EINVAL, "graph too small or too sparse for the tile layout");
-  BYO_CHECK(n <= ((int64_t)1 << 31) - 1, BYO_EINVAL, "graph too large for the tile layout");
-  std::vector<int64_t> off((size_t)n + 1);
-  std::vector<int32_t> nbr((size_t)m);
-  BYO_HIP(hipMemcpyAsync(off.data(), g->off, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToHost, s));
-  BYO_HIP(hipMemcpyAsync(nbr.data(), g->nbr, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToHost, s));
-  BYO_HIP(hipStreamSynchronize(s));
-  std::vector<int32_t> esrc, rdeg, orig, label;
-  std::vector<uint16_t> edst;
-  std::vector<int64_t> tile_off;
-  build_tiles_host(off, nbr, n, shift, esrc, edst, tile_off, rdeg, orig, label);
-  const int64_t nblk = (int64_t)tile_off.size() - 1;
-  // Pack each tile into 64-entry groups. A group holds up to 64 consecutive
-  // entries whose sources lie within 2^16 of the first (the group's anchor);
-  // the rest of a group that cannot take the next entry is padding pointing
-  // at the dummy slot 2^shift. Each entry is one word: its source's 16-bit
-  // offset from the anchor and its 16-bit tile-local destination.
-  const uint32_t dummy = 1u << shift;
-  unsigned T = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
-  if (m < (1 << 20)) T = 1;
-  std::vector<int64_t> b0(T + 1, nblk);  // tile ranges of about m / T entries
-  b0[0] = 0;
-  for (unsigned t = 1; t < T; ++t)
-    b0[t] = std::upper_bound(tile_off.begin(), tile_off.end(), m * (int64_t)t / (int64_t)T) - tile_off.begin() - 1;
-  for (unsigned t = 1; t <= T; ++t) b0[t] = std::max(b0[t], b0[t - 1]);
-  auto run = [&](auto fn) {
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < T; ++t) th.emplace_back(fn, t);
-    for (auto &x : th) x.join();
-  };
-  // end of the group that starts at entry i of a tile ending at hi
-  auto group_end = [&](int64_t i, int64_t hi) {
-    const int64_t lim = std::min(hi, i + 64);
-    const int32_t a = esrc[(size_t)i];
-    int64_t j = i + 1;
-    while (j < lim && (int64_t)esrc[(size_t)j] - a <= 65535) ++j;
-    return j;
-  };
-  std::vector<int64_t> ngrp((size_t)nblk, 0);
-  run([&](unsigned t) {
-    for (int64_t b = b0[t]; b < b0[t + 1]; ++b)
-      for (int64_t i = tile_off[b]; i < tile_off[b + 1]; i = group_end(i, tile_off[b + 1])) ngrp[(size_t)b]++;
-  });
-  std::vector<int64_t> ptile((size_t)nblk + 1, 0);
-  for (int64_t b = 0; b < nblk; ++b) ptile[b + 1] = ptile[b] + 64 * ngrp[(size_t)b];
-  const int64_t mp = ptile[nblk], ngroups = mp / 64;
+__global__ void tl_degkey_kernel(const int32_t *__restrict__ deg, int64_t n, int64_t max_deg, uint32_t *key,
+                                 int32_t *idx) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    key[v] = (uint32_t)(max_deg - deg[v]);
+    idx[v] = (int32_t)v;
+  }
+}
+
+__global__ void tl_label_kernel(const int32_t *__restrict__ orig, const int32_t *__restrict__ deg, int64_t n,
+                                int32_t *rlabel, int32_t *rdeg) {
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = orig[w];
+    rlabel[v] = (int32_t)w;
+    rdeg[w] = deg[v];
+  }
+}
+
+// rowmark[roff[w]] = w for every non-empty row (rowmark zeroed before); the
+// running maximum of rowmark is then the row of each slot.
+__global__ void tl_rowmark_kernel(const int64_t *__restrict__ roff, const int32_t *__restrict__ rdeg, int64_t n,
+                                  int32_t *rowmark) {
+  for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w < n; w += (int64_t)gridDim.x * blockDim.x)
+    if (rdeg[w] > 0) rowmark[roff[w]] = (int32_t)w;
+}
+
+__global__ void tl_entries_kernel(const int64_t *__restrict__ off, const int32_t *__restrict__ nbr,
+                                  const int32_t *__restrict__ orig, const int32_t *__restrict__ rlabel,
+                                  const int64_t *__restrict__ roff, const int32_t *__restrict__ row, int64_t m,
+                                  int shift, int32_t *rnbr, uint32_t *key, uint64_t *val) {
+  const uint32_t mask = (1u << shift) - 1;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t w = row[p];
+    const int32_t x = rlabel[nbr[off[orig[w]] + (p - roff[w])]];
+    rnbr[p] = x;
+    key[p] = (uint32_t)x >> shift;
+    val[p] = ((uint64_t)(uint32_t)w << 16) | ((uint32_t)x & mask);
+  }
+}
+
+// first entry of every tile b in [0, nblk] (m for tiles past the last entry)
+__global__ void tl_tile_off_kernel(const uint32_t *__restrict__ key, int64_t m, int64_t nblk, int64_t *tile_off) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b > nblk) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)key[mid] < b) lo = mid + 1;
+    else hi = mid;
+  }
+  tile_off[b] = lo;
+}
+
+// a segment (same tile, same 2^16 source window) starts at p
+__global__ void tl_segflag_kernel(const uint32_t *__restrict__ key, const uint64_t *__restrict__ val, int64_t m,
+                                  uint32_t *flag) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x)
+    flag[p] = p == 0 || key[p] != key[p - 1] || (val[p] >> 32) != (val[p - 1] >> 32);
+}
+
+// segid is the inclusive count of segment starts, so segment segid[p] - 1
+// holds p; segbeg[nseg] = m closes the last one.
+__global__ void tl_segbeg_kernel(const uint32_t *__restrict__ flag, const int64_t *__restrict__ segid, int64_t m,
+                                 int64_t *segbeg) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+    if (flag[p]) segbeg[segid[p] - 1] = p;
+    if (p == m - 1) segbeg[segid[p]] = m;
+  }
+}
+
+__global__ void tl_segroups_kernel(const int64_t *__restrict__ segbeg, int64_t nseg, int64_t *ngroups) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= nseg; i += (int64_t)gridDim.x * blockDim.x)
+    ngroups[i] = i < nseg ? (segbeg[i + 1] - segbeg[i] + 63) / 64 : 0;
+}
+
+// ent was filled with padding; every real entry goes to its segment's groups
+// at its offset in the segment, and a group's first entry writes the anchor.
+__global__ void tl_place_kernel(const uint64_t *__restrict__ val, const int64_t *__restrict__ segid,
+                                const int64_t *__restrict__ segbeg, const int64_t *__restrict__ gbefore, int64_t m,
+                                uint32_t *ent, int32_t *anchor) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sg = segid[p] - 1, l = p - segbeg[sg], q = gbefore[sg] * 64 + l;
+    const uint64_t x = val[p];
+    const uint32_t w = (uint32_t)(x >> 16), base = w & ~0xffffu;
+    ent[q] = (w - base) | ((uint32_t)(x & 0xffffu) << 16);
+    if ((l & 63) == 0) anchor[q >> 6] = (int32_t)base;
+  }
+}
+
+// first group of every tile b in [0, nblk]
+__global__ void tl_tile_groups_kernel(const int64_t *__restrict__ tile_off, const int64_t *__restrict__ segid,
+                                      const int64_t *__restrict__ gbefore, int64_t m, int64_t nblk, int64_t nseg,
+                                      int64_t *tgrp) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b > nblk) return;
+  const int64_t p = tile_off[b];
+  tgrp[b] = p >= m ? gbefore[nseg] : gbefore[segid[p] - 1];
+}
+
+// device buffers of one build, freed on every exit once the stream's queued
+// work is done
+struct tl_tmp {
+  hipStream_t s;
+  std::vector<void *> v;
+  explicit tl_tmp(hipStream_t st) : s(st) {}
+  template <class T>
+  byo_status get(T **p, size_t count) {
+    *p = nullptr;
+    BYO_HIP(hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1)));
+    v.push_back(*p);
+    return BYO_OK;
+  }
+  ~tl_tmp() {
+    (void)hipStreamSynchronize(s);
+    for (void *x : v) (void)hipFree(x);
+  }
+};
+
+int bits_for(int64_t x) {  // bits needed to hold 0 .. x
+  int b = 1;
+  while (b < 63 && (x >> b) != 0) ++b;
+  return b;
+}
+
+}  // namespace
+
+static byo_status tiles_build(const byo_graph *g, byo_tiles *p, hipStream_t s) {
+  const int64_t n = p->n, m = p->m, nblk = p->nblk;
+  const int shift = p->shift;
+  tl_tmp tmp(s);
+  uint32_t *vkey = nullptr, *vkey2 = nullptr, *ka = nullptr, *kb = nullptr;
+  int32_t *vidx = nullptr;
+  uint64_t *va = nullptr, *vb = nullptr;
+  BYO_TRY(tmp.get(&vkey, (size_t)n));
+  BYO_TRY(tmp.get(&vkey2, (size_t)n));
+  BYO_TRY(tmp.get(&vidx, (size_t)n));
+  BYO_TRY(tmp.get(&ka, (size_t)m));
+  BYO_TRY(tmp.get(&kb, (size_t)m));
+  BYO_TRY(tmp.get(&va, (size_t)m));
+  BYO_TRY(tmp.get(&vb, (size_t)m));
+  BYO_HIP(hipMalloc(&p->orig, sizeof(int32_t) * (size_t)n));
+  BYO_HIP(hipMalloc(&p->rlabel, sizeof(int32_t) * (size_t)n));
+  BYO_HIP(hipMalloc(&p->rdeg, sizeof(int32_t) * (size_t)n));
+  BYO_HIP(hipMalloc(&p->roff, sizeof(int64_t) * (size_t)(n + 1)));
+  BYO_HIP(hipMalloc(&p->rnbr, sizeof(int32_t) * (size_t)m));
+  int32_t *rowmark = (int32_t *)ka, *row = (int32_t *)kb;
+  int64_t *segid = (int64_t *)va;
+  const unsigned dbits = (unsigned)bits_for(g->max_deg), tbits = (unsigned)bits_for(nblk - 1);
+  // one temporary buffer, as large as the largest library call needs
+  size_t q[6] = {0, 0, 0, 0, 0, 0};
+  BYO_HIP(rocprim::radix_sort_pairs(nullptr, q[0], vkey, vkey2, vidx, p->orig, (size_t)n, 0u, dbits, s));
+  BYO_HIP(rocprim::exclusive_scan(nullptr, q[1], p->rdeg, p->roff, (long long)0, (size_t)n,
+                                  rocprim::plus<long long>(), s));
+  BYO_HIP(rocprim::inclusive_scan(nullptr, q[2], rowmark, row, (size_t)m, rocprim::maximum<int32_t>(), s));
+  BYO_HIP(rocprim::radix_sort_pairs(nullptr, q[3], ka, kb, va, vb, (size_t)m, 0u, tbits, s));
+  BYO_HIP(rocprim::inclusive_scan(nullptr, q[4], ka, segid, (size_t)m, rocprim::plus<long long>(), s));
+  BYO_HIP(rocprim::exclusive_scan(nullptr, q[5], segid, segid, (long long)0, (size_t)m + 1,
+                                  rocprim::plus<long long>(), s));
+  size_t qmax = *std::max_element(q, q + 6);
+  void *ts = nullptr;
+  BYO_TRY(tmp.get((uint8_t **)&ts, qmax));
+  // 1. relabel by descending degree
+  tl_degkey_kernel<<<tl_blocks(n), TL_THREADS, 0, s>>>(g->deg, n, g->max_deg, vkey, vidx);
+  BYO_HIP(hipGetLastError());
+  BYO_HIP(rocprim::radix_sort_pairs(ts, qmax, vkey, vkey2, vidx, p->orig, (size_t)n, 0u, dbits, s));
+  tl_label_kernel<<<tl_blocks(n), TL_THREADS, 0, s>>>(p->orig, g->deg, n, p->rlabel, p->rdeg);
+  BYO_HIP(hipGetLastError());
+  // 2. relabelled row offsets and the row of every slot
+  BYO_HIP(rocprim::exclusive_scan(ts, qmax, p->rdeg, p->roff, (long long)0, (size_t)n, rocprim::plus<long long>(),
+                                  s));
+  BYO_TRY(fill_u64((uint64_t *)(p->roff + n), 1, (uint64_t)m, s));
+  BYO_HIP(hipMemsetAsync(rowmark, 0, sizeof(int32_t) * (size_t)m, s));
+  tl_rowmark_kernel<<<tl_blocks(n), TL_THREADS, 0, s>>>(p->roff, p->rdeg, n, rowmark);
+  BYO_HIP(hipGetLastError());
+  BYO_HIP(rocprim::inclusive_scan(ts, qmax, rowmark, row, (size_t)m, rocprim::maximum<int32_t>(), s));
+  // 3. relabelled CSR, tile keys and packed (source, destination) values
+  tl_entries_kernel<<<tl_blocks(m), TL_THREADS, 0, s>>>(g->off, g->nbr, p->orig, p->rlabel, p->roff, row, m, shift,
+                                                        p->rnbr, ka, va);
+  BYO_HIP(hipGetLastError());
+  // 4. group by tile, sources still ascending inside a tile
+  BYO_HIP(rocprim::radix_sort_pairs(ts, qmax, ka, kb, va, vb, (size_t)m, 0u, tbits, s));
+  int64_t *tile_off = nullptr, *tgrp = nullptr;
+  BYO_TRY(tmp.get(&tile_off, (size_t)nblk + 1));
+  BYO_TRY(tmp.get(&tgrp, (size_t)nblk + 1));
+  tl_tile_off_kernel<<<tl_blocks(nblk + 1), TL_THREADS, 0, s>>>(kb, m, nblk, tile_off);
+  BYO_HIP(hipGetLastError());
+  // 5. segments and their groups
+  uint32_t *flag = ka;
+  tl_segflag_kernel<<<tl_blocks(m), TL_THREADS, 0, s>>>(kb, vb, m, flag);
+  BYO_HIP(hipGetLastError());
+  BYO_HIP(rocprim::inclusive_scan(ts, qmax, flag, segid, (size_t)m, rocprim::plus<long long>(), s));
+  int64_t nseg = 0;
+  BYO_TRY(sync_read(s, segid + (m - 1), &nseg, sizeof(nseg)));
+  int64_t *segbeg = nullptr, *ngrp = nullptr, *gbefore = nullptr;
+  BYO_TRY(tmp.get(&segbeg, (size_t)nseg + 1));
+  BYO_TRY(tmp.get(&ngrp, (size_t)nseg + 1));
+  BYO_TRY(tmp.get(&gbefore, (size_t)nseg + 1));
+  tl_segbeg_kernel<<<tl_blocks(m), TL_THREADS, 0, s>>>(flag, segid, m, segbeg);
+  BYO_HIP(hipGetLastError());
+  tl_segroups_kernel<<<tl_blocks(nseg + 1), TL_THREADS, 0, s>>>(segbeg, nseg, ngrp);
+  BYO_HIP(hipGetLastError());
+  BYO_HIP(rocprim::exclusive_scan(ts, qmax, ngrp, gbefore, (long long)0, (size_t)nseg + 1,
+                                  rocprim::plus<long long>(), s));
+  tl_tile_groups_kernel<<<tl_blocks(nblk + 1), TL_THREADS, 0, s>>>(tile_off, segid, gbefore, m, nblk, nseg, tgrp);
+  BYO_HIP(hipGetLastError());
+  std::vector<int64_t> ptile((size_t)nblk + 1);
+  BYO_TRY(sync_read(s, tgrp, ptile.data(), sizeof(int64_t) * ptile.size()));
+  const int64_t ngroups = ptile[(size_t)nblk];
   BYO_CHECK(ngroups < ((int64_t)1 << 31), BYO_EINVAL, "too many entry groups");
-  std::vector<uint32_t> ent((size_t)mp);
-  std::vector<int32_t> anchor((size_t)ngroups);
-  run([&](unsigned t) {
-    for (int64_t b = b0[t]; b < b0[t + 1]; ++b) {
-      int64_t q = ptile[b];
-      for (int64_t i = tile_off[b], hi = tile_off[b + 1]; i < hi;) {
-        const int64_t j = group_end(i, hi);
-        const int32_t a = esrc[(size_t)i];
-        anchor[(size_t)(q / 64)] = a;
-        for (int64_t r = 0; r < 64; ++r) {
-          const int64_t x = i + r;
-          ent[(size_t)(q + r)] = x < j ? ((uint32_t)(esrc[(size_t)x] - a) | ((uint32_t)edst[(size_t)x] << 16))
-                                       : (dummy << 16);
-        }
-        q += 64;
-        i = j;
-      }
-    }
-  });
-  std::vector<int32_t>().swap(esrc);
-  std::vector<uint16_t>().swap(edst);
+  for (auto &x : ptile) x *= 64;
+  const int64_t mp = ngroups * 64;
+  p->mp = mp;
+  BYO_HIP(hipMalloc(&p->ent, sizeof(uint32_t) * (size_t)std::max<int64_t>(mp, 1)));
+  BYO_HIP(hipMalloc(&p->anchor, sizeof(int32_t) * (size_t)std::max<int64_t>(ngroups, 1)));
+  // padding points at the dummy slot 2^shift, one past the tile
+  BYO_TRY(fill_i32((int32_t *)p->ent, mp, (int32_t)((1u << shift) << 16), s));
+  tl_place_kernel<<<tl_blocks(m), TL_THREADS, 0, s>>>(vb, segid, segbeg, gbefore, m, p->ent, p->anchor);
+  BYO_HIP(hipGetLastError());
   // chunks: about 512 over the whole entry set, each tile cut into equal
   // pieces of whole groups
   const int64_t target = std::max<int64_t>(1 << 16, (mp + 511) / 512);
   std::vector<int64_t> cbeg;
   std::vector<int32_t> bfirst((size_t)nblk + 1), cblk;
   for (int64_t b = 0; b < nblk; ++b) {
-    bfirst[b] = (int32_t)cbeg.size();
-    int64_t lo = ptile[b], groups = (ptile[b + 1] - lo) / 64;
+    bfirst[(size_t)b] = (int32_t)cbeg.size();
+    int64_t lo = ptile[(size_t)b], groups = (ptile[(size_t)b + 1] - lo) / 64;
     if (groups == 0) continue;
     int64_t k = (groups * 64 + target - 1) / target;
     for (int64_t i = 0; i < k; ++i) {
@@ -218,59 +301,40 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
       cblk.push_back((int32_t)b);
     }
   }
-  bfirst[nblk] = (int32_t)cbeg.size();
-  const int64_t nchunks = (int64_t)cbeg.size();
+  bfirst[(size_t)nblk] = (int32_t)cbeg.size();
+  p->nchunks = (int64_t)cbeg.size();
   cbeg.push_back(mp);
-
-  byo_tiles *p = new byo_tiles();
-  p->shift = shift;
-  p->n = n;
-  p->m = m;
-  p->mp = mp;
-  p->nblk = nblk;
-  p->nchunks = nchunks;
-  p->h_label = std::move(label);
-  w.tiles = p;
-  BYO_HIP(hipMalloc(&p->ent, sizeof(uint32_t) * (size_t)mp));
-  BYO_HIP(hipMalloc(&p->anchor, sizeof(int32_t) * (size_t)ngroups));
-  BYO_HIP(hipMalloc(&p->rdeg, sizeof(int32_t) * (size_t)n));
-  BYO_HIP(hipMalloc(&p->orig, sizeof(int32_t) * (size_t)n));
   BYO_HIP(hipMalloc(&p->cbeg, sizeof(int64_t) * cbeg.size()));
   BYO_HIP(hipMalloc(&p->bfirst, sizeof(int32_t) * bfirst.size()));
-  BYO_HIP(hipMalloc(&p->cblk, sizeof(int32_t) * (size_t)nchunks));
-  BYO_HIP(hipMalloc(&p->cflag, sizeof(uint32_t) * (size_t)nchunks));
-  BYO_HIP(hipMalloc(&p->rlabel, sizeof(int32_t) * (size_t)n));
-  BYO_HIP(hipMemcpy(p->ent, ent.data(), sizeof(uint32_t) * (size_t)mp, hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->anchor, anchor.data(), sizeof(int32_t) * (size_t)ngroups, hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->rdeg, rdeg.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->orig, orig.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->cbeg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->bfirst, bfirst.data(), sizeof(int32_t) * bfirst.size(), hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->cblk, cblk.data(), sizeof(int32_t) * (size_t)nchunks, hipMemcpyHostToDevice));
-  BYO_HIP(hipMemcpy(p->rlabel, p->h_label.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
-  // the CSR in relabelled IDs (row w = row orig[w], neighbours relabelled), for
-  // push levels that run in the layout's order
-  {
-    std::vector<int64_t> roff((size_t)n + 1, 0);
-    for (int64_t x = 0; x < n; ++x) roff[(size_t)x + 1] = roff[(size_t)x] + rdeg[(size_t)x];
-    std::vector<int32_t> rnbr((size_t)m);
-    const std::vector<int32_t> &lab = p->h_label;
-    std::vector<int64_t> r0(T + 1, n);  // relabelled row ranges of about m / T entries
-    r0[0] = 0;
-    for (unsigned t = 1; t < T; ++t)
-      r0[t] = std::lower_bound(roff.begin(), roff.end(), m * (int64_t)t / (int64_t)T) - roff.begin();
-    for (unsigned t = 1; t <= T; ++t) r0[t] = std::max(r0[t], r0[t - 1]);
-    run([&](unsigned t) {
-      for (int64_t x = r0[t]; x < r0[t + 1]; ++x) {
-        const int64_t u = orig[(size_t)x], o = off[(size_t)u], d = off[(size_t)u + 1] - o;
-        for (int64_t i = 0; i < d; ++i) rnbr[(size_t)(roff[(size_t)x] + i)] = lab[(size_t)nbr[(size_t)(o + i)]];
-      }
-    });
-    BYO_HIP(hipMalloc(&p->roff, sizeof(int64_t) * (size_t)(n + 1)));
-    BYO_HIP(hipMalloc(&p->rnbr, sizeof(int32_t) * (size_t)m));
-    BYO_HIP(hipMemcpy(p->roff, roff.data(), sizeof(int64_t) * (size_t)(n + 1), hipMemcpyHostToDevice));
-    BYO_HIP(hipMemcpy(p->rnbr, rnbr.data(), sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice));
+  BYO_HIP(hipMalloc(&p->cblk, sizeof(int32_t) * (size_t)std::max<int64_t>(p->nchunks, 1)));
+  BYO_HIP(hipMalloc(&p->cflag, sizeof(uint32_t) * (size_t)std::max<int64_t>(p->nchunks, 1)));
+  BYO_HIP(hipMemcpyAsync(p->cbeg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice, s));
+  BYO_HIP(hipMemcpyAsync(p->bfirst, bfirst.data(), sizeof(int32_t) * bfirst.size(), hipMemcpyHostToDevice, s));
+  BYO_HIP(hipMemcpyAsync(p->cblk, cblk.data(), sizeof(int32_t) * cblk.size(), hipMemcpyHostToDevice, s));
+  // the temporaries and the host vectors must outlive the queued work
+  BYO_HIP(hipStreamSynchronize(s));
+  return BYO_OK;
+}
+
+byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
+  byo_workspace &w = g->ws;
+  BYO_CHECK(shift >= 12 && shift <= 14, BYO_EINVAL, "tile size must be 2^12 .. 2^14");
+  if (w.tiles && w.tiles->shift == shift) return BYO_OK;
+  tiles_release(w);
+  BYO_CHECK(tiles_wanted(g), BYO_EINVAL, "graph too small or too sparse for the tile layout");
+  BYO_CHECK(g->n <= ((int64_t)1 << 31) - 1, BYO_EINVAL, "graph too large for the tile layout");
+  byo_tiles *p = new byo_tiles();
+  p->shift = shift;
+  p->n = g->n;
+  p->m = g->m;
+  p->nblk = (g->n + (1ll << shift) - 1) >> shift;
+  const byo_status st = tiles_build(g, p, s);
+  if (st != BYO_OK) {
+    (void)hipStreamSynchronize(s);
+    tiles_free(p);
+    return st;
   }
+  w.tiles = p;
   return BYO_OK;
 }
 
