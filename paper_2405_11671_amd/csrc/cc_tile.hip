@@ -42,18 +42,36 @@ __global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const uint32_t *__r
   __syncthreads();
   const int64_t beg = cbeg[c], end = cbeg[c + 1];
   int mine = 0;
-  for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)CT_THREADS * CT_ILP) {
+  // Software-pipelined like the PageRank tile pass: the next round's entry
+  // words are requested before this round's bitmap and label gathers are
+  // consumed. A wavefront reads one whole group, so the anchor index is
+  // uniform (a scalar load); indices past the chunk end are clamped.
+  constexpr int64_t STEP = (int64_t)CT_THREADS * CT_ILP;
+  uint32_t wd[CT_ILP];
+  int32_t an[CT_ILP];
+  auto fetch = [&](int64_t f0) {
+#pragma unroll
+    for (int j = 0; j < CT_ILP; ++j) {
+      int64_t i = f0 + (int64_t)j * CT_THREADS;
+      i = i < end ? i : beg;  // a chunk is never empty
+      wd[j] = ent[i];
+      an[j] = anchor[__builtin_amdgcn_readfirstlane((int32_t)(i >> 6))];
+    }
+  };
+  int64_t e0 = beg + t;
+  fetch(e0);
+  for (; e0 < end; e0 += STEP) {
     int32_t u[CT_ILP];
     uint32_t d[CT_ILP];
     uint64_t ab[CT_ILP];
 #pragma unroll
     for (int j = 0; j < CT_ILP; ++j) {
-      int64_t i = e0 + (int64_t)j * CT_THREADS;
-      i = i < end ? i : beg;  // a chunk is never empty
-      tile_entry(ent, anchor, i, u[j], d[j]);
+      d[j] = wd[j] >> 16;
+      u[j] = an[j] + (int32_t)(wd[j] & 0xffffu);
     }
 #pragma unroll
     for (int j = 0; j < CT_ILP; ++j) ab[j] = abits[u[j] >> 6];
+    fetch(e0 + STEP);
     bool ok[CT_ILP];
     bool some = false;
 #pragma unroll

@@ -225,6 +225,13 @@ struct byo_tiles {
   int32_t *rnbr = nullptr;    // [m] its neighbours, relabelled
   void *partial = nullptr;    // chunk results, sized by the user (tiles_partial)
   size_t partial_bytes = 0;
+  // PageRank apply plan: one word per apply workgroup, its first relabelled
+  // vertex with bit 0 set for a many-chunk tile (64 vertices, chunk sums
+  // split four ways) and clear otherwise (1024 vertices); adpart holds one
+  // dangling partial per apply workgroup.
+  int32_t *aplan = nullptr;   // [napply]
+  float *adpart = nullptr;    // [napply]
+  int64_t napply = 0;
 };
 // Relabelled source and tile-local destination of entry e. The caller's
 // wavefront reads one whole group (e / 64 is the same in every lane), so the
@@ -249,7 +256,7 @@ void tiles_release(byo_workspace &w);
 // tiled PageRank step (pagerank_tile.hip); opt = byo_opts::pr_blocked
 int pr_tile_shift(int32_t opt);
 byo_status pr_tile_step(byo_graph *g, const float *contrib, float damping, float *contrib_next, float *out,
-                        hipStream_t s);
+                        const float *dpart_in, int64_t nparts_in, hipStream_t s);
 
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);

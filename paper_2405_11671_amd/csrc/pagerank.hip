@@ -296,8 +296,9 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     int c = 0;
     for (int32_t t = 0; t < iters; ++t) {
       bool last = t + 1 == iters;
+      const byo_tiles *tl = g->ws.tiles;
       BYO_TRY(pr_tile_step(g, w.contrib[c], (float)damping, last ? nullptr : w.contrib[1 - c], last ? d_rank : nullptr,
-                           s));
+                           t == 0 ? w.dpart : tl->adpart, t == 0 ? nb : tl->napply, s));
       c = 1 - c;
     }
     return BYO_OK;
