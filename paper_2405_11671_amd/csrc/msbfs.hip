@@ -496,10 +496,10 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
 template <int W>
 __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
     const uint64_t *__restrict__ partial, const uint32_t *__restrict__ cflag, const int32_t *__restrict__ bfirst,
-    uint64_t *__restrict__ seen, uint64_t *__restrict__ front_cur, uint64_t *__restrict__ front_next,
-    const uint64_t *__restrict__ abits_cur, uint64_t *__restrict__ abits_next, uint64_t *__restrict__ fbits,
-    const int32_t *__restrict__ rdeg, const int32_t *__restrict__ orig, uint8_t *__restrict__ depth, int32_t k,
-    uint8_t newdepth, int64_t n, byo_counters *__restrict__ ctr) {
+    uint64_t *__restrict__ seen, uint64_t *__restrict__ front_next, uint64_t *__restrict__ abits_next,
+    uint64_t *__restrict__ fbits, const int32_t *__restrict__ rdeg, const int32_t *__restrict__ orig,
+    uint8_t *__restrict__ depth, int32_t k, uint8_t newdepth, int64_t n, byo_counters *__restrict__ ctr,
+    unsigned long long *__restrict__ tally) {
   constexpr int B = 1 << MT_SHIFT;
   uint64_t full[W];
 #pragma unroll
@@ -507,7 +507,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
     int bits = k - 64 * w;
     full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
   }
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, pairs = 0, edges = 0;
   const bool vec_depth = (k & 15) == 0 && ((uintptr_t)depth & 15) == 0;
   // capped grid: a few thousand counter atomics per level, not one per 256 vertices
   for (int64_t base = (int64_t)blockIdx.x * MS_BLOCK; base < n; base += (int64_t)gridDim.x * MS_BLOCK) {
@@ -519,10 +519,6 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
     for (int w = 0; w < W; ++w) nb[w] = sv[w] = 0ull;
     int64_t row = 0;
     if (valid) {
-      if ((abits_cur[v >> 6] >> (v & 63)) & 1ull) {
-#pragma unroll
-        for (int w = 0; w < W; ++w) front_cur[v * W + w] = 0ull;  // consumed
-      }
       now_full = (fbits[v >> 6] >> (v & 63)) & 1ull;
       if (!now_full) {
         const int64_t b = v >> MT_SHIFT, l = v & (B - 1);
@@ -575,16 +571,24 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
           }
           row = orig[v];
           degsum += (unsigned long long)rdeg[v];
+          unsigned long long pc = 0;
+#pragma unroll
+          for (int w = 0; w < W; ++w) pc += (unsigned long long)__popcll(nb[w]);
+          pairs += pc;
+          edges += pc * (unsigned long long)rdeg[v];
         } else {
 #pragma unroll
           for (int w = 0; w < W; ++w) nb[w] = 0ull;
         }
       }
     }
-    if (vec_depth)
+    if (!depth) {
+      // depths of this level come from the level history later
+    } else if (vec_depth) {
       write_depths_wave<W>(depth, k, row, nb, sv, newdepth);  // every lane of the wavefront
-    else if (any)
+    } else if (any) {
       write_depths<W>(depth, row, k, nb, sv, newdepth);
+    }
     uint64_t am = __ballot(any);
     uint64_t fm = __ballot(now_full);  // vertices past n count as full
     if (lane_id() == 0 && v < n) {
@@ -595,24 +599,96 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
   }
   unsigned long long ts = block_sum<unsigned long long, MS_BLOCK>(degsum);
   unsigned long long tc = block_sum<unsigned long long, MS_BLOCK>(count);
+  unsigned long long tp = block_sum<unsigned long long, MS_BLOCK>(pairs);
+  unsigned long long te = block_sum<unsigned long long, MS_BLOCK>(edges);
   if (threadIdx.x == 0) {
     if (ts) atomicAdd(&ctr->degsum, ts);
     if (tc) atomicAdd(&ctr->count, tc);
+    if (tp) atomicAdd(&tally[0], tp);
+    if (te) atomicAdd(&tally[1], te);
   }
 }
 
-// Sources: seen/front bits at the relabelled vertex, frontier bitmap bit,
-// depth 0 at the original vertex.
-__global__ void ms_tile_init_kernel(const int32_t *__restrict__ srcs, const int32_t *__restrict__ rlabel, int32_t k,
-                                    int32_t W, uint64_t *seen, uint64_t *front, uint64_t *abits, uint8_t *depth) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Sources, in one workgroup (k <= 256 threads): the source vertices' frontier
+// records are cleared (the slot may hold an earlier run's masks), then seen
+// and frontier bits at the relabelled vertex and its active bitmap bit. Depth
+// 0 comes from the level history. The tallies (reached (vertex, source)
+// pairs, and the degrees summed over them) start from the k sources and are
+// added to level by level.
+__global__ void __launch_bounds__(256) ms_tile_init_kernel(const int32_t *__restrict__ srcs,
+                                                           const int32_t *__restrict__ rlabel, int32_t k, int32_t W,
+                                                           uint64_t *seen, uint64_t *front, uint64_t *abits,
+                                                           const int32_t *__restrict__ rdeg,
+                                                           unsigned long long *__restrict__ tally) {
+  const int j = threadIdx.x;
+  const int64_t r = j < k ? (int64_t)rlabel[srcs[j]] : 0;
+  // (source, source) pairs and their degrees start the reached and edge tallies
+  const unsigned long long e = block_sum<unsigned long long, 256>(j < k ? (unsigned long long)rdeg[r] : 0ull);
+  if (j == 0) {
+    atomicAdd(&tally[0], (unsigned long long)k);
+    atomicAdd(&tally[1], e);
+  }
+  if (j < k)
+    for (int w = 0; w < W; ++w) front[r * W + w] = 0ull;
+  __syncthreads();
   if (j < k) {
-    int64_t r = rlabel[srcs[j]];
-    unsigned long long bit = 1ull << (j & 63);
+    const unsigned long long bit = 1ull << (j & 63);
     atomicOr((unsigned long long *)&seen[r * W + (j >> 6)], bit);
     atomicOr((unsigned long long *)&front[r * W + (j >> 6)], bit);
     atomicOr((unsigned long long *)&abits[r >> 6], 1ull << (r & 63));
-    depth[(int64_t)srcs[j] * k + j] = 0;
+  }
+}
+
+// Depth rows from the level history: level l's frontier masks f[l] (valid
+// where the active bitmap a[l] has the vertex) hold the sources first seen at
+// depth l; sources never seen keep 255. Rows are taken in the layout's vertex
+// order, so the history is read front to back and each row (orig[w], in the
+// caller's order) is written whole by 2^lg consecutive threads, one 16-source
+// group each (the groups' count rounded up to a power of two). A thread
+// first loads the active words of every level, then the mask words of the
+// levels that have its vertex, each round with all levels in flight. (Taking
+// rows in the caller's order instead writes the array front to back but
+// scatters the history reads, and measured slower.)
+constexpr int MS_HIST = 16;
+struct ms_hist_args {
+  const uint64_t *f[MS_HIST];
+  const uint64_t *a[MS_HIST];
+};
+
+template <int W>
+__global__ void __launch_bounds__(256) ms_depth_flush_kernel(ms_hist_args h, int32_t L,
+                                                             const int32_t *__restrict__ orig, int64_t n, int32_t k,
+                                                             int lg, uint8_t *__restrict__ depth) {
+  const int G = (k + 15) >> 4;
+  const bool vec = (k & 15) == 0 && ((uintptr_t)depth & 15) == 0;
+  const int g = threadIdx.x & ((1 << lg) - 1);
+  const int64_t rows = 256 >> lg;
+  for (int64_t w = (int64_t)blockIdx.x * rows + (threadIdx.x >> lg); w < n; w += (int64_t)gridDim.x * rows) {
+    if (g >= G) continue;
+    const int word = g >> 2, sh = 16 * (g & 3);
+    const uint64_t bit = 1ull << (w & 63);
+    uint64_t act[MS_HIST], fm[MS_HIST];
+#pragma unroll
+    for (int l = 0; l < MS_HIST; ++l) act[l] = l < L ? h.a[l][w >> 6] : 0ull;
+#pragma unroll
+    for (int l = 0; l < MS_HIST; ++l) fm[l] = (act[l] & bit) ? h.f[l][w * W + word] : 0ull;
+    uint32_t c[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+    for (int l = 0; l < MS_HIST; ++l) {
+      uint32_t bits = (uint32_t)(fm[l] >> sh) & 0xFFFFu;
+      while (bits) {
+        const int j = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const uint32_t s8 = 8u * (uint32_t)(j & 3);
+        c[j >> 2] = (c[j >> 2] & ~(0xFFu << s8)) | ((uint32_t)l << s8);
+      }
+    }
+    uint8_t *row = depth + (int64_t)orig[w] * k + 16 * g;
+    if (vec) {
+      *(uint4 *)row = make_uint4(c[0], c[1], c[2], c[3]);
+    } else {
+      for (int j = 0; j < 16 && 16 * g + j < k; ++j) row[j] = (uint8_t)(c[j >> 2] >> (8 * (j & 3)));
+    }
   }
 }
 
@@ -654,6 +730,13 @@ struct ms_ws {
   int32_t *touched = nullptr, *active[2] = {nullptr, nullptr}, *srcs = nullptr;
   byo_counters *ctr = nullptr;
   unsigned long long *tally = nullptr;
+  // Tiled runs keep each level's frontier masks and active bitmap (slots 0
+  // and 1 are front[] and abits[], the rest allocated on first use) and build
+  // the depths from them in one pass.
+  int nhist = 0;
+  uint64_t *hfront[MS_HIST] = {}, *habits[MS_HIST] = {};
+  // visit and the touched bits are back to zero after a completed tiled run
+  bool tiled_clean = false;
 };
 
 static void ms_free(ms_ws &m) {
@@ -661,6 +744,10 @@ static void ms_free(ms_ws &m) {
                m.ctr, m.tally, m.abits[0], m.abits[1], m.fbits};
   for (void *x : p)
     if (x) (void)hipFree(x);
+  for (int i = 2; i < m.nhist; ++i) {
+    if (m.hfront[i]) (void)hipFree(m.hfront[i]);
+    if (m.habits[i]) (void)hipFree(m.habits[i]);
+  }
   m = ms_ws();
 }
 
@@ -683,7 +770,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
     const int32_t *__restrict__ orig, uint64_t *__restrict__ visit, uint64_t *__restrict__ seen,
     uint64_t *__restrict__ front_next, uint64_t *__restrict__ touched_bits, uint64_t *__restrict__ abits_next,
     uint64_t *__restrict__ fbits, uint8_t *__restrict__ depth, int32_t k, uint8_t newdepth,
-    byo_counters *__restrict__ ctr) {
+    byo_counters *__restrict__ ctr, unsigned long long *__restrict__ tally) {
   uint64_t full[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
@@ -691,7 +778,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
     full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
   }
   const int64_t cnt = (int64_t)tctr->count;
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, pairs = 0, edges = 0;
   for (int64_t i = (int64_t)blockIdx.x * MS_BLOCK + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * MS_BLOCK) {
     const int32_t v = touched[i];
     uint64_t nb[W], sv[W];
@@ -712,9 +799,14 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
         seen[(int64_t)v * W + w] = sv[w] | nb[w];
         front_next[(int64_t)v * W + w] = nb[w];
       }
-      write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
+      if (depth) write_depths<W>(depth, orig[v], k, nb, sv, newdepth);
       degsum += (unsigned long long)rdeg[v];
       count += 1;
+      unsigned long long pc = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) pc += (unsigned long long)__popcll(nb[w]);
+      pairs += pc;
+      edges += pc * (unsigned long long)rdeg[v];
       atomicOr((unsigned long long *)&abits_next[v >> 6], (unsigned long long)bit);
       if (now_full) atomicOr((unsigned long long *)&fbits[v >> 6], (unsigned long long)bit);
     }
@@ -722,76 +814,136 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
   }
   const unsigned long long ts = block_sum<unsigned long long, MS_BLOCK>(degsum);
   const unsigned long long tc = block_sum<unsigned long long, MS_BLOCK>(count);
+  const unsigned long long tp = block_sum<unsigned long long, MS_BLOCK>(pairs);
+  const unsigned long long te = block_sum<unsigned long long, MS_BLOCK>(edges);
   if (threadIdx.x == 0) {
     if (ts) atomicAdd(&ctr->degsum, ts);
     if (tc) atomicAdd(&ctr->count, tc);
+    if (tp) atomicAdd(&tally[0], tp);
+    if (te) atomicAdd(&tally[1], te);
   }
 }
 
+// Level buffers of a tiled level: the current and next frontier masks and
+// active bitmaps (history slots), the active list buffer, and the depth array
+// (null while the depths come from the history).
+struct ms_level_bufs {
+  uint64_t *front_cur, *front_next, *abits_cur, *abits_next;
+  int32_t *active;
+  uint8_t *depth;
+};
+
 template <int W>
-static byo_status launch_tile_push(byo_graph *g, const byo_tiles *t, ms_ws &mw, int cur, int64_t acount,
-                                   long long adeg, uint8_t *depth, int32_t k, uint8_t nd, byo_counters *tctr,
+static byo_status launch_tile_push(byo_graph *g, const byo_tiles *t, ms_ws &mw, const ms_level_bufs &lb,
+                                   int64_t acount, long long adeg, int32_t k, uint8_t nd, byo_counters *tctr,
                                    byo_counters *ctr, const byo_opts &o, hipStream_t s) {
   const int64_t n = g->n, words = (n + 63) / 64;
-  const int nx = 1 - cur;
   byo_workspace &w = g->ws;
   // active list from the frontier bitmap, then push over the relabelled CSR
-  BYO_TRY(bitmap_to_ids(mw.abits[cur], words, n, mw.active[cur], w.partial, w.partial_cap,
-                        (unsigned long long *)w.misc, s));
+  BYO_TRY(bitmap_to_ids(lb.abits_cur, words, n, lb.active, w.partial, w.partial_cap, (unsigned long long *)w.misc,
+                        s));
   byo_graph rg = tiles_view(g, t);
   level_io io;
   std::memset(&io, 0, sizeof(io));
-  io.in_ids = mw.active[cur];
+  io.in_ids = lb.active;
   io.in_count = acount;
   io.out_ids = mw.touched;
   io.out_bits = mw.tbits;
   io.ctr = tctr;
-  ms_state ms{W, mw.front[cur], mw.seen, mw.visit};
+  ms_state ms{W, lb.front_cur, mw.seen, mw.visit};
   BYO_TRY(ms_push_level(&rg, BYO_V_PUSH_EDGE, ms, io, o, s, adeg));
-  BYO_TRY(fill_u64(mw.abits[nx], words, 0ull, s));
+  BYO_TRY(fill_u64(lb.abits_next, words, 0ull, s));
   {
     ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
     const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (adeg + MS_BLOCK - 1) / MS_BLOCK), 2048);
     ms_tile_finish_kernel<W><<<nb, MS_BLOCK, 0, s>>>(mw.touched, tctr, t->rdeg, t->orig, mw.visit, mw.seen,
-                                                     mw.front[nx], mw.tbits, mw.abits[nx], mw.fbits, depth, k, nd,
-                                                     ctr);
+                                                     lb.front_next, mw.tbits, lb.abits_next, mw.fbits, lb.depth, k,
+                                                     nd, ctr, mw.tally);
   }
-  launch_clear<W>(mw.active[cur], acount, mw.front[cur], s);  // consumed frontier back to zero
   BYO_HIP(hipGetLastError());
   return BYO_OK;
 }
 
 template <int W>
-static void launch_tile_level(const byo_tiles *t, ms_ws &mw, int cur, uint8_t *depth, int32_t k, uint8_t nd,
+static void launch_tile_level(const byo_tiles *t, ms_ws &mw, const ms_level_bufs &lb, int32_t k, uint8_t nd,
                               int64_t n, byo_counters *ctr, hipStream_t s) {
   int64_t words = (n + 63) / 64;
-  int nx = 1 - cur;
   {
     ktimer_scope kt(BYO_K_MSBFS_PULL, s);
-    ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, t->cblk,
-                                                                 mw.front[cur],
-                                                                 mw.abits[cur], mw.fbits, words,
+    ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, t->cblk, lb.front_cur,
+                                                                 lb.abits_cur, mw.fbits, words,
                                                                  (uint64_t *)t->partial, t->cflag);
   }
   ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
   ms_tile_apply_kernel<W><<<(unsigned)std::min<int64_t>((n + MS_BLOCK - 1) / MS_BLOCK, 2048), MS_BLOCK, 0, s>>>(
-      (const uint64_t *)t->partial, t->cflag, t->bfirst, mw.seen, mw.front[cur], mw.front[nx], mw.abits[cur],
-      mw.abits[nx], mw.fbits, t->rdeg, t->orig, depth, k, nd, n, ctr);
+      (const uint64_t *)t->partial, t->cflag, t->bfirst, mw.seen, lb.front_next, lb.abits_next, mw.fbits, t->rdeg,
+      t->orig, lb.depth, k, nd, n, ctr, mw.tally);
+}
+
+// History slots for the tiled levels: as many as fit in a quarter of the free
+// device memory, at most MS_HIST (two always exist).
+static byo_status ms_hist_ensure(ms_ws &mw, int64_t n, int W) {
+  if (mw.nhist > 0) return BYO_OK;
+  const size_t words = (size_t)std::max<int64_t>((n + 63) / 64, 1);
+  const size_t per = sizeof(uint64_t) * ((size_t)n * W + words);
+  size_t fr = 0, tot = 0;
+  BYO_HIP(hipMemGetInfo(&fr, &tot));
+  int H = 2;
+  while (H < MS_HIST && (size_t)(H - 1) * per <= fr / 4) ++H;
+  mw.hfront[0] = mw.front[0];
+  mw.hfront[1] = mw.front[1];
+  mw.habits[0] = mw.abits[0];
+  mw.habits[1] = mw.abits[1];
+  mw.nhist = 2;
+  for (int i = 2; i < H; ++i) {
+    BYO_HIP(hipMalloc(&mw.hfront[i], sizeof(uint64_t) * (size_t)n * W));
+    BYO_HIP(hipMalloc(&mw.habits[i], sizeof(uint64_t) * words));
+    mw.nhist = i + 1;
+  }
+  return BYO_OK;
+}
+
+static void launch_depth_flush(const ms_ws &mw, int32_t L, const byo_tiles *t, int64_t n, int32_t k, int W,
+                               uint8_t *depth, hipStream_t s) {
+  ms_hist_args h;
+  for (int i = 0; i < MS_HIST; ++i) {
+    h.f[i] = i < mw.nhist ? mw.hfront[i] : nullptr;
+    h.a[i] = i < mw.nhist ? mw.habits[i] : nullptr;
+  }
+  const int G = (k + 15) / 16;
+  int lg = 0;
+  while ((1 << lg) < G) ++lg;
+  const int64_t rows = 256 >> lg;
+  const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + rows - 1) / rows), 65536);
+  ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
+  switch (W) {
+    case 1: ms_depth_flush_kernel<1><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
+    case 2: ms_depth_flush_kernel<2><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
+    case 3: ms_depth_flush_kernel<3><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
+    default: ms_depth_flush_kernel<4><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
+  }
 }
 
 // Levels in the layout's vertex order, direction-optimising like the CSR
 // path: a push over the relabelled CSR while |U| + sum(deg U) <= m / div,
-// else a pass over the tiles. The caller has zeroed seen, both frontier
-// buffers, the touched and full bitmaps and the counters, and filled depth
-// with 255.
+// else a pass over the tiles. Level l's frontier masks and active bitmap go
+// to history slot l; the depth rows are built from the slots in one pass at
+// the end, or just before a level would need a slot beyond the last. Levels
+// after that alternate between the last two slots and write their depths
+// directly. The caller has zeroed seen, the full bitmap and the counters
+// (and visit and the touched bits unless a tiled run left them zero).
 static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
                                uint8_t *d_depth, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(tiles_ensure(g, MT_SHIFT, s));
   byo_tiles *t = g->ws.tiles;
   BYO_TRY(tiles_partial(t, sizeof(uint64_t) * (size_t)W << MT_SHIFT));
   const int64_t n = g->n, words = (n + 63) / 64;
-  BYO_HIP(hipMemsetAsync(mw.abits[0], 0, sizeof(uint64_t) * (size_t)words, s));
-  ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, t->rlabel, k, W, mw.seen, mw.front[0], mw.abits[0], d_depth);
+  BYO_TRY(ms_hist_ensure(mw, n, W));
+  const int H = mw.nhist;
+  auto slot = [H](int l) { return l < H ? l : (H - 2) + ((l - H) & 1); };
+  BYO_HIP(hipMemsetAsync(mw.habits[0], 0, sizeof(uint64_t) * (size_t)words, s));
+  ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, t->rlabel, k, W, mw.seen, mw.hfront[0], mw.habits[0], t->rdeg,
+                                        mw.tally);
   BYO_HIP(hipGetLastError());
   // first frontier: the distinct sources (from the frontier bitmap) and their
   // degree sum
@@ -799,7 +951,7 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
   long long adeg = 0;
   {
     unsigned long long cnt = 0;
-    BYO_TRY(bitmap_to_ids(mw.abits[0], words, n, mw.active[0], g->ws.partial, g->ws.partial_cap,
+    BYO_TRY(bitmap_to_ids(mw.habits[0], words, n, mw.active[0], g->ws.partial, g->ws.partial_cap,
                           (unsigned long long *)g->ws.misc, s));
     BYO_TRY(sync_read(s, g->ws.misc, &cnt, sizeof(cnt)));
     acount = (int64_t)cnt;
@@ -810,29 +962,38 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
   const int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
-  int cur = 0, level = 0;
+  int level = 0;
+  bool flushed = false;
   while (acount > 0) {
     if (level + 1 >= MS_MAX_LEVELS) {
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "a distance reached 255 (depths are uint8)");
     }
+    if (level + 1 == H) {  // the next level needs a slot the history still uses
+      launch_depth_flush(mw, H, t, n, k, W, d_depth, s);
+      BYO_HIP(hipGetLastError());
+      flushed = true;
+    }
     const uint8_t nd = (uint8_t)(level + 1);
+    const int cs = slot(level), ns = slot(level + 1);
+    const ms_level_bufs lb{mw.hfront[cs], mw.hfront[ns], mw.habits[cs], mw.habits[ns], mw.active[level & 1],
+                           flushed ? d_depth : nullptr};
     byo_counters *tctr = mw.ctr + 2 * level, *ctr = mw.ctr + 2 * level + 1;
     const bool fixed_pull = o.fixed_variant == BYO_V_PULL_THREAD || o.fixed_variant == BYO_V_PULL_WAVE;
     const bool push = o.selector == BYO_SEL_FIXED ? !fixed_pull : acount + adeg <= g->m / div;
     if (push) {
       switch (W) {
-        case 1: BYO_TRY(launch_tile_push<1>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
-        case 2: BYO_TRY(launch_tile_push<2>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
-        case 3: BYO_TRY(launch_tile_push<3>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
-        default: BYO_TRY(launch_tile_push<4>(g, t, mw, cur, acount, adeg, d_depth, k, nd, tctr, ctr, o, s)); break;
+        case 1: BYO_TRY(launch_tile_push<1>(g, t, mw, lb, acount, adeg, k, nd, tctr, ctr, o, s)); break;
+        case 2: BYO_TRY(launch_tile_push<2>(g, t, mw, lb, acount, adeg, k, nd, tctr, ctr, o, s)); break;
+        case 3: BYO_TRY(launch_tile_push<3>(g, t, mw, lb, acount, adeg, k, nd, tctr, ctr, o, s)); break;
+        default: BYO_TRY(launch_tile_push<4>(g, t, mw, lb, acount, adeg, k, nd, tctr, ctr, o, s)); break;
       }
     } else {
       switch (W) {
-        case 1: launch_tile_level<1>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
-        case 2: launch_tile_level<2>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
-        case 3: launch_tile_level<3>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
-        default: launch_tile_level<4>(t, mw, cur, d_depth, k, nd, n, ctr, s); break;
+        case 1: launch_tile_level<1>(t, mw, lb, k, nd, n, ctr, s); break;
+        case 2: launch_tile_level<2>(t, mw, lb, k, nd, n, ctr, s); break;
+        case 3: launch_tile_level<3>(t, mw, lb, k, nd, n, ctr, s); break;
+        default: launch_tile_level<4>(t, mw, lb, k, nd, n, ctr, s); break;
       }
     }
     BYO_HIP(hipGetLastError());
@@ -840,18 +1001,18 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
     BYO_TRY(sync_read(s, ctr, &c, sizeof(c)));
     st.variant_count[push ? BYO_V_PUSH_EDGE : BYO_V_PULL_WAVE]++;
     ++level;
-    cur = 1 - cur;
     acount = (int64_t)c.count;
     adeg = (long long)c.degsum;
   }
-  ms_tally_kernel<<<(unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096), MS_BLOCK, 0, s>>>(
-      mw.seen, W, t->rdeg, n, mw.tally);
+  // levels 0 .. level are in slots 0 .. level (the last one empty)
+  if (!flushed) launch_depth_flush(mw, level + 1, t, n, k, W, d_depth, s);
   unsigned long long tl[2] = {0, 0};
   BYO_TRY(sync_read(s, mw.tally, tl, sizeof(tl)));
   st.levels = level;
   st.reached = (int64_t)tl[0];
   st.edges = (int64_t)tl[1];
   if (stats) *stats = st;
+  mw.tiled_clean = true;
   return BYO_OK;
 }
 }  // namespace byo
@@ -895,6 +1056,26 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     mw.W = W;
   }
   size_t vb = sizeof(uint64_t) * (size_t)n * W;
+  std::vector<int32_t> hs(k);
+  for (int32_t j = 0; j < k; ++j) hs[j] = (int32_t)h_srcs[j];
+  BYO_HIP(hipMemcpyAsync(mw.srcs, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+  if (o.tiled && tiles_wanted(g)) {
+    // the frontier slots need no clearing and the depth rows are written whole
+    BYO_HIP(hipMemsetAsync(mw.seen, 0, vb, s));
+    if (!mw.tiled_clean) {
+      BYO_HIP(hipMemsetAsync(mw.visit, 0, vb, s));
+      BYO_HIP(hipMemsetAsync(mw.tbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
+    }
+    BYO_HIP(hipMemsetAsync(mw.fbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
+    BYO_HIP(hipMemsetAsync(mw.ctr, 0, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1), s));
+    BYO_HIP(hipMemsetAsync(mw.tally, 0, sizeof(unsigned long long) * 2, s));
+    mw.tiled_clean = false;
+    byo_status r = ms_tiled_run(g, mw, k, W, d_depth, o, s, stats);
+    // the copy of hs must stay alive until the stream has read it
+    if (r != BYO_OK) (void)hipStreamSynchronize(s);
+    return r;
+  }
+  mw.tiled_clean = false;
   BYO_HIP(hipMemsetAsync(mw.seen, 0, vb, s));
   BYO_HIP(hipMemsetAsync(mw.front[0], 0, vb, s));
   BYO_HIP(hipMemsetAsync(mw.front[1], 0, vb, s));
@@ -908,10 +1089,6 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (total / 16 + 255) / 256), 65536);
     u8_fill_kernel<<<nb, 256, 0, s>>>(d_depth, total, 255);
   }
-  std::vector<int32_t> hs(k);
-  for (int32_t j = 0; j < k; ++j) hs[j] = (int32_t)h_srcs[j];
-  BYO_HIP(hipMemcpyAsync(mw.srcs, hs.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
-  if (o.tiled && tiles_wanted(g)) return ms_tiled_run(g, mw, k, W, d_depth, o, s, stats);
   ms_init_kernel<<<1, 256, 0, s>>>(mw.srcs, k, W, mw.seen, mw.front[0], d_depth);
   // first active list: the distinct sources
   std::vector<int32_t> act(hs);

@@ -42,6 +42,21 @@ def hub_over_er(leaves=70000, avg_degree=8.0, seed=13):
     return pairs(n, src, dst, f"hub{leaves}_er{avg_degree:g}")
 
 
+def king_lattice(rows=200, cols=400):
+    """rows x cols lattice with the 8 king-move neighbours: average degree
+    near 8 (so the tile layout applies) and a diameter of max(rows, cols) - 1,
+    for traversals with far more levels than the tiled multi-source run keeps
+    frontier history for."""
+    r, c = np.meshgrid(np.arange(rows), np.arange(cols), indexing="ij")
+    v = (r * cols + c).ravel()
+    src, dst = [], []
+    for dr, dc in ((0, 1), (1, 0), (1, 1), (1, -1)):
+        ok = ((r + dr < rows) & (c + dc >= 0) & (c + dc < cols)).ravel()
+        src.append(v[ok])
+        dst.append(v[ok] + dr * cols + dc)
+    return pairs(rows * cols, np.concatenate(src), np.concatenate(dst), f"king{rows}x{cols}")
+
+
 def small_suite():
     """Graphs that finish in the oracle in well under a second."""
     return [

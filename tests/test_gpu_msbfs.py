@@ -69,6 +69,30 @@ def test_msbfs_tiled_matches_oracle(pi, k):
     assert st2["edges"] == st["edges"] and st2["reached"] == st["reached"]
 
 
+@pytest.mark.parametrize("k", [16, 150, 256])
+def test_msbfs_tiled_many_levels(k):
+    """A king-move lattice from sources near its middle: about 200 levels, far
+    more than the frontier-history slots, so the depth rows are built from the
+    history partway and the later levels write their depths on top."""
+    p = graphs.king_lattice()
+    g, og = build(p)
+    assert g.m >= 4 * g.n >= 4 * 65536
+    rows, cols = 200, 400
+    rng = np.random.default_rng(7 + k)
+    r = rng.integers(90, 110, k)
+    c = rng.integers(190, 210, k)
+    srcs = r * cols + c
+    D, st = byo.msbfs(g, srcs, tiled=1)
+    want = og.msbfs(srcs)
+    assert st["levels"] > 100
+    assert np.array_equal(D.cpu().numpy(), want), k
+    # the Chebyshev distance is the closed form on this lattice
+    vr, vc = np.divmod(np.arange(g.n), cols)
+    j = k - 1
+    cheb = np.maximum(np.abs(vr - r[j]), np.abs(vc - c[j]))
+    assert np.array_equal(want.reshape(g.n, k)[:, j], cheb)
+
+
 @pytest.mark.parametrize("p", SUITE, ids=[p.name for p in SUITE])
 def test_msbfs_tiled_falls_back_below_size_cut(p):
     """tiled = 1 on graphs the layout does not take runs over the CSR."""
