@@ -641,14 +641,12 @@ __global__ void __launch_bounds__(256) ms_tile_init_kernel(const int32_t *__rest
 
 // Depth rows from the level history: level l's frontier masks f[l] (valid
 // where the active bitmap a[l] has the vertex) hold the sources first seen at
-// depth l; sources never seen keep 255. Rows are taken in the layout's vertex
-// order, so the history is read front to back and each row (orig[w], in the
-// caller's order) is written whole by 2^lg consecutive threads, one 16-source
-// group each (the groups' count rounded up to a power of two). A thread
-// first loads the active words of every level, then the mask words of the
-// levels that have its vertex, each round with all levels in flight. (Taking
-// rows in the caller's order instead writes the array front to back but
-// scatters the history reads, and measured slower.)
+// depth l; sources never seen keep 255. One thread per (relabelled vertex w,
+// 64-source word), so a wavefront covers 64 / W vertices: per level one load
+// of their shared active word and one contiguous load of their mask words,
+// all levels in flight. A word's 64 bits become 64 depth bytes four at a time
+// (a 4-bit mask times 0x00204081 puts bit j at bit 8j), and the thread writes
+// its 64 bytes of row orig[w] (the caller's order).
 constexpr int MS_HIST = 16;
 struct ms_hist_args {
   const uint64_t *f[MS_HIST];
@@ -658,36 +656,39 @@ struct ms_hist_args {
 template <int W>
 __global__ void __launch_bounds__(256) ms_depth_flush_kernel(ms_hist_args h, int32_t L,
                                                              const int32_t *__restrict__ orig, int64_t n, int32_t k,
-                                                             int lg, uint8_t *__restrict__ depth) {
-  const int G = (k + 15) >> 4;
+                                                             uint8_t *__restrict__ depth) {
   const bool vec = (k & 15) == 0 && ((uintptr_t)depth & 15) == 0;
-  const int g = threadIdx.x & ((1 << lg) - 1);
-  const int64_t rows = 256 >> lg;
-  for (int64_t w = (int64_t)blockIdx.x * rows + (threadIdx.x >> lg); w < n; w += (int64_t)gridDim.x * rows) {
-    if (g >= G) continue;
-    const int word = g >> 2, sh = 16 * (g & 3);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * W; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = i / W;
+    const int word = (int)(i - w * W);
     const uint64_t bit = 1ull << (w & 63);
     uint64_t act[MS_HIST], fm[MS_HIST];
 #pragma unroll
     for (int l = 0; l < MS_HIST; ++l) act[l] = l < L ? h.a[l][w >> 6] : 0ull;
 #pragma unroll
-    for (int l = 0; l < MS_HIST; ++l) fm[l] = (act[l] & bit) ? h.f[l][w * W + word] : 0ull;
-    uint32_t c[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    for (int l = 0; l < MS_HIST; ++l) fm[l] = (act[l] & bit) ? h.f[l][i] : 0ull;
+    uint32_t c[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) c[q] = 0xFFFFFFFFu;
 #pragma unroll
     for (int l = 0; l < MS_HIST; ++l) {
-      uint32_t bits = (uint32_t)(fm[l] >> sh) & 0xFFFFu;
-      while (bits) {
-        const int j = __ffs(bits) - 1;
-        bits &= bits - 1;
-        const uint32_t s8 = 8u * (uint32_t)(j & 3);
-        c[j >> 2] = (c[j >> 2] & ~(0xFFu << s8)) | ((uint32_t)l << s8);
+      const uint64_t m = fm[l];
+      if (!m) continue;
+      const uint32_t ls = 0x01010101u * (uint32_t)l;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const uint32_t b4 = (uint32_t)(m >> (4 * q)) & 0xFu;
+        const uint32_t bm = ((b4 * 0x00204081u) & 0x01010101u) * 0xFFu;
+        c[q] = (c[q] & ~bm) | (ls & bm);
       }
     }
-    uint8_t *row = depth + (int64_t)orig[w] * k + 16 * g;
-    if (vec) {
-      *(uint4 *)row = make_uint4(c[0], c[1], c[2], c[3]);
+    uint8_t *row = depth + (int64_t)orig[w] * k + 64 * word;
+    if (vec && 64 * word + 64 <= k) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        ((uint4 *)row)[s4] = make_uint4(c[4 * s4], c[4 * s4 + 1], c[4 * s4 + 2], c[4 * s4 + 3]);
     } else {
-      for (int j = 0; j < 16 && 16 * g + j < k; ++j) row[j] = (uint8_t)(c[j >> 2] >> (8 * (j & 3)));
+      for (int j = 0; j < 64 && 64 * word + j < k; ++j) row[j] = (uint8_t)(c[j >> 2] >> (8 * (j & 3)));
     }
   }
 }
@@ -910,17 +911,14 @@ static void launch_depth_flush(const ms_ws &mw, int32_t L, const byo_tiles *t, i
     h.f[i] = i < mw.nhist ? mw.hfront[i] : nullptr;
     h.a[i] = i < mw.nhist ? mw.habits[i] : nullptr;
   }
-  const int G = (k + 15) / 16;
-  int lg = 0;
-  while ((1 << lg) < G) ++lg;
-  const int64_t rows = 256 >> lg;
-  const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + rows - 1) / rows), 65536);
+  const int64_t total = n * (int64_t)W;
+  const unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (total + 255) / 256), 65536);
   ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
   switch (W) {
-    case 1: ms_depth_flush_kernel<1><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
-    case 2: ms_depth_flush_kernel<2><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
-    case 3: ms_depth_flush_kernel<3><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
-    default: ms_depth_flush_kernel<4><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, lg, depth); break;
+    case 1: ms_depth_flush_kernel<1><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, depth); break;
+    case 2: ms_depth_flush_kernel<2><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, depth); break;
+    case 3: ms_depth_flush_kernel<3><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, depth); break;
+    default: ms_depth_flush_kernel<4><<<nb, 256, 0, s>>>(h, L, t->orig, n, k, depth); break;
   }
 }
 
