@@ -33,7 +33,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 PR_SOURCE = os.path.join(ROOT, "paper_2405_11671_amd", "csrc", "pagerank_tile.hip")
-PR_KERNELS = "pr_tile_kernel<12> + pr_tile_apply_kernel<12> (one PageRank step)"
+
+
+def pr_kernels(n):
+    """Names of the tiled PageRank step's kernels: the library takes tiles of
+    2^12 vertices up to n = 2^22, 2^13 up to 2^23 and 2^14 beyond."""
+    s = min(14, max(12, (max(n, 1) - 1).bit_length() - 10))
+    return f"pr_tile_kernel<{s}> + pr_tile_apply_kernel<{s}> (one PageRank step)"
 
 
 def source_tag(path):
@@ -359,7 +365,7 @@ def main():
     # the committed counters were taken on the RMAT-22 workload with the tile layout
     traffic = counter_traffic(source_tag(PR_SOURCE)) if (not args.no_tiles and args.scale == 22) else None
     achieved = pr_bytes / (pr_avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": PR_KERNELS if not args.no_tiles else "pr_chunk_kernel + pr_pull_kernel<0>",
+    roofline = {"bound": "hbm", "kernel": pr_kernels(g.n) if not args.no_tiles else "pr_chunk_kernel + pr_pull_kernel<0>",
                 "achieved": round(achieved, 2),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / (pr_avg_ms * 1e-3) / 1e9, 2),

@@ -87,19 +87,23 @@ typedef struct byo_opts {
                              device-resident loop: one cooperative kernel of 64
                              workgroups, grid barriers between levels (0 = off; default 0) */
   int32_t pr_blocked;     /* PageRank layout: 0 = pull over the CSR (default); 1 = entries
-                             regrouped by destination tile of 2^14 degree-ordered vertices,
-                             exact fixed-point sums in LDS; 12..14 = tiles of 2^value.
-                             The tiled layout is used when n >= 2^16 and m >= 4n (else the
-                             pull); it is built on the host on first use (about 6 bytes per
-                             entry plus 8 per vertex of device memory) and kept with the
-                             graph. */
+                             regrouped by destination tile of degree-ordered vertices, exact
+                             fixed-point sums in LDS, tiles of 2^12 vertices up to n = 2^22,
+                             2^13 up to 2^23, 2^14 beyond; 12..14 = tiles of 2^value. The
+                             tiled layout is used when n >= 2^16 and m >= 4n (else the pull);
+                             it is built on the device on first use (about 8 bytes per entry
+                             plus 24 per vertex of device memory) and kept with the graph,
+                             one layout per tile size. */
   int32_t use_graph;      /* BFS: 1 = device-side level control replayed from a captured
                              hipGraph (threshold rule on the device), 0 = host loop (default) */
-  int32_t tiled;          /* multi-source BFS and connectivity: 1 = every level / round over
-                             the degree-ordered tile layout (the one PageRank's pr_blocked
-                             uses) when n >= 2^16 and m >= 4n; 0 = over the CSR with the
-                             selected variants (default) */
-  int32_t reserved[5];
+  int32_t tiled;          /* multi-source BFS and connectivity: 1 = dense levels / rounds over
+                             the degree-ordered tile layout (the kind PageRank's pr_blocked
+                             uses; multi-source BFS always with tiles of 2^12 vertices) when
+                             n >= 2^16 and m >= 4n; 0 = over the CSR with the selected
+                             variants (default) */
+  int32_t tile_shift;     /* connectivity with tiled = 1: tiles of 2^value vertices (12..14);
+                             0 = chosen from n as for pr_blocked = 1 (default) */
+  int32_t reserved[4];
 } byo_opts;
 
 /* Per-call statistics (optional out-parameter; pass NULL to skip). */

@@ -219,8 +219,8 @@ static void cc_tile_pass(const byo_tiles *t, int32_t *lab, const uint64_t *abits
 // pointer-jumping pass when enabled.
 byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(ws_ensure_traversal(g));
-  BYO_TRY(tiles_ensure(g, g->ws.tiles ? g->ws.tiles->shift : BYO_TILE_SHIFT, s));
-  byo_tiles *t = g->ws.tiles;
+  byo_tiles *t = nullptr;
+  BYO_TRY(tiles_ensure(g, (o.tile_shift >= 12 && o.tile_shift <= 14) ? o.tile_shift : tiles_auto_shift(g), s, &t));
   BYO_TRY(tiles_partial(t, sizeof(int32_t) << t->shift));
   BYO_TRY(tiles_scratch(t));
   byo_workspace &w = g->ws;

@@ -161,7 +161,8 @@ struct byo_workspace {
   int64_t nchunks = -1;
   int32_t pr_dpart_blocks = 0;
   void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
-  byo::byo_tiles *tiles = nullptr;   // degree-ordered destination-tile layout (tiles.hip)
+  // degree-ordered destination-tile layouts, one per tile size 2^12 .. 2^14 (tiles.hip)
+  byo::byo_tiles *tiles[3] = {nullptr, nullptr, nullptr};
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
 };
@@ -203,7 +204,6 @@ void ms_release(byo_workspace &ws);
 // descending degree; entries grouped by tile of 2^shift relabelled
 // destinations, ascending relabelled source inside a tile; tiles cut into
 // chunks of about equal size.
-constexpr int BYO_TILE_SHIFT = 12;
 struct byo_tiles {
   int shift = 0;
   int64_t n = 0, m = 0, mp = 0, nblk = 0, nchunks = 0;
@@ -244,7 +244,13 @@ __device__ __forceinline__ void tile_entry(const uint32_t *__restrict__ ent, con
   src = anchor[g] + (int32_t)(x & 0xffffu);
 }
 bool tiles_wanted(const byo_graph *g);  // n >= 2^16 and m >= 4n
-byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s);
+// The layout with tiles of 2^shift vertices (12 .. 14), built on first use
+// and kept with the graph next to the layouts of other tile sizes.
+byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s, byo_tiles **out);
+// Tile size for passes that may choose: 2^12 up to n = 2^22, 2^13 up to
+// 2^23, 2^14 beyond (larger graphs re-read fewer contribution lines with
+// fewer, larger tiles).
+int tiles_auto_shift(const byo_graph *g);
 byo_status tiles_partial(byo_tiles *t, size_t bytes_per_chunk);
 byo_status tiles_scratch(byo_tiles *t);
 // The layout's relabelled CSR seen as a graph, for the CSR push kernels: same
@@ -254,9 +260,9 @@ byo_graph tiles_view(const byo_graph *g, const byo_tiles *t);
 byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 void tiles_release(byo_workspace &w);
 // tiled PageRank step (pagerank_tile.hip); opt = byo_opts::pr_blocked
-int pr_tile_shift(int32_t opt);
-byo_status pr_tile_step(byo_graph *g, const float *contrib, float damping, float *contrib_next, float *out,
-                        const float *dpart_in, int64_t nparts_in, hipStream_t s);
+int pr_tile_shift(const byo_graph *g, int32_t opt);
+byo_status pr_tile_step(byo_graph *g, byo_tiles *p, const float *contrib, float damping, float *contrib_next,
+                        float *out, const float *dpart_in, int64_t nparts_in, hipStream_t s);
 
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);

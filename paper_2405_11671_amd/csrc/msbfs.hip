@@ -932,8 +932,8 @@ static void launch_depth_flush(const ms_ws &mw, int32_t L, const byo_tiles *t, i
 // (and visit and the touched bits unless a tiled run left them zero).
 static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
                                uint8_t *d_depth, const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
-  BYO_TRY(tiles_ensure(g, MT_SHIFT, s));
-  byo_tiles *t = g->ws.tiles;
+  byo_tiles *t = nullptr;
+  BYO_TRY(tiles_ensure(g, MT_SHIFT, s, &t));
   BYO_TRY(tiles_partial(t, sizeof(uint64_t) * (size_t)W << MT_SHIFT));
   const int64_t n = g->n, words = (n + 63) / 64;
   BYO_TRY(ms_hist_ensure(mw, n, W));

@@ -289,16 +289,16 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     return BYO_OK;
   }
   if (o.pr_blocked != 0 && tiles_wanted(g)) {
-    BYO_TRY(tiles_ensure(g, pr_tile_shift(o.pr_blocked), s));
+    byo_tiles *tl = nullptr;
+    BYO_TRY(tiles_ensure(g, pr_tile_shift(g, o.pr_blocked), s, &tl));
     // the tiled step runs in the layout's relabelled vertex order
-    pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->ws.tiles->rdeg, n, w.words, w.contrib[0], w.dpart);
+    pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(tl->rdeg, n, w.words, w.contrib[0], w.dpart);
     BYO_HIP(hipGetLastError());
     int c = 0;
     for (int32_t t = 0; t < iters; ++t) {
       bool last = t + 1 == iters;
-      const byo_tiles *tl = g->ws.tiles;
-      BYO_TRY(pr_tile_step(g, w.contrib[c], (float)damping, last ? nullptr : w.contrib[1 - c], last ? d_rank : nullptr,
-                           t == 0 ? w.dpart : tl->adpart, t == 0 ? nb : tl->napply, s));
+      BYO_TRY(pr_tile_step(g, tl, w.contrib[c], (float)damping, last ? nullptr : w.contrib[1 - c],
+                           last ? d_rank : nullptr, t == 0 ? w.dpart : tl->adpart, t == 0 ? nb : tl->napply, s));
       c = 1 - c;
     }
     return BYO_OK;

@@ -20,7 +20,7 @@ constexpr int PT_ILP = 16;
 constexpr int PT_APPLY = 256;
 constexpr int PT_AV = 4;
 
-int pr_tile_shift(int32_t opt) { return (opt >= 12 && opt <= 14) ? opt : BYO_TILE_SHIFT; }
+int pr_tile_shift(const byo_graph *g, int32_t opt) { return (opt >= 12 && opt <= 14) ? opt : tiles_auto_shift(g); }
 
 // Contributions are summed as unsigned 64-bit fixed point with 61 fraction
 // bits. Every contribution is p[u]/deg(u) <= 1 and a row's total is
@@ -219,9 +219,8 @@ static void launch_step(const byo_tiles *p, const byo_graph *g, const float *con
 // dangling partials of the previous step (the layout's adpart) or of the
 // initialisation; this step's go to the layout's adpart (napply of them).
 // out (nullable) receives p' in the caller's order.
-byo_status pr_tile_step(byo_graph *g, const float *contrib, float damping, float *contrib_next, float *out,
-                        const float *dpart_in, int64_t nparts_in, hipStream_t s) {
-  byo_tiles *p = g->ws.tiles;
+byo_status pr_tile_step(byo_graph *g, byo_tiles *p, const float *contrib, float damping, float *contrib_next,
+                        float *out, const float *dpart_in, int64_t nparts_in, hipStream_t s) {
   BYO_CHECK(p, BYO_ESTATE, "tile layout not built");
   BYO_TRY(tiles_partial(p, sizeof(unsigned long long) << p->shift));
   BYO_CHECK(p->nchunks > 0 && p->napply > 0, BYO_ESTATE, "tile layout without entries");

@@ -43,9 +43,16 @@ static void tiles_free(byo_tiles *p) {
 }
 
 void tiles_release(byo_workspace &w) {
-  if (!w.tiles) return;
-  tiles_free(w.tiles);
-  w.tiles = nullptr;
+  for (auto &t : w.tiles) {
+    if (t) tiles_free(t);
+    t = nullptr;
+  }
+}
+
+int tiles_auto_shift(const byo_graph *g) {
+  int lg = 0;
+  while (lg < 62 && ((int64_t)1 << lg) < g->n) ++lg;
+  return std::min(14, std::max(12, lg - 10));
 }
 
 // Device construction of the tile layout, all on the caller's stream:
@@ -329,11 +336,14 @@ static byo_status tiles_build(const byo_graph *g, byo_tiles *p, hipStream_t s) {
   return BYO_OK;
 }
 
-byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
+byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s, byo_tiles **out) {
   byo_workspace &w = g->ws;
   BYO_CHECK(shift >= 12 && shift <= 14, BYO_EINVAL, "tile size must be 2^12 .. 2^14");
-  if (w.tiles && w.tiles->shift == shift) return BYO_OK;
-  tiles_release(w);
+  byo_tiles *&slot = w.tiles[shift - 12];
+  if (slot) {
+    *out = slot;
+    return BYO_OK;
+  }
   BYO_CHECK(tiles_wanted(g), BYO_EINVAL, "graph too small or too sparse for the tile layout");
   BYO_CHECK(g->n <= ((int64_t)1 << 31) - 1, BYO_EINVAL, "graph too large for the tile layout");
   byo_tiles *p = new byo_tiles();
@@ -347,7 +357,8 @@ byo_status tiles_ensure(byo_graph *g, int shift, hipStream_t s) {
     tiles_free(p);
     return st;
   }
-  w.tiles = p;
+  slot = p;
+  *out = p;
   return BYO_OK;
 }
 

@@ -103,8 +103,9 @@ def test_msbfs_tiled_falls_back_below_size_cut(p):
 
 
 def test_msbfs_tiled_after_pagerank_layout_change():
-    """PageRank with another tile size rebuilds the shared layout; the next
-    tiled multi-source run rebuilds it back and stays exact."""
+    """PageRank with another tile size builds a second layout next to the
+    multi-source run's 2^12 one; both keep giving exact results, in either
+    order."""
     p = TILED[0]
     g, og = build(p)
     srcs = gen.pick_sources(p, 100, seed=3)

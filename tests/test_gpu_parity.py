@@ -123,16 +123,18 @@ TILED = [gen.rmat_pairs(16, 16, seed=12), gen.er_pairs(70001, 10, seed=5), gen.r
          graphs.hub_over_er()]
 
 
+@pytest.mark.parametrize("shift", [0, 13, 14])
 @pytest.mark.parametrize("shortcut", [1, 0])
 @pytest.mark.parametrize("pi", range(len(TILED)))
-def test_cc_tiled_matches_oracle(pi, shortcut):
+def test_cc_tiled_matches_oracle(pi, shortcut, shift):
     """Connectivity over the tile layout: minimum original ID per component
-    (many components and isolated vertices in the sparse RMAT)."""
+    (many components and isolated vertices in the sparse RMAT), with the tile
+    size chosen from n and at 2^13 and 2^14 (a layout of its own per size)."""
     p = TILED[pi]
     g, og = build(p)
-    lab, st = byo.cc(g, tiled=1, cc_shortcut=shortcut)
+    lab, st = byo.cc(g, tiled=1, cc_shortcut=shortcut, tile_shift=shift)
     want = og.cc()
-    assert np.array_equal(lab.cpu().numpy(), want), (pi, shortcut)
+    assert np.array_equal(lab.cpu().numpy(), want), (pi, shortcut, shift)
     assert st["levels"] >= 1
 
 
