@@ -102,11 +102,13 @@ __global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const uint32_t *__r
 }
 
 // Smallest label offered to w over its tile's chunks; lower lab[w] to it and
-// mark w active. One wavefront owns one word of the next active bitmap.
+// mark w active (a wavefront ORs in its word of the next active bitmap, which
+// the caller cleared), and hook the vertex w's old label named.
 template <int SHIFT>
 __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *__restrict__ partial,
                                                                  const uint32_t *__restrict__ cflag,
                                                                  const int32_t *__restrict__ bfirst,
+                                                                 const int32_t *__restrict__ rlabel,
                                                                  int32_t *__restrict__ lab,
                                                                  uint64_t *__restrict__ abits_next, int64_t n,
                                                                  byo_counters *__restrict__ ctr) {
@@ -135,14 +137,25 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
       }
       for (; c < c1; ++c)
         if (cflag[c]) m = min(m, pl[(int64_t)c << SHIFT]);
-      if (m < lab[w]) {
-        lab[w] = m;
+      const int32_t old = lab[w];
+      if (m < old) {
+        atomicMin(&lab[w], m);
         changed = true;
+        // Hooking: the vertex whose ID w carried as its label is in w's
+        // component too, so it may take m as well; it becomes active when it
+        // drops. Labels only decrease and stay IDs of the component, so the
+        // result (the smallest ID of each component) is unchanged; fewer
+        // rounds reach it.
+        const int32_t h = rlabel[old];
+        // (read first: most labels name a few roots, and once a root holds m
+        // its hooks would only queue on the same address)
+        if (h != w && m < lab[h] && m < atomicMin(&lab[h], m))
+          atomicOr((unsigned long long *)&abits_next[h >> 6], 1ull << (h & 63));
       }
     }
     uint64_t am = __ballot(changed);
-    if (lane_id() == 0 && w < n) {
-      abits_next[w >> 6] = am;
+    if (lane_id() == 0 && w < n && am) {
+      atomicOr((unsigned long long *)&abits_next[w >> 6], (unsigned long long)am);
       count += (unsigned long long)__popcll(am);
     }
   }
@@ -208,8 +221,10 @@ static void cc_tile_pass(const byo_tiles *t, int32_t *lab, const uint64_t *abits
   ktimer_scope kt(BYO_K_CC_PULL, s);
   cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, lab, abits,
                                                                    (int32_t *)t->partial, t->cflag);
+  // the apply ORs its bits in (a hooked vertex may sit in another wavefront's word)
+  (void)fill_u64(abits_next, (n + 63) / 64, 0ull, s);
   cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>((const int32_t *)t->partial, t->cflag, t->bfirst,
-                                                                 lab, abits_next, n, ctr);
+                                                                 t->rlabel, lab, abits_next, n, ctr);
 }
 
 // Rounds in the layout's order, direction-optimising: a push over the
