@@ -418,16 +418,29 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
   constexpr int B = 1 << MT_SHIFT;
   __shared__ uint64_t acc[B * W];
   __shared__ uint64_t need[B / 64 + 1];  // word B / 64 (padding entries) stays 0
-  __shared__ int s_any;
+  __shared__ int s_any, s_need;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
   const int64_t tile = cblk[c];
-  for (int i = t; i < B * W; i += MT_THREADS) acc[i] = 0ull;
-  if (t == 0) s_any = 0;
+  if (t == 0) {
+    s_any = 0;
+    s_need = 0;
+  }
+  __syncthreads();
   if (t <= B / 64) {
     int64_t wd = (tile << (MT_SHIFT - 6)) + t;
-    need[t] = (t < B / 64 && wd < words) ? ~fbits[wd] : 0ull;
+    const uint64_t x = (t < B / 64 && wd < words) ? ~fbits[wd] : 0ull;
+    need[t] = x;
+    if (x) s_need = 1;  // every writer stores the same value
   }
+  __syncthreads();
+  // a tile whose vertices have all seen every source has nothing to gain:
+  // the workgroup leaves without streaming its entries
+  if (!s_need) {
+    if (t == 0) cflag[c] = 0u;
+    return;
+  }
+  for (int i = t; i < B * W; i += MT_THREADS) acc[i] = 0ull;
   __syncthreads();
   const int64_t beg = cbeg[c], end = cbeg[c + 1];
   int mine = 0;
