@@ -103,7 +103,12 @@ typedef struct byo_opts {
                              variants (default) */
   int32_t tile_shift;     /* connectivity with tiled = 1: tiles of 2^value vertices (12..14);
                              0 = chosen from n as for pr_blocked = 1 (default) */
-  int32_t reserved[4];
+  int32_t ms_history;     /* multi-source BFS with tiled = 1: levels whose frontier masks are kept
+                             for building the depth rows in one pass (2..16; later levels write
+                             depths directly); 0 = as many as fit in a quarter of the free device
+                             memory, at most 16 (default). Each kept level costs 8 * W * n bytes
+                             (W = ceil(k / 64)) plus n / 8. */
+  int32_t reserved[3];
 } byo_opts;
 
 /* Per-call statistics (optional out-parameter; pass NULL to skip). */

@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
                 ("t_block", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("cc_shortcut", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
                 ("pr_blocked", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("tiled", ctypes.c_int32), ("tile_shift", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("tiled", ctypes.c_int32), ("tile_shift", ctypes.c_int32), ("ms_history", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class RunStats(ctypes.Structure):

@@ -949,8 +949,10 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
   BYO_TRY(tiles_ensure(g, MT_SHIFT, s, &t));
   BYO_TRY(tiles_partial(t, sizeof(uint64_t) * (size_t)W << MT_SHIFT));
   const int64_t n = g->n, words = (n + 63) / 64;
+  BYO_CHECK(o.ms_history == 0 || (o.ms_history >= 2 && o.ms_history <= MS_HIST), BYO_EINVAL,
+            "ms_history must be 0 or 2 .. 16");
   BYO_TRY(ms_hist_ensure(mw, n, W));
-  const int H = mw.nhist;
+  const int H = o.ms_history ? std::min(o.ms_history, mw.nhist) : mw.nhist;
   auto slot = [H](int l) { return l < H ? l : (H - 2) + ((l - H) & 1); };
   BYO_HIP(hipMemsetAsync(mw.habits[0], 0, sizeof(uint64_t) * (size_t)words, s));
   ms_tile_init_kernel<<<1, 256, 0, s>>>(mw.srcs, t->rlabel, k, W, mw.seen, mw.hfront[0], mw.habits[0], t->rdeg,

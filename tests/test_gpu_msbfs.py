@@ -93,6 +93,32 @@ def test_msbfs_tiled_many_levels(k):
     assert np.array_equal(want.reshape(g.n, k)[:, j], cheb)
 
 
+@pytest.mark.parametrize("hist", [2, 3, 5])
+def test_msbfs_tiled_history_cap(hist):
+    """Fewer frontier-history slots than levels: the depth rows are built at the
+    level that would need one slot more, and the later levels write their
+    depths directly, at the smallest caps too."""
+    rng = np.random.default_rng(40 + hist)
+    for p, ks in ((TILED[0], (64, 150, 256)), (graphs.king_lattice(), (16,))):
+        g, og = build(p)
+        for k in ks:
+            if p.name.startswith("king"):  # near the middle: every distance stays below 255
+                srcs = rng.integers(90, 110, k) * 400 + rng.integers(190, 210, k)
+            else:
+                srcs = rng.integers(0, og.n, k)
+            D, st = byo.msbfs(g, srcs, tiled=1, ms_history=hist)
+            assert st["levels"] > hist
+            assert np.array_equal(D.cpu().numpy(), og.msbfs(srcs)), (p.name, k, hist)
+
+
+def test_msbfs_tiled_history_cap_range():
+    g, _ = build(TILED[0])
+    for bad in (1, 17, -1):
+        with pytest.raises(byo.ByoError) as e:
+            byo.msbfs(g, [0, 1], tiled=1, ms_history=bad)
+        assert e.value.status == -1
+
+
 @pytest.mark.parametrize("p", SUITE, ids=[p.name for p in SUITE])
 def test_msbfs_tiled_falls_back_below_size_cut(p):
     """tiled = 1 on graphs the layout does not take runs over the CSR."""
