@@ -215,7 +215,10 @@ byo_status byo_edge_map(byo_graph *g, byo_vset *U, byo_edge_fn F, const void *F_
 byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
                    void *stream, byo_run_stats *stats);
 /* Connectivity by min-label propagation over edgeMap: label[v] = smallest
- * vertex ID in v's component. */
+ * vertex ID in v's component. With tiled = 1, dense rounds run over the tile
+ * layout, and a vertex whose label drops also lowers the vertex its old label
+ * named (hooking); cc_shortcut adds pointer jumping. Any path gives the same
+ * labels. */
 byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *stream, byo_run_stats *stats);
 /* PageRank, FP32, `iters` steps from 1/n: p'[v] = (1-d)/n + d * (sum over
  * u in N(v) of p[u]/deg(u) + D/n), D = mass on degree-0 vertices. */
@@ -223,7 +226,9 @@ byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, float *d_ra
                         void *stream, byo_run_stats *stats);
 /* Multi-source BFS from k <= 256 sources, 64 sources per u64 word.
  * d_depth is vertex-major uint8: depth[v * k + j] = hop distance from
- * h_srcs[j] (255 = unreached). BYO_ELIMIT if a distance reaches 255. */
+ * h_srcs[j] (255 = unreached). BYO_ELIMIT if a distance reaches 255; the
+ * contents of d_depth are then unspecified. With tiled = 1 the rows are built
+ * from kept per-level frontier masks (see ms_history). */
 byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, uint8_t *d_depth, const byo_opts *opts,
                      void *stream, byo_run_stats *stats);
 
