@@ -63,6 +63,10 @@ typedef enum {
 } byo_kernel_family;
 
 byo_status byo_ktimer_enable(int32_t on);
+/* Families that record while timing is on: bit f for family f (default all).
+ * Each timed launch records two events on its stream, which costs host time
+ * where the host waits on the device between launches (level loops). */
+byo_status byo_ktimer_select(uint32_t mask);
 byo_status byo_ktimer_reset(void);
 /* Launch count and summed device milliseconds of one family (waits for its events). */
 byo_status byo_ktimer_read(int32_t family, int64_t *launches, double *total_ms);

@@ -280,6 +280,17 @@ def ktimer_enable(on: bool = True):
     _lib.check(_lib.load().byo_ktimer_enable(1 if on else 0))
 
 
+def ktimer_select(families=None):
+    """Record only these families (names or ids) while timing is on; None = all."""
+    if families is None:
+        mask = 0xFFFFFFFF
+    else:
+        mask = 0
+        for f in families:
+            mask |= 1 << (_lib.K_FAMILIES.index(f) if isinstance(f, str) else int(f))
+    _lib.check(_lib.load().byo_ktimer_select(ctypes.c_uint32(mask)))
+
+
 def ktimer_reset():
     _lib.check(_lib.load().byo_ktimer_reset())
 

@@ -28,6 +28,7 @@ SIGNATURES = {
     "byo_trace_read": (st, [ctypes.POINTER(LevelRecord), i64, i64p]),
     "byo_trace_pending": (st, [i64p]),
     "byo_ktimer_enable": (st, [i32]),
+    "byo_ktimer_select": (st, [ctypes.c_uint32]),
     "byo_ktimer_reset": (st, []),
     "byo_ktimer_read": (st, [i32, i64p, ctypes.POINTER(dbl)]),
 

@@ -11,6 +11,7 @@ namespace {
 std::mutex g_mu;
 bool g_trace_on = false;
 bool g_ktimer_on = false;
+uint32_t g_ktimer_mask = 0xFFFFFFFFu;  // families that record while timing is on
 std::vector<byo_level_record> g_records;
 std::vector<hipEvent_t> g_pool;
 struct pending_t {
@@ -49,7 +50,7 @@ void trace_push(const byo_level_record &r) {
 }
 
 ktimer_scope::ktimer_scope(int fam, hipStream_t st) : family(fam), s(st) {
-  if (!g_ktimer_on) return;
+  if (!g_ktimer_on || !((g_ktimer_mask >> fam) & 1u)) return;
   a = event_get();
   if (a) (void)hipEventRecord(a, s);
 }
@@ -109,6 +110,11 @@ byo_status byo_trace_read(byo_level_record *out, int64_t cap, int64_t *count) {
 
 byo_status byo_ktimer_enable(int32_t on) {
   g_ktimer_on = on != 0;
+  return BYO_OK;
+}
+
+byo_status byo_ktimer_select(uint32_t mask) {
+  g_ktimer_mask = mask;
   return BYO_OK;
 }
 
