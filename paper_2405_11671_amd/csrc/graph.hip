@@ -25,7 +25,22 @@ byo_status hip_fail(hipError_t e, const char *what, const char *file, int line) 
   return (e == hipErrorOutOfMemory) ? BYO_ENOMEM : BYO_EHIP;
 }
 
+// Small reads (level counters, counts) go through a pinned staging buffer of
+// the calling host thread, allocated on its first read and kept for the
+// thread's life (64 KiB; not freed at exit, when the runtime may be gone): a
+// copy into pageable memory would be staged by the runtime, which costs time
+// on every level of a level loop.
+constexpr size_t SYNC_STAGE_BYTES = 1 << 16;
+static thread_local void *g_stage = nullptr;
+
 byo_status sync_read(hipStream_t s, const void *d_src, void *h_dst, size_t bytes) {
+  if (bytes <= SYNC_STAGE_BYTES) {
+    if (!g_stage) BYO_HIP(hipHostMalloc(&g_stage, SYNC_STAGE_BYTES, hipHostMallocDefault));
+    BYO_HIP(hipMemcpyAsync(g_stage, d_src, bytes, hipMemcpyDeviceToHost, s));
+    BYO_HIP(hipStreamSynchronize(s));
+    std::memcpy(h_dst, g_stage, bytes);
+    return BYO_OK;
+  }
   BYO_HIP(hipMemcpyAsync(h_dst, d_src, bytes, hipMemcpyDeviceToHost, s));
   BYO_HIP(hipStreamSynchronize(s));
   return BYO_OK;
