@@ -16,6 +16,8 @@ next to the batched rate.
 
 Prints ONE JSON line. `--probe pr` instead runs a few PageRank steps and a
 plain 512 MiB device copy, for hardware-counter runs (bytes per dispatch).
+`--ablation` instead replays the container-API configurations of the paper's
+Table api-components-avg (one JSON line of per-case times and slowdowns).
 """
 from __future__ import annotations
 
@@ -189,6 +191,72 @@ def batch_workload(byo, gen, count=64):
     return res
 
 
+PAPER_RMAT_ABCD = (0.5, 0.1, 0.1, 0.3)   # the paper's rMAT generator setting (Section 5)
+
+
+def api_ablation(byo, gen, args):
+    """Container-API ablation (Section 4.2, Table api-components-avg): the same
+    CSR container and host-driven level loop, with optional container functions
+    left out. BFS (total over the sources), connectivity and PageRank
+    (args.pr_iters steps) per graph and configuration, median of 3 timed runs
+    after one untimed run; slowdown = time / time with the full API. Summaries
+    per configuration over every (graph, algorithm) case: mean, 95th
+    percentile and maximum, as the table reports them."""
+    import torch
+    graphs = [
+        (f"rmat-{args.scale} graph500", lambda: gen.rmat_pairs(args.scale, 16, gen.GRAPH500_ABCD, seed=1)),
+        (f"rmat-{args.scale - 1} paper abcd", lambda: gen.rmat_pairs(args.scale - 1, 16, PAPER_RMAT_ABCD, seed=3)),
+        (f"er n=2^{args.scale - 1} d=50", lambda: gen.er_pairs(1 << (args.scale - 1), 50, seed=4)),
+        ("grid 2048x2048 del0.1", lambda: gen.grid_pairs(2048, 2048, 0.1, seed=1)),
+    ]
+    configs = sorted(byo.API_CONFIGS.items(), key=lambda kv: kv[1])
+    cases = []
+    for gname, make in graphs:
+        p = make()
+        srcs = [int(s) for s in gen.pick_sources(p, 2, seed=5)]
+        off, nbr = byo.csr_from_pairs(p.n, p.src, p.dst)
+        del p
+        g = byo.Graph.from_csr(off, nbr)
+        n, m = g.n, g.m
+        del off, nbr
+        depth = torch.empty(n, dtype=torch.int32, device="cuda")
+        parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        label = torch.empty(n, dtype=torch.int32, device="cuda")
+        rank = torch.empty(n, dtype=torch.float32, device="cuda")
+        algos = {
+            "bfs": lambda o: [byo.bfs(g, s, opts=o, depth=depth, parent=parent) for s in srcs],
+            "cc": lambda o: byo.cc(g, opts=o, label=label),
+            "pagerank": lambda o: byo.pagerank(g, 0.85, args.pr_iters, opts=o, rank=rank),
+        }
+        for cname, omit in configs:
+            o = byo.default_opts(api_omit=omit)
+            for aname, fn in algos.items():
+                fn(o)
+                ts = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    fn(o)
+                    torch.cuda.synchronize()
+                    ts.append((time.perf_counter() - t) * 1e3)
+                cases.append({"graph": gname, "n": n, "m": m, "algo": aname, "config": cname, "api_omit": omit,
+                              "ms": round(float(np.median(ts)), 4)})
+            log(f"[ablation] {gname} {cname}: " + " ".join(f"{c['algo']}={c['ms']:.2f}ms" for c in cases[-3:]))
+        del g, depth, parent, label, rank
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    full = {(c["graph"], c["algo"]): c["ms"] for c in cases if c["api_omit"] == 0}
+    for c in cases:
+        c["slowdown"] = round(c["ms"] / full[(c["graph"], c["algo"])], 4)
+    summary = {}
+    for cname, omit in configs:
+        sl = np.array([c["slowdown"] for c in cases if c["api_omit"] == omit])
+        summary[cname] = {"api_omit": omit, "mean": round(float(sl.mean()), 3),
+                          "p95": round(float(np.percentile(sl, 95)), 3), "max": round(float(sl.max()), 3)}
+    print(json.dumps({"ablation": "container API (Table api-components-avg)", "unit": "slowdown over full API",
+                      "summary": summary, "cases": cases}), flush=True)
+
+
 def probe_pr(g, n, iters):
     import torch
     import paper_2405_11671_amd as byo
@@ -220,6 +288,8 @@ def parse():
     ap.add_argument("--cpu-sample-pr-iters", type=int, default=6)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--probe", choices=["pr"], default=None)
+    ap.add_argument("--ablation", action="store_true",
+                    help="replay the container-API configurations instead of the benchmark step")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--grid-side", type=int, default=4096)
@@ -241,6 +311,10 @@ def main():
     import paper_2405_11671_amd as byo
     from paper_2405_11671_amd import gen
 
+    if args.ablation:
+        torch.cuda.init()
+        api_ablation(byo, gen, args)
+        return
     t0 = time.time()
     pairs = gen.rmat_pairs(args.scale, 16, gen.GRAPH500_ABCD, seed=1, permute=True)
     srcs = gen.pick_sources(pairs, args.sources, seed=2)

@@ -103,13 +103,48 @@ typedef struct byo_opts {
                              variants (default) */
   int32_t tile_shift;     /* connectivity with tiled = 1: tiles of 2^value vertices (12..14);
                              0 = chosen from n as for pr_blocked = 1 (default) */
+  int32_t api_omit;       /* container-API ablation: BYO_API_NO_* bits of container functions
+                             BFS, connectivity and PageRank may not use; 0 = the whole API
+                             (default) */
   int32_t ms_history;     /* multi-source BFS with tiled = 1: levels whose frontier masks are kept
                              for building the depth rows in one pass (2..16; later levels write
                              depths directly); 0 = as many as fit in a quarter of the free device
                              memory, at most 16 (default). Each kept level costs 8 * W * n bytes
                              (W = ceil(k / 64)) plus n / 8. */
-  int32_t reserved[3];
+  int32_t reserved[2];
 } byo_opts;
+
+/* Container functions a traversal can be denied (Section 4.2 defines the
+ * GraphContainer API: map_neighbors and num_vertices required; num_edges,
+ * degree, early-exit and parallel maps optional; Table api-components-avg
+ * measures configurations that leave them out). Results never change; only
+ * the work does:
+ *  - NO_DEGREE: every degree the framework needs (frontier degree sums for
+ *    the sparse/dense cutoff, degree bucketing, edge-balanced offsets,
+ *    PageRank's division) is counted by mapping over the vertex's
+ *    neighbours: once per frontier vertex per level, and for every vertex at
+ *    every PageRank step;
+ *  - NO_NUM_EDGES: m for the cutoff is recomputed at every level, as the
+ *    sum of the degrees (by mapping, without degree);
+ *  - NO_EARLY_EXIT: a BFS pull lane scans its whole list (the first frontier
+ *    neighbour found is still the parent); lists handed to the wavefront's
+ *    cooperative scan keep the parallel early exit unless that is left out
+ *    too;
+ *  - NO_PAR_MAP: a vertex's neighbours are mapped by one thread: push by a
+ *    thread per frontier vertex, connectivity's pull and PageRank's rows by
+ *    one lane each (no wavefront-assisted rows, no chunks);
+ *  - NO_PAR_EARLY_EXIT: no wavefront-cooperative early-exit BFS pull.
+ * With any bit set, BFS and connectivity run the host-driven CSR level loop
+ * (no device-resident small-frontier loop, no hipGraph capture, no tiled
+ * connectivity) and PageRank the CSR pull (no tiled step). The multi-source
+ * BFS ignores it. */
+enum {
+  BYO_API_NO_DEGREE = 1,
+  BYO_API_NO_NUM_EDGES = 2,
+  BYO_API_NO_EARLY_EXIT = 4,
+  BYO_API_NO_PAR_MAP = 8,
+  BYO_API_NO_PAR_EARLY_EXIT = 16
+};
 
 /* Per-call statistics (optional out-parameter; pass NULL to skip). */
 typedef struct byo_run_stats {

@@ -11,12 +11,13 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (ByoError, F_BFS, F_CC_MIN, F_PR_ACC, NUM_VARIANTS, SEL_FIXED, SEL_HEURISTIC, SEL_MLP,
+from ._lib import (API_CONFIGS, API_NO_DEGREE, API_NO_EARLY_EXIT, API_NO_NUM_EDGES, API_NO_PAR_EARLY_EXIT,
+                   API_NO_PAR_MAP, ByoError, F_BFS, F_CC_MIN, F_PR_ACC, NUM_VARIANTS, SEL_FIXED, SEL_HEURISTIC, SEL_MLP,
                    V_PULL_THREAD, V_PULL_WAVE, V_PUSH_BUCKET, V_PUSH_EDGE, V_PUSH_THREAD, V_PUSH_WAVE, VARIANTS,
                    default_opts)
 
 __all__ = ["Graph", "VSet", "bfs", "cc", "pagerank", "edge_map", "csr_from_pairs", "default_opts", "ByoError",
-           "VARIANTS", "NUM_VARIANTS"]
+           "VARIANTS", "NUM_VARIANTS", "API_CONFIGS"]
 
 
 def _torch():

@@ -16,6 +16,20 @@ NUM_VARIANTS = 6
 VARIANTS = ("push_thread", "push_wave", "push_bucket", "push_edge", "pull_thread", "pull_wave")
 V_PUSH_THREAD, V_PUSH_WAVE, V_PUSH_BUCKET, V_PUSH_EDGE, V_PULL_THREAD, V_PULL_WAVE = range(6)
 SEL_HEURISTIC, SEL_MLP, SEL_FIXED = 0, 1, 2
+# optional graph-container functions a run may leave out (byo_opts.api_omit)
+API_NO_DEGREE, API_NO_NUM_EDGES, API_NO_EARLY_EXIT, API_NO_PAR_MAP, API_NO_PAR_EARLY_EXIT = 1, 2, 4, 8, 16
+# the container-API configurations of Table api-components-avg, as api_omit
+API_CONFIGS = {
+    "min": 31,                       # map_neighbors and num_vertices only
+    "min+degree": 30,
+    "min_efficient": 28,             # min + degree + num_edges
+    "full-num_edges": 2,
+    "full-degree": 1,
+    "no_early_exit": 20,             # both early-exit maps left out
+    "no_parallel_map": 24,           # both parallel maps left out
+    "full-parallel_early_exit": 16,
+    "full": 0,
+}
 F_BFS, F_CC_MIN, F_PR_ACC = 0, 1, 2
 HOST_INPUT, DEVICE_COPY, DEVICE_BORROW, VALIDATE = 0x1, 0x2, 0x4, 0x8
 
@@ -34,8 +48,8 @@ class Opts(ctypes.Structure):
                 ("t_block", ctypes.c_int32), ("max_levels", ctypes.c_int32),
                 ("cc_shortcut", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
                 ("pr_blocked", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("tiled", ctypes.c_int32), ("tile_shift", ctypes.c_int32), ("ms_history", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("tiled", ctypes.c_int32), ("tile_shift", ctypes.c_int32), ("api_omit", ctypes.c_int32),
+                ("ms_history", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class RunStats(ctypes.Structure):

@@ -32,6 +32,7 @@ struct LevelArgs {
   byo_counters *ctr;
   byo_counters *ctr_clear;
   int32_t t_wave, t_block;
+  int32_t no_early_exit;                // pulls scan whole lists (container without early-exit maps)
 };
 
 // ---------------------------------------------------------------- functors
@@ -79,7 +80,8 @@ constexpr int PULL_ILP = 8;
 
 // First u in nbr[beg, lim) (ascending) whose bit is set in `bits`, else -1.
 __device__ __forceinline__ int32_t first_member(const int32_t *__restrict__ nbr, const uint64_t *__restrict__ bits,
-                                                int64_t beg, int64_t lim) {
+                                                int64_t beg, int64_t lim, bool scan_all = false) {
+  int32_t first = -1;
   for (int64_t e = beg; e < lim; e += PULL_ILP) {
     int32_t u[PULL_ILP];
     uint64_t w[PULL_ILP];
@@ -89,9 +91,10 @@ __device__ __forceinline__ int32_t first_member(const int32_t *__restrict__ nbr,
     for (int j = 0; j < PULL_ILP; ++j) w[j] = u[j] >= 0 ? bits[u[j] >> 6] : 0ull;
 #pragma unroll
     for (int j = 0; j < PULL_ILP; ++j)
-      if ((w[j] >> (u[j] & 63)) & 1ull) return u[j];
+      if (first < 0 && ((w[j] >> (u[j] & 63)) & 1ull)) first = u[j];
+    if (first >= 0 && !scan_all) return first;  // early exit
   }
-  return -1;
+  return first;
 }
 
 // min(best, label[u] for u in nbr[beg, lim) with bit u set in `bits`).
@@ -375,7 +378,8 @@ __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
 // ---------------------------------------------------------------- pull kernels (BFS)
 
 // One wavefront per 64-vertex bitmap word; lane = bit. Only unvisited
-// vertices scan their lists, and stop at the first neighbour in U. The
+// vertices scan their lists, and stop at the first neighbour in U (unless
+// no_early_exit, for the lists the lane scans by itself). The
 // wavefront owns its word of `visited` and the output bitmap, so no atomics.
 template <bool WAVE_ASSIST>
 __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f) {
@@ -396,8 +400,12 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
     if (cand) {
       beg = a.off[v];
       end = a.off[v + 1];
-      int64_t lim = WAVE_ASSIST ? (end - beg > a.t_wave ? beg + a.t_wave : end) : end;
-      par = first_member(a.nbr, a.in_bits, beg, lim);
+      // a list longer than t_wave goes to the wavefront's cooperative
+      // early-exit scan; the others use the serial scan, which reads the
+      // whole list when the container has no early-exit map
+      const bool coop = WAVE_ASSIST && end - beg > a.t_wave;
+      int64_t lim = coop ? beg + a.t_wave : end;
+      par = first_member(a.nbr, a.in_bits, beg, lim, a.no_early_exit != 0 && !coop);
       found = par >= 0;
     }
     if (WAVE_ASSIST) {
@@ -623,6 +631,7 @@ static LevelArgs make_args(const byo_graph *g, const level_io &io, const byo_opt
   a.t_wave = o.t_wave > 0 ? o.t_wave : 32;
   a.t_block = o.t_block > 0 ? o.t_block : 4096;
   if (a.t_block < a.t_wave) a.t_block = a.t_wave;
+  a.no_early_exit = (o.api_omit & BYO_API_NO_EARLY_EXIT) ? 1 : 0;
   return a;
 }
 

@@ -149,6 +149,10 @@ struct byo_workspace {
   byo_counters *ctr = nullptr;       // [BYO_COUNTER_SLOTS]
   byo_counters *h_ctr = nullptr;     // pinned host mirror
   int32_t *misc = nullptr;           // small device scratch (flags)
+  int32_t *api_deg = nullptr;        // [n] degrees counted by mapping (container-API ablation, api.hip)
+  int32_t *api_heavy = nullptr;      // [m / 4096 + 1] lists counted in chunks
+  int64_t *api_pre = nullptr;        // [m / 4096 + 1] chunks before each of those lists
+  unsigned long long *api_aux = nullptr;  // [4] degree sum, chunked lists, chunks
   // PageRank
   float *contrib[2] = {nullptr, nullptr};
   float *dpart = nullptr;            // dangling partial sums
@@ -263,6 +267,23 @@ void tiles_release(byo_workspace &w);
 int pr_tile_shift(const byo_graph *g, int32_t opt);
 byo_status pr_tile_step(byo_graph *g, byo_tiles *p, const float *contrib, float damping, float *contrib_next,
                         float *out, const float *dpart_in, int64_t nparts_in, hipStream_t s);
+
+// container-API ablation (api.hip): degree / num_edges obtained without the
+// container's degree() / num_edges(), and the variants the parallel-map
+// capabilities allow
+byo_status api_degree_buffer(byo_graph *g, hipStream_t s, int32_t **out);
+// Degrees of the frontier (ids[0..k), or the set bits of bits when ids is
+// null) by mapping, into the degree buffer; their sum in *degsum. The maps
+// are parallel unless omit has BYO_API_NO_PAR_MAP.
+byo_status api_frontier_degrees(byo_graph *g, uint32_t omit, const int32_t *ids, const uint64_t *bits, int64_t k,
+                                hipStream_t s, int64_t *degsum);
+// m: g->m, or without num_edges() the sum of deg (of mapped degrees without
+// degree())
+byo_status api_num_edges(byo_graph *g, uint32_t omit, const int32_t *deg, hipStream_t s, int64_t *m);
+// every vertex's degree by mapping, into the degree buffer (no host wait)
+byo_status api_map_degrees(byo_graph *g, uint32_t omit, hipStream_t s, int32_t **mdeg);
+// the variant the container's functions allow in place of v (BFS pulls exit early)
+int api_variant(uint32_t omit, int v, bool early_exit_pull);
 
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);

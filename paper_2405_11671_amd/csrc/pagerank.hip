@@ -7,7 +7,8 @@
 // edge, and writes p only after the last step.
 //
 // Summation order is fixed (no float atomics), so results are deterministic:
-//  - rows with degree <= t_wave: one lane, ascending;
+//  - rows with degree <= t_wave: one lane, ascending (FP64 accumulation above
+//    PR_LANE_F32 terms);
 //  - t_wave < degree <= HEAVY: the wavefront, lane-strided partial sums and a
 //    butterfly reduction;
 //  - degree > HEAVY: HEAVY-edge chunks reduced by one workgroup each in a
@@ -23,6 +24,7 @@ namespace byo {
 constexpr int PR_BLOCK = 256;
 constexpr int64_t PR_HEAVY = 4096;   // chunk length and heavy-row threshold
 constexpr int PR_ILP = 8;
+constexpr int64_t PR_LANE_F32 = 256;  // longest row one lane sums in FP32
 
 static int64_t pr_blocks(int64_t words) { return std::max<int64_t>(1, (words + 3) / 4); }
 
@@ -99,6 +101,7 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_chunk_kernel(const int32_t *__res
 }
 
 // MODE 0: one PageRank step. MODE 1: plain accumulation acc[v] = sum contrib[u].
+// deg, when given, divides in place of the row length (a mapped degree).
 template <int MODE>
 __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__restrict__ off, const int32_t *__restrict__ nbr,
                                                            const int32_t *__restrict__ deg, int64_t n, int64_t words,
@@ -120,7 +123,7 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__rest
     beg = off[v];
     end = off[v + 1];
     d = (int32_t)(end - beg);
-    if (d <= t_wave) {
+    if (d <= t_wave && d <= PR_LANE_F32) {
       // ascending order, PR_ILP independent gathers per step
       for (int64_t e = beg; e < end; e += PR_ILP) {
         float c[PR_ILP];
@@ -129,6 +132,19 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__rest
 #pragma unroll
         for (int j = 0; j < PR_ILP; ++j) s += c[j];
       }
+    } else if (d <= t_wave) {
+      // a long row summed by one lane (t_wave raised, or no parallel map):
+      // an FP32 running sum of 10^4..10^5 terms drifts by up to d ulps, so
+      // this one accumulates in FP64
+      double sd = 0.0;
+      for (int64_t e = beg; e < end; e += PR_ILP) {
+        float c[PR_ILP];
+#pragma unroll
+        for (int j = 0; j < PR_ILP; ++j) c[j] = (e + j < end) ? contrib[nbr[e + j]] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < PR_ILP; ++j) sd += (double)c[j];
+      }
+      s = (float)sd;
     } else if (d > PR_HEAVY) {
       int32_t c0 = row_chunk0[v];
       int32_t nc = (int32_t)((d + PR_HEAVY - 1) / PR_HEAVY);
@@ -159,6 +175,7 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__rest
   float r = base[0] + damping * s;
   float dang = 0.0f;
   if (valid) {
+    if (deg) d = deg[v];  // a degree the container reports by mapping
     if (contrib_next) contrib_next[v] = d > 0 ? r / (float)d : 0.0f;
     if (d == 0) dang = r;
     if (out) out[v] = r;
@@ -250,7 +267,7 @@ byo_status pr_accumulate(byo_graph *g, const float *contrib, float *acc, hipStre
                                                              w.chunk_sum, w.dpart, 0, 0.0, g->n, w.base, 0);
   }
   pr_pull_kernel<1><<<(unsigned)pr_blocks(w.words), PR_BLOCK, 0, s>>>(
-      g->off, g->nbr, g->deg, g->n, w.words, contrib, w.row_chunk0, w.chunk_sum, w.base, 1.0f, nullptr, w.dpart,
+      g->off, g->nbr, nullptr, g->n, w.words, contrib, w.row_chunk0, w.chunk_sum, w.base, 1.0f, nullptr, w.dpart,
       acc, 32);
   BYO_HIP(hipGetLastError());
   return BYO_OK;
@@ -280,7 +297,15 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
   byo_workspace &w = g->ws;
   int64_t nb = pr_blocks(w.words);
   int32_t tw = o.t_wave > 0 ? o.t_wave : 32;
-  pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->deg, n, w.words, w.contrib[0], w.dpart);
+  // Container-API ablation (Table api-components-avg): without degree() every
+  // step maps each vertex's list to count it; without a parallel map every
+  // list is summed by one lane.
+  const uint32_t omit = (uint32_t)o.api_omit;
+  const bool par_map = !(omit & BYO_API_NO_PAR_MAP);
+  int32_t *mdeg = nullptr;
+  if (omit & BYO_API_NO_DEGREE) BYO_TRY(api_map_degrees(g, omit, s, &mdeg));
+  if (!par_map) tw = INT32_MAX;
+  pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(mdeg ? mdeg : g->deg, n, w.words, w.contrib[0], w.dpart);
   BYO_HIP(hipGetLastError());
   if (iters == 0) {
     // a zero-step run returns the initial vector p = 1/n
@@ -288,7 +313,7 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     BYO_HIP(hipGetLastError());
     return BYO_OK;
   }
-  if (o.pr_blocked != 0 && tiles_wanted(g)) {
+  if (o.pr_blocked != 0 && omit == 0 && tiles_wanted(g)) {
     byo_tiles *tl = nullptr;
     BYO_TRY(tiles_ensure(g, pr_tile_shift(g, o.pr_blocked), s, &tl));
     // the tiled step runs in the layout's relabelled vertex order
@@ -306,14 +331,17 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
   int cur = 0;
   for (int32_t t = 0; t < iters; ++t) {
     bool last = t + 1 == iters;
+    // the degree of every vertex, mapped again at each step
+    if (mdeg && t > 0) BYO_TRY(api_map_degrees(g, omit, s, &mdeg));
     {
+      // without a parallel map only the step constant is computed here
+      const int64_t nch = par_map ? w.nchunks : 0;
       ktimer_scope kc(BYO_K_PR_CHUNK, s);
-      pr_chunk_kernel<<<(unsigned)std::max<int64_t>(w.nchunks, 1), PR_BLOCK, 0, s>>>(
-        g->nbr, w.contrib[cur], w.chunk_beg, w.chunk_row, w.nchunks, w.chunk_sum, w.dpart, nb, damping, n, w.base,
-        1);
+      pr_chunk_kernel<<<(unsigned)std::max<int64_t>(nch, 1), PR_BLOCK, 0, s>>>(
+        g->nbr, w.contrib[cur], w.chunk_beg, w.chunk_row, nch, w.chunk_sum, w.dpart, nb, damping, n, w.base, 1);
     }
     ktimer_scope kp(BYO_K_PR_PULL, s);
-    pr_pull_kernel<0><<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->off, g->nbr, g->deg, n, w.words, w.contrib[cur],
+    pr_pull_kernel<0><<<(unsigned)nb, PR_BLOCK, 0, s>>>(g->off, g->nbr, mdeg, n, w.words, w.contrib[cur],
                                                         w.row_chunk0, w.chunk_sum, w.base, (float)damping,
                                                         last ? nullptr : w.contrib[1 - cur], w.dpart,
                                                         last ? d_rank : nullptr, tw);

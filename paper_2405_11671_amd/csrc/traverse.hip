@@ -186,6 +186,42 @@ static byo_status make_dense(byo_graph *g, frontier &fr, hipStream_t s) {
   return BYO_OK;
 }
 
+// A container that leaves out optional functions of the graph API (Section
+// 4.2; the configurations of Table api-components-avg). Without degree() the
+// run sees only degrees it has mapped: the graph's degree array is swapped,
+// for the run, for the buffer that the mapped degrees of each frontier go to,
+// and the frontier's degree sum comes from that map. Without num_edges() m is
+// summed over the vertices whenever a level needs it.
+struct api_scope {
+  byo_graph *g;
+  uint32_t omit;
+  int32_t *saved = nullptr;
+  api_scope(byo_graph *gr, int32_t om) : g(gr), omit((uint32_t)om) {}
+  api_scope(const api_scope &) = delete;
+  api_scope &operator=(const api_scope &) = delete;
+  byo_status begin(hipStream_t s) {
+    if (!(omit & BYO_API_NO_DEGREE)) return BYO_OK;
+    int32_t *mdeg = nullptr;
+    BYO_TRY(api_degree_buffer(g, s, &mdeg));
+    saved = g->deg;
+    g->deg = mdeg;
+    return BYO_OK;
+  }
+  ~api_scope() {
+    if (saved) g->deg = saved;
+  }
+  // at a level's start: the frontier's degree sum and m as the container
+  // provides them
+  byo_status level(frontier &fr, hipStream_t s, int64_t *m) {
+    if (omit & BYO_API_NO_DEGREE) {
+      byo_workspace &w = g->ws;
+      BYO_TRY(api_frontier_degrees(g, omit, fr.sparse ? w.ids[fr.cur] : nullptr,
+                                   fr.sparse ? nullptr : w.bits[fr.cur], fr.k, s, &fr.degsum));
+    }
+    return api_num_edges(g, omit, g->deg, s, m);
+  }
+};
+
 }  // namespace byo
 
 using namespace byo;
@@ -215,6 +251,8 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   byo_workspace &w = g->ws;
   int64_t n = g->n;
   int64_t ns = (int64_t)srcs.size();
+  api_scope api(g, o.api_omit);
+  BYO_TRY(api.begin(s));
   BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
   BYO_TRY(fill_i32(d_parent, n, -1, s));
   BYO_TRY(fill_i32(d_depth, n, -1, s));
@@ -237,7 +275,9 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   fr.sparse = true;
   fr.k = ns;
   fr.degsum = dsum;
-  int64_t reached = ns, edges = dsum;
+  // without degree() each frontier's degree sum is mapped at its level
+  const bool mapped_deg = (o.api_omit & BYO_API_NO_DEGREE) != 0;
+  int64_t reached = ns, edges = mapped_deg ? 0 : dsum;
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   bfs_state bs{d_parent, d_depth, w.visited, 0};
   int32_t level = 0;
@@ -248,8 +288,8 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     }
     const int64_t dl_edges = std::min<int64_t>(std::max<int64_t>(16 * (int64_t)o.small_frontier, 65536),
                                                BYO_DLOOP_QCAP);
-    if (o.small_frontier > 0 && fr.k <= o.small_frontier && fr.k <= BYO_DLOOP_QCAP && fr.degsum <= dl_edges &&
-        bfs_small_loop_usable(g)) {
+    if (o.small_frontier > 0 && o.api_omit == 0 && fr.k <= o.small_frontier && fr.k <= BYO_DLOOP_QCAP &&
+        fr.degsum <= dl_edges && bfs_small_loop_usable(g)) {
       // run levels on the device while the frontier stays small
       BYO_TRY(make_sparse(g, fr, s));
       small_loop_out r;
@@ -275,8 +315,15 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
       }
       continue;
     }
+    int64_t m_seen = g->m;
+    if (o.api_omit) {
+      BYO_TRY(api.level(fr, s, &m_seen));
+      if (mapped_deg) edges += fr.degsum;
+    }
     level_features f = features(g, fr.k, fr.degsum, n - reached, level, fr.dense && !fr.sparse);
+    f.m = m_seen;
     int v = pick(o, f, use_mlp);
+    if (o.api_omit) v = api_variant((uint32_t)o.api_omit, v, true);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -303,7 +350,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     ++level;
     if (c.count == 0) break;
     reached += (int64_t)c.count;
-    edges += (int64_t)c.degsum;
+    if (!mapped_deg) edges += (int64_t)c.degsum;
     fr.cur = nxt;
     fr.sparse = !is_pull(v);
     fr.dense = is_pull(v);
@@ -329,7 +376,7 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   byo_opts_default(&o);
   if (opts) o = *opts;
   std::vector<int32_t> srcs(1, (int32_t)src);
-  if (o.use_graph) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
+  if (o.use_graph && o.api_omit == 0) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
   return bfs_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
 }
 
@@ -346,9 +393,11 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     if (stats) *stats = st;
     return BYO_OK;
   }
-  if (o.tiled && tiles_wanted(g)) return cc_tiled_run(g, d_label, o, s, stats);
+  if (o.tiled && o.api_omit == 0 && tiles_wanted(g)) return cc_tiled_run(g, d_label, o, s, stats);
   BYO_TRY(ws_ensure_traversal(g));
   byo_workspace &w = g->ws;
+  api_scope api(g, o.api_omit);
+  BYO_TRY(api.begin(s));
   iota_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, s>>>(d_label, n);
   zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);
   BYO_HIP(hipGetLastError());
@@ -373,8 +422,16 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "connectivity round cap reached");
     }
+    int64_t m_seen = g->m;
+    if (o.api_omit) {
+      BYO_TRY(api.level(fr, s, &m_seen));
+      // the first frontier holds every vertex: its degree sum is m
+      if (round == 0 && !(o.api_omit & BYO_API_NO_DEGREE)) fr.degsum = m_seen;
+    }
     level_features f = features(g, fr.k, fr.degsum, n, round, fr.dense && !fr.sparse);
+    f.m = m_seen;
     int v = pick(o, f, use_mlp);
+    if (o.api_omit) v = api_variant((uint32_t)o.api_omit, v, false);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
