@@ -17,11 +17,13 @@ next to the batched rate.
 Prints ONE JSON line. `--probe pr` instead runs a few PageRank steps and a
 plain 512 MiB device copy, for hardware-counter runs (bytes per dispatch).
 `--ablation` instead replays the container-API configurations of the paper's
-Table api-components-avg (one JSON line of per-case times and slowdowns).
+Table api-components-avg, and `--compression` compares the byte-coded CSR with
+the CSR (one JSON line of per-case times and slowdowns each).
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -202,6 +204,22 @@ def api_ablation(byo, gen, args):
     after one untimed run; slowdown = time / time with the full API. Summaries
     per configuration over every (graph, algorithm) case: mean, 95th
     percentile and maximum, as the table reports them."""
+    configs = [(k, {"api_omit": v}) for k, v in sorted(byo.API_CONFIGS.items(), key=lambda kv: kv[1])]
+    container_study(byo, gen, args, configs, "full", "container API (Table api-components-avg)",
+                    "slowdown over full API")
+
+
+def compression_study(byo, gen, args):
+    """CSR against the byte-coded CSR (the paper's compressed CSR row of its
+    container tables) on the same graphs, algorithms and host-driven level loop;
+    slowdown = time / CSR time, and bytes per edge of each container."""
+    container_study(byo, gen, args, [("csr", {}), ("byte-coded csr", {"compressed": 1})], "csr",
+                    "byte-coded CSR against CSR", "slowdown over CSR")
+
+
+def container_study(byo, gen, args, configs, base_name, title, unit):
+    """Times BFS, connectivity and PageRank per graph and configuration (opts
+    keyword sets); see api_ablation."""
     import torch
     graphs = [
         (f"rmat-{args.scale} graph500", lambda: gen.rmat_pairs(args.scale, 16, gen.GRAPH500_ABCD, seed=1)),
@@ -209,8 +227,8 @@ def api_ablation(byo, gen, args):
         (f"er n=2^{args.scale - 1} d=50", lambda: gen.er_pairs(1 << (args.scale - 1), 50, seed=4)),
         ("grid 2048x2048 del0.1", lambda: gen.grid_pairs(2048, 2048, 0.1, seed=1)),
     ]
-    configs = sorted(byo.API_CONFIGS.items(), key=lambda kv: kv[1])
     cases = []
+    sizes = {}
     for gname, make in graphs:
         p = make()
         srcs = [int(s) for s in gen.pick_sources(p, 2, seed=5)]
@@ -228,8 +246,15 @@ def api_ablation(byo, gen, args):
             "cc": lambda o: byo.cc(g, opts=o, label=label),
             "pagerank": lambda o: byo.pagerank(g, 0.85, args.pr_iters, opts=o, rank=rank),
         }
-        for cname, omit in configs:
-            o = byo.default_opts(api_omit=omit)
+        if any(kw.get("compressed") for _, kw in configs):
+            g.cz_build()
+            nbytes = ctypes.c_int64()
+            byo._lib.check(byo._lib.load().byo_cz_bytes(g.handle, ctypes.byref(nbytes)))
+            sizes[gname] = {"csr_bytes_per_edge": round((8 * (n + 1) + 4 * m) / m, 3),
+                            "cz_bytes_per_edge": round((8 * (n + 1) + nbytes.value) / m, 3),
+                            "cz_list_bytes_per_edge": round(nbytes.value / m, 3)}
+        for cname, kw in configs:
+            o = byo.default_opts(**kw)
             for aname, fn in algos.items():
                 fn(o)
                 ts = []
@@ -239,22 +264,22 @@ def api_ablation(byo, gen, args):
                     fn(o)
                     torch.cuda.synchronize()
                     ts.append((time.perf_counter() - t) * 1e3)
-                cases.append({"graph": gname, "n": n, "m": m, "algo": aname, "config": cname, "api_omit": omit,
+                cases.append({"graph": gname, "n": n, "m": m, "algo": aname, "config": cname,
                               "ms": round(float(np.median(ts)), 4)})
-            log(f"[ablation] {gname} {cname}: " + " ".join(f"{c['algo']}={c['ms']:.2f}ms" for c in cases[-3:]))
+            log(f"[study] {gname} {cname}: " + " ".join(f"{c['algo']}={c['ms']:.2f}ms" for c in cases[-3:]))
         del g, depth, parent, label, rank
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-    full = {(c["graph"], c["algo"]): c["ms"] for c in cases if c["api_omit"] == 0}
+    base = {(c["graph"], c["algo"]): c["ms"] for c in cases if c["config"] == base_name}
     for c in cases:
-        c["slowdown"] = round(c["ms"] / full[(c["graph"], c["algo"])], 4)
+        c["slowdown"] = round(c["ms"] / base[(c["graph"], c["algo"])], 4)
     summary = {}
-    for cname, omit in configs:
-        sl = np.array([c["slowdown"] for c in cases if c["api_omit"] == omit])
-        summary[cname] = {"api_omit": omit, "mean": round(float(sl.mean()), 3),
+    for cname, kw in configs:
+        sl = np.array([c["slowdown"] for c in cases if c["config"] == cname])
+        summary[cname] = {"opts": kw, "mean": round(float(sl.mean()), 3),
                           "p95": round(float(np.percentile(sl, 95)), 3), "max": round(float(sl.max()), 3)}
-    print(json.dumps({"ablation": "container API (Table api-components-avg)", "unit": "slowdown over full API",
-                      "summary": summary, "cases": cases}), flush=True)
+    print(json.dumps({"study": title, "unit": unit, "summary": summary, "sizes": sizes or None, "cases": cases}),
+          flush=True)
 
 
 def probe_pr(g, n, iters):
@@ -290,6 +315,8 @@ def parse():
     ap.add_argument("--probe", choices=["pr"], default=None)
     ap.add_argument("--ablation", action="store_true",
                     help="replay the container-API configurations instead of the benchmark step")
+    ap.add_argument("--compression", action="store_true",
+                    help="compare the byte-coded CSR with the CSR instead of the benchmark step")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--grid-side", type=int, default=4096)
@@ -311,9 +338,9 @@ def main():
     import paper_2405_11671_amd as byo
     from paper_2405_11671_amd import gen
 
-    if args.ablation:
+    if args.ablation or args.compression:
         torch.cuda.init()
-        api_ablation(byo, gen, args)
+        (api_ablation if args.ablation else compression_study)(byo, gen, args)
         return
     t0 = time.time()
     pairs = gen.rmat_pairs(args.scale, 16, gen.GRAPH500_ABCD, seed=1, permute=True)

@@ -111,7 +111,11 @@ typedef struct byo_opts {
                              depths directly); 0 = as many as fit in a quarter of the free device
                              memory, at most 16 (default). Each kept level costs 8 * W * n bytes
                              (W = ceil(k / 64)) plus n / 8. */
-  int32_t reserved[2];
+  int32_t compressed;     /* 1: BFS, connectivity and PageRank read the byte-coded lists
+                             (byo_cz_build; built on first use) through the host-driven level loop:
+                             push and pull by thread or wavefront, PageRank's pull over the lists.
+                             With api_omit != 0: BYO_EINVAL. 0 = the CSR (default) */
+  int32_t reserved[1];
 } byo_opts;
 
 /* Container functions a traversal can be denied (Section 4.2 defines the
@@ -200,6 +204,37 @@ byo_status byo_graph_arrays(const byo_graph *g, const int64_t **d_off, const int
  * vertices, mean and coefficient of variation of the degree. */
 byo_status byo_graph_stats(const byo_graph *g, int64_t *max_deg, int64_t *isolated, double *mean,
                            double *cv);
+
+/* ------------------------------------------------------------------------
+ * Byte-coded CSR: the compressed container of Section 2 ("compressed
+ * graphs": each sorted list stored by difference encoding with byte codes),
+ * in the blocked form that lets blocks decode independently. Kept with the
+ * graph next to the CSR; BFS, connectivity and PageRank decode it inside
+ * their kernels when byo_opts.compressed = 1.
+ *
+ * Format. Vertex v's list (degree d = deg[v], neighbours u_0 < ... < u_{d-1})
+ * starts at byte off[v] of the stream; off[n] = total bytes. It holds
+ * nb = ceil(d / 64) blocks, block j being u_{64j} .. u_{min(d, 64j+64)-1}:
+ *  - if nb > 1, first nb - 1 little-endian uint32: the byte offset, from
+ *    off[v], of blocks 1 .. nb - 1;
+ *  - then the blocks in order. A block's first neighbour u is stored as
+ *    zigzag(u - v) (zigzag(x) = 2x for x >= 0, -2x - 1 for x < 0), every
+ *    further one as its gap to the previous neighbour (>= 1);
+ *  - each stored value is a byte code: 7 bits per byte, low group first,
+ *    bit 7 set on every byte but the last.
+ * Degree-0 vertices take no bytes.
+ * ---------------------------------------------------------------------- */
+/* Build the byte-coded lists on the device (once per graph; later calls
+ * return at once). Syncs. */
+byo_status byo_cz_build(byo_graph *g, void *stream);
+/* Size of the byte stream; BYO_EINVAL before byo_cz_build. */
+byo_status byo_cz_bytes(const byo_graph *g, int64_t *nbytes);
+/* Copy the offsets (n + 1 int64) and the stream (byo_cz_bytes bytes) to
+ * host buffers the caller owns. Syncs. BYO_EINVAL before byo_cz_build. */
+byo_status byo_cz_copy(const byo_graph *g, int64_t *h_off, uint8_t *h_bytes);
+/* Decode v's list on the device into d_out[0 .. deg(v)) (device buffer the
+ * caller owns), ascending. Builds the lists if needed. */
+byo_status byo_cz_decode(byo_graph *g, int64_t v, int32_t *d_out, void *stream);
 
 /* ------------------------------------------------------------------------
  * vertexSubset (Section 3.2): sparse (IDs) or dense (bit array u64[ceil(n/64)],

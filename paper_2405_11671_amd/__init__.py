@@ -125,6 +125,28 @@ class Graph:
                                                ctypes.byref(cv)))
         return {"max_degree": mx.value, "isolated": iso.value, "mean_degree": mean.value, "cv_degree": cv.value}
 
+    def cz_build(self):
+        """Build the byte-coded lists (once per graph)."""
+        _lib.check(_lib.load().byo_cz_build(self._h, _stream()))
+
+    def cz_arrays(self):
+        """(offsets int64[n+1], stream uint8[bytes]) of the byte-coded lists, on the host."""
+        lib = _lib.load()
+        self.cz_build()
+        nb = ctypes.c_int64()
+        _lib.check(lib.byo_cz_bytes(self._h, ctypes.byref(nb)))
+        off = np.empty(self.n + 1, np.int64)
+        data = np.empty(max(nb.value, 1), np.uint8)
+        _lib.check(lib.byo_cz_copy(self._h, off.ctypes.data, data.ctypes.data))
+        return off, data[: nb.value]
+
+    def cz_decode(self, v: int):
+        """v's neighbours decoded from the byte-coded lists on the device (int32 tensor)."""
+        torch = _torch()
+        out = torch.empty(max(self.degree(v), 1), dtype=torch.int32, device="cuda")
+        _lib.check(_lib.load().byo_cz_decode(self._h, int(v), _ptr(out), _stream()))
+        return out[: self.degree(v)]
+
     def device_arrays(self):
         """(off, nbr, deg) device pointers as ints."""
         o, nb, d = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()

@@ -49,7 +49,8 @@ class Opts(ctypes.Structure):
                 ("cc_shortcut", ctypes.c_int32), ("small_frontier", ctypes.c_int32),
                 ("pr_blocked", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tiled", ctypes.c_int32), ("tile_shift", ctypes.c_int32), ("api_omit", ctypes.c_int32),
-                ("ms_history", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("ms_history", ctypes.c_int32), ("compressed", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class RunStats(ctypes.Structure):
@@ -117,6 +118,10 @@ SIGNATURES = {
     "byo_get_neighbors": (st, [vp, i64, vp, i64, i64p]),
     "byo_graph_arrays": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]),
     "byo_graph_stats": (st, [vp, i64p, i64p, dblp, dblp]),
+    "byo_cz_build": (st, [vp, vp]),
+    "byo_cz_bytes": (st, [vp, i64p]),
+    "byo_cz_copy": (st, [vp, vp, vp]),
+    "byo_cz_decode": (st, [vp, i64, vp, vp]),
     "byo_vset_create": (st, [vp, ctypes.POINTER(vp)]),
     "byo_vset_destroy": (None, [vp]),
     "byo_vset_from_ids": (st, [vp, vp, i64, vp]),

@@ -127,7 +127,7 @@ byo_status byo_batch_bfs(byo_batch *b, const int64_t *h_srcs, int32_t *d_depth, 
     srcs[i] = (int32_t)(h_srcs[i] + b->voff[i]);
   }
   hipStream_t s = (hipStream_t)stream;
-  if (o.use_graph && o.api_omit == 0)
+  if (o.use_graph && o.api_omit == 0 && !o.compressed)
     BYO_TRY(bfs_graph_run(b->g, srcs, d_depth, d_parent, o, s, stats));
   else
     BYO_TRY(bfs_run(b->g, srcs, d_depth, d_parent, o, s, stats));

@@ -11,66 +11,9 @@
 // level loop never needs a memset between levels.
 #include <algorithm>
 
-#include "internal.h"
+#include "edgemap_dev.h"
 
 namespace byo {
-
-constexpr int EM_BLOCK = 256;
-
-struct LevelArgs {
-  const int64_t *__restrict__ off;
-  const int32_t *__restrict__ nbr;
-  const int32_t *__restrict__ deg;
-  const int32_t *__restrict__ in_ids;
-  const uint64_t *__restrict__ in_bits;
-  const long long *__restrict__ scan;   // PUSH_EDGE: frontier degree scan
-  int64_t k;                            // |U|
-  int64_t n, words;
-  long long total;                      // PUSH_EDGE: sum of deg(U)
-  int32_t *out_ids;                     // sparse output (nullable)
-  uint64_t *out_bits;                   // dense output (nullable)
-  byo_counters *ctr;
-  byo_counters *ctr_clear;
-  int32_t t_wave, t_block;
-  int32_t no_early_exit;                // pulls scan whole lists (container without early-exit maps)
-};
-
-// ---------------------------------------------------------------- functors
-
-// BFS: a vertex is claimed by the first successful CAS of its parent from -1.
-struct BfsF {
-  int32_t *parent;
-  int32_t *depth;
-  uint64_t *visited;
-  int32_t newdepth;
-  static constexpr bool kDenseFromUpdate = false;
-  __device__ __forceinline__ int32_t src_value(int32_t u) const { return u; }
-  __device__ __forceinline__ bool update(int32_t u, int32_t /*su*/, int32_t v, uint64_t * /*out_bits*/) const {
-    uint64_t bit = 1ull << (v & 63);
-    if (visited[v >> 6] & bit) return false;
-    if (atomicCAS(&parent[v], -1, u) != -1) return false;
-    depth[v] = newdepth;
-    atomicOr((unsigned long long *)&visited[v >> 6], (unsigned long long)bit);
-    return true;
-  }
-};
-
-// Min-label: lower label[v] to label[u]; a vertex is emitted once per call,
-// by whoever first sets its bit in the output bitmap.
-struct CcF {
-  int32_t *label;
-  static constexpr bool kDenseFromUpdate = true;
-  __device__ __forceinline__ int32_t src_value(int32_t u) const { return label[u]; }
-  __device__ __forceinline__ bool update(int32_t /*u*/, int32_t lu, int32_t v, uint64_t *out_bits) const {
-    if (lu >= label[v]) return false;
-    int32_t old = atomicMin(&label[v], lu);
-    if (lu >= old) return false;
-    uint64_t bit = 1ull << (v & 63);
-    unsigned long long prev = atomicOr((unsigned long long *)&out_bits[v >> 6], (unsigned long long)bit);
-    return !(prev & bit);
-  }
-};
-
 
 // ---------------------------------------------------------------- pull scans
 
@@ -123,41 +66,6 @@ __device__ __forceinline__ void wave_count(bool pred, unsigned long long *count)
   uint64_t m = __ballot(pred);
   if (m == 0) return;
   if (lane_id() == __ffsll((long long)m) - 1) atomicAdd(count, (unsigned long long)__popcll(m));
-}
-
-// Emit v if pred. With a sparse output the wavefront reserves slots with one
-// atomic; otherwise the count stays in a register (`count`) and is added once
-// per workgroup in finish_level: same-address atomics from every wavefront of
-// a large grid serialise and would dominate the level.
-template <typename F>
-__device__ __forceinline__ void emit(const LevelArgs &a, bool pred, int32_t v, unsigned long long &degsum,
-                                     unsigned long long &count) {
-  if (a.out_ids)
-    wave_append(pred, v, a.out_ids, &a.ctr->count);
-  else
-    count += pred ? 1ull : 0ull;
-  if (pred) {
-    if (!F::kDenseFromUpdate && a.out_bits)
-      atomicOr((unsigned long long *)&a.out_bits[v >> 6], 1ull << (v & 63));
-    degsum += (unsigned long long)a.deg[v];
-  }
-}
-
-template <int BLOCK>
-__device__ __forceinline__ void finish_level(const LevelArgs &a, unsigned long long degsum,
-                                             unsigned long long count) {
-  unsigned long long t = block_sum<unsigned long long, BLOCK>(degsum);
-  unsigned long long c = block_sum<unsigned long long, BLOCK>(count);
-  if (threadIdx.x == 0) {
-    if (t) atomicAdd(&a.ctr->degsum, t);
-    if (c) atomicAdd(&a.ctr->count, c);
-    if (blockIdx.x == 0 && a.ctr_clear) {
-      a.ctr_clear->count = 0;
-      a.ctr_clear->degsum = 0;
-      a.ctr_clear->aux0 = 0;
-      a.ctr_clear->aux1 = 0;
-    }
-  }
 }
 
 // ---------------------------------------------------------------- push kernels

@@ -168,6 +168,7 @@ void ws_free(byo_workspace &w) {
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);
   ms_release(w);
   tiles_release(w);
+  cz_free(w.cz);
   gm_release(w);
   dl_release(w);
   w = byo_workspace();

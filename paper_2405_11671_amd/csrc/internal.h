@@ -137,6 +137,15 @@ namespace byo {
 struct byo_tiles;
 }
 
+namespace byo {
+// byte-coded neighbour lists (cz.hip): coff[v] = byte offset of v's list
+struct byo_cz {
+  int64_t *coff = nullptr;   // [n + 1]
+  uint8_t *bytes = nullptr;  // [coff[n]], padded
+  int64_t nbytes = 0;
+};
+}  // namespace byo
+
 struct byo_workspace {
   int64_t n = 0;
   int64_t words = 0;
@@ -167,6 +176,7 @@ struct byo_workspace {
   void *ms = nullptr;                // multi-source BFS buffers (msbfs.hip)
   // degree-ordered destination-tile layouts, one per tile size 2^12 .. 2^14 (tiles.hip)
   byo::byo_tiles *tiles[3] = {nullptr, nullptr, nullptr};
+  byo::byo_cz *cz = nullptr;           // byte-coded lists, built on first use
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
 };
@@ -285,6 +295,12 @@ byo_status api_map_degrees(byo_graph *g, uint32_t omit, hipStream_t s, int32_t *
 // the variant the container's functions allow in place of v (BFS pulls exit early)
 int api_variant(uint32_t omit, int v, bool early_exit_pull);
 
+// byte-coded CSR (cz.hip): built once per graph on first use and kept with it
+byo_status cz_ensure(byo_graph *g, hipStream_t s, const byo_cz **out);
+void cz_free(byo_cz *z);
+// the thread or wavefront form a variant takes over byte-coded lists
+int cz_variant(int v);
+
 // conversions (vset.hip)
 byo_status bitmap_clear(uint64_t *bits, int64_t words, hipStream_t s);
 byo_status ids_to_bitmap(const int32_t *ids, int64_t k, uint64_t *bits, int64_t words, hipStream_t s);
@@ -328,6 +344,9 @@ byo_status bfs_level(byo_graph *g, int variant, const bfs_state &st, const level
                      const byo_opts &o, hipStream_t s, long long known_total = -1);
 byo_status cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, const byo_opts &o,
                     hipStream_t s, long long known_total = -1);
+// the same levels over the byte-coded lists (variants as cz_variant maps them)
+byo_status cz_bfs_level(byo_graph *g, int variant, const bfs_state &st, const level_io &io, hipStream_t s);
+byo_status cz_cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, hipStream_t s);
 // acc[v] = sum over u in N(v) of contrib[u] (pagerank.hip)
 byo_status pr_accumulate(byo_graph *g, const float *contrib, float *acc, hipStream_t s);
 byo_status cc_shortcut(byo_graph *g, int32_t *label, uint64_t *out_bits, byo_counters *ctr, hipStream_t s);

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <vector>
 
+#include "cz_dev.h"
 #include "internal.h"
 
 namespace byo {
@@ -184,6 +185,64 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_pull_kernel(const int64_t *__rest
   if (threadIdx.x == 0) dpart[lb] = t;
 }
 
+// One PageRank step over the byte-coded lists: a lane sums its row's first
+// block in order; the further blocks of long rows are summed by the
+// wavefront, one block per lane, then reduced. The rest is pr_pull_kernel's
+// step (same base, contributions, dangling partials).
+__global__ void __launch_bounds__(PR_BLOCK) pr_cz_pull_kernel(const int64_t *__restrict__ coff,
+                                                              const uint8_t *__restrict__ bytes,
+                                                              const int32_t *__restrict__ deg, int64_t n,
+                                                              const float *__restrict__ contrib,
+                                                              const float *__restrict__ base, float damping,
+                                                              float *__restrict__ contrib_next,
+                                                              float *__restrict__ dpart, float *__restrict__ out) {
+  int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  int64_t w = lb * (PR_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
+  int64_t v64 = w * 64 + lane_id();
+  bool valid = v64 < n;
+  int32_t v = (int32_t)v64;
+  int32_t d = 0;
+  int64_t r = 0;
+  if (valid) {
+    d = deg[v];
+    r = coff[v];
+  }
+  const int32_t nb = cz_nblocks(d);
+  // the batch's gathers are issued together, then added in order
+  auto add = [&](const int32_t *u, float &acc) {
+    float c[CZ_BATCH];
+#pragma unroll
+    for (int t = 0; t < CZ_BATCH; ++t) c[t] = u[t] >= 0 ? contrib[u[t]] : 0.0f;
+#pragma unroll
+    for (int t = 0; t < CZ_BATCH; ++t) acc += c[t];
+    return false;
+  };
+  float s = 0.0f;
+  if (nb > 0) cz_block_batches<false>(bytes, r, v, d, nb, 0, [&](const int32_t *u) { return add(u, s); });
+  uint64_t pm = __ballot(nb > 1);
+  while (pm) {
+    const int l = __ffsll((long long)pm) - 1;
+    pm &= pm - 1;
+    const int32_t vl = read_lane_i32(v, l), dl = read_lane_i32(d, l);
+    const int64_t rl = (int64_t)read_lane_u64((uint64_t)r, l);
+    const int32_t nbl = cz_nblocks(dl);
+    float part = 0.0f;
+    for (int32_t j = 1 + lane_id(); j < nbl; j += BYO_WAVE)
+      cz_block_batches<false>(bytes, rl, vl, dl, nbl, j, [&](const int32_t *u) { return add(u, part); });
+    part = wave_sum(part);
+    if (lane_id() == l) s += part;
+  }
+  float rv = base[0] + damping * s;
+  float dang = 0.0f;
+  if (valid) {
+    if (contrib_next) contrib_next[v] = d > 0 ? rv / (float)d : 0.0f;
+    if (d == 0) dang = rv;
+    if (out) out[v] = rv;
+  }
+  float t = block_sum<float, PR_BLOCK>(dang);
+  if (threadIdx.x == 0) dpart[lb] = t;
+}
+
 byo_status ws_ensure_pagerank(byo_graph *g, hipStream_t s) {
   BYO_TRY(ws_ensure_traversal(g));
   byo_workspace &w = g->ws;
@@ -301,6 +360,7 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
   // step maps each vertex's list to count it; without a parallel map every
   // list is summed by one lane.
   const uint32_t omit = (uint32_t)o.api_omit;
+  BYO_CHECK(!o.compressed || omit == 0, BYO_EINVAL, "byte-coded lists run with the full container API");
   const bool par_map = !(omit & BYO_API_NO_PAR_MAP);
   int32_t *mdeg = nullptr;
   if (omit & BYO_API_NO_DEGREE) BYO_TRY(api_map_degrees(g, omit, s, &mdeg));
@@ -311,6 +371,26 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     // a zero-step run returns the initial vector p = 1/n
     fill_f32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_rank, n, 1.0f / (float)n);
     BYO_HIP(hipGetLastError());
+    return BYO_OK;
+  }
+  if (o.compressed) {
+    const byo_cz *cz = nullptr;
+    BYO_TRY(cz_ensure(g, s, &cz));
+    int c = 0;
+    for (int32_t t = 0; t < iters; ++t) {
+      bool last = t + 1 == iters;
+      {
+        ktimer_scope kc(BYO_K_PR_CHUNK, s);  // the step constant only
+        pr_chunk_kernel<<<1, PR_BLOCK, 0, s>>>(g->nbr, w.contrib[c], w.chunk_beg, w.chunk_row, 0, w.chunk_sum,
+                                                w.dpart, nb, damping, n, w.base, 1);
+      }
+      ktimer_scope kp(BYO_K_PR_PULL, s);
+      pr_cz_pull_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(cz->coff, cz->bytes, g->deg, n, w.contrib[c], w.base,
+                                                          (float)damping, last ? nullptr : w.contrib[1 - c], w.dpart,
+                                                          last ? d_rank : nullptr);
+      BYO_HIP(hipGetLastError());
+      c = 1 - c;
+    }
     return BYO_OK;
   }
   if (o.pr_blocked != 0 && omit == 0 && tiles_wanted(g)) {

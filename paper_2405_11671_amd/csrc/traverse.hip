@@ -254,6 +254,8 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   api_scope api(g, o.api_omit);
   BYO_TRY(api.begin(s));
   BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
+  BYO_CHECK(!o.compressed || o.api_omit == 0, BYO_EINVAL, "byte-coded lists run with the full container API");
+  if (o.compressed) BYO_TRY(cz_ensure(g, s, nullptr));
   BYO_TRY(fill_i32(d_parent, n, -1, s));
   BYO_TRY(fill_i32(d_depth, n, -1, s));
   // sources staged through the spare frontier list
@@ -288,7 +290,8 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     }
     const int64_t dl_edges = std::min<int64_t>(std::max<int64_t>(16 * (int64_t)o.small_frontier, 65536),
                                                BYO_DLOOP_QCAP);
-    if (o.small_frontier > 0 && o.api_omit == 0 && fr.k <= o.small_frontier && fr.k <= BYO_DLOOP_QCAP &&
+    if (o.small_frontier > 0 && o.api_omit == 0 && !o.compressed && fr.k <= o.small_frontier &&
+        fr.k <= BYO_DLOOP_QCAP &&
         fr.degsum <= dl_edges && bfs_small_loop_usable(g)) {
       // run levels on the device while the frontier stays small
       BYO_TRY(make_sparse(g, fr, s));
@@ -324,6 +327,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     f.m = m_seen;
     int v = pick(o, f, use_mlp);
     if (o.api_omit) v = api_variant((uint32_t)o.api_omit, v, true);
+    if (o.compressed) v = cz_variant(v);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -341,7 +345,10 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
       io.out_ids = w.ids[nxt];
     }
     bs.level = level;
-    BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
+    if (o.compressed)
+      BYO_TRY(cz_bfs_level(g, v, bs, io, s));
+    else
+      BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
     lt.stop();
     st.variant_count[v]++;
     byo_counters c;
@@ -376,7 +383,7 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   byo_opts_default(&o);
   if (opts) o = *opts;
   std::vector<int32_t> srcs(1, (int32_t)src);
-  if (o.use_graph && o.api_omit == 0) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
+  if (o.use_graph && o.api_omit == 0 && !o.compressed) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
   return bfs_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
 }
 
@@ -393,8 +400,10 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     if (stats) *stats = st;
     return BYO_OK;
   }
-  if (o.tiled && o.api_omit == 0 && tiles_wanted(g)) return cc_tiled_run(g, d_label, o, s, stats);
+  BYO_CHECK(!o.compressed || o.api_omit == 0, BYO_EINVAL, "byte-coded lists run with the full container API");
+  if (o.tiled && o.api_omit == 0 && !o.compressed && tiles_wanted(g)) return cc_tiled_run(g, d_label, o, s, stats);
   BYO_TRY(ws_ensure_traversal(g));
+  if (o.compressed) BYO_TRY(cz_ensure(g, s, nullptr));
   byo_workspace &w = g->ws;
   api_scope api(g, o.api_omit);
   BYO_TRY(api.begin(s));
@@ -432,6 +441,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     f.m = m_seen;
     int v = pick(o, f, use_mlp);
     if (o.api_omit) v = api_variant((uint32_t)o.api_omit, v, false);
+    if (o.compressed) v = cz_variant(v);
     int nxt = 1 - fr.cur;
     level_io io;
     std::memset(&io, 0, sizeof(io));
@@ -449,7 +459,10 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
       io.in_ids = w.ids[fr.cur];
       io.out_ids = shortcut ? nullptr : w.ids[nxt];
     }
-    BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
+    if (o.compressed)
+      BYO_TRY(cz_cc_level(g, v, d_label, io, s));
+    else
+      BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
     if (shortcut) BYO_TRY(cc_shortcut(g, d_label, w.bits[nxt], io.ctr, s));
     lt.stop();
     st.variant_count[v]++;
