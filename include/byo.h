@@ -113,7 +113,9 @@ typedef struct byo_opts {
                              (W = ceil(k / 64)) plus n / 8. */
   int32_t compressed;     /* 1: BFS, connectivity and PageRank read the byte-coded lists
                              (byo_cz_build; built on first use) through the host-driven level loop:
-                             push and pull by thread or wavefront, PageRank's pull over the lists.
+                             push by thread, wavefront (also for PUSH_BUCKET) or blocks spread over
+                             the grid (PUSH_EDGE), pull by thread or wavefront, PageRank's pull over
+                             the lists.
                              With api_omit != 0: BYO_EINVAL. 0 = the CSR (default) */
   int32_t reserved[1];
 } byo_opts;

@@ -9,7 +9,8 @@
 //
 // Levels: a lane decodes whole lists (THREAD) or only its list's first block
 // while the wavefront decodes the further blocks of long lists, one block per
-// lane (WAVE); the pull keeps the first frontier neighbour in ascending order.
+// lane (WAVE); the block-parallel push spreads the frontier's blocks over the
+// grid (EDGE); the pull keeps the first frontier neighbour in ascending order.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -211,6 +212,12 @@ byo_status cz_build(const byo_graph *g, byo_cz *z, hipStream_t s) {
   cz_write_kernel<<<cz_grid(nblk), CZ_THREADS, 0, s>>>(g->off, g->nbr, g->deg, bbase, blkv2, pos, z->coff, nblk,
                                                        z->bytes);
   BYO_HIP(hipGetLastError());
+  // buffers of the block-parallel push
+  BYO_HIP(hipMalloc(&z->fnb, sizeof(int64_t) * (size_t)(n + 1)));
+  BYO_HIP(hipMalloc(&z->fpre, sizeof(int64_t) * (size_t)(n + 1)));
+  BYO_HIP(rocprim::exclusive_scan(nullptr, z->scan_bytes, z->fnb, z->fpre, (int64_t)0, (size_t)n + 1,
+                                  rocprim::plus<int64_t>(), s));
+  BYO_HIP(hipMalloc(&z->scan_tmp, std::max<size_t>(z->scan_bytes, 1)));
   BYO_HIP(hipStreamSynchronize(s));
   return BYO_OK;
 }
@@ -244,6 +251,8 @@ struct CzArgs {
 // blocks after the first are decoded by the whole wavefront, one per lane.
 template <bool WAVE, typename F>
 __global__ void __launch_bounds__(EM_BLOCK) cz_push_kernel(LevelArgs a, CzArgs z, F f) {
+  __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
+  int32_t *row = lds[threadIdx.x / BYO_WAVE];
   unsigned long long degsum = 0, count = 0;
   // uniform trip count per workgroup: every lane reaches the wavefront part
   for (int64_t base = (int64_t)blockIdx.x * EM_BLOCK; base < a.k; base += (int64_t)gridDim.x * EM_BLOCK) {
@@ -271,14 +280,11 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_kernel(LevelArgs a, CzArgs z
         pm &= pm - 1;
         const int32_t ul = read_lane_i32(u, l), dl = read_lane_i32(d, l), sul = read_lane_i32(su, l);
         const int64_t rl = (int64_t)read_lane_u64((uint64_t)r, l);
+        const int64_t el = z.coff[ul + 1];
         const int32_t nbl = cz_nblocks(dl);
-        for (int32_t j0 = 1; j0 < nbl; j0 += BYO_WAVE) {
-          const int32_t j = j0 + lane_id();
-          if (j < nbl)
-            cz_block_for<false>(z.bytes, rl, ul, dl, nbl, j, [&](int32_t v) {
-              emit<F>(a, f.update(ul, sul, v, a.out_bits), v, degsum, count);
-              return false;
-            });
+        for (int32_t j = 1; j < nbl; ++j) {
+          const int32_t v = cz_wave_block(z.bytes, rl, el, ul, dl, nbl, j, row);
+          emit<F>(a, v >= 0 && f.update(ul, sul, v, a.out_bits), v, degsum, count);
         }
       }
     }
@@ -292,6 +298,8 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_kernel(LevelArgs a, CzArgs z
 // time; the lowest block holding a member gives the parent.
 template <bool WAVE>
 __global__ void __launch_bounds__(EM_BLOCK) cz_bfs_pull_kernel(LevelArgs a, CzArgs z, BfsF f) {
+  __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
+  int32_t *row = lds[threadIdx.x / BYO_WAVE];
   unsigned long long degsum = 0, count = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
@@ -331,13 +339,13 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_bfs_pull_kernel(LevelArgs a, CzAr
         pm &= pm - 1;
         const int32_t vl = read_lane_i32(v, l), dl = read_lane_i32(d, l);
         const int64_t rl = (int64_t)read_lane_u64((uint64_t)r, l);
+        const int64_t el = z.coff[vl + 1];
         const int32_t nbl = cz_nblocks(dl);
         bool done = false;
-        for (int32_t j0 = 1; j0 < nbl && !done; j0 += BYO_WAVE) {
-          const int32_t j = j0 + lane_id();
-          int32_t hitu = -1;
-          if (j < nbl)
-            cz_block_batches<true>(z.bytes, rl, vl, dl, nbl, j, [&](const int32_t *u) { return first_in_u(u, hitu); });
+        for (int32_t j = 1; j < nbl && !done; ++j) {
+          // block j decoded by the wavefront; its lowest member is the parent
+          const int32_t u = cz_wave_block(z.bytes, rl, el, vl, dl, nbl, j, row);
+          const int32_t hitu = u >= 0 && test_bit(a.in_bits, u) ? u : -1;
           const uint64_t hm = __ballot(hitu >= 0);
           if (hm) {
             const int32_t pu = read_lane_i32(hitu, __ffsll((long long)hm) - 1);
@@ -407,6 +415,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_cc_pull_kernel(LevelArgs a, CzArg
     for (int32_t j = 0; j < own; ++j)
       cz_block_batches<false>(z.bytes, r, v, d, nb, j, [&](const int32_t *u) { return take(u, best); });
     if (WAVE) {
+      // blocks after the first: one per lane, lane-serial
       uint64_t pm = __ballot(valid && nb > 1);
       while (pm) {
         const int l = __ffsll((long long)pm) - 1;
@@ -439,12 +448,93 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_cc_pull_kernel(LevelArgs a, CzArg
   finish_level<EM_BLOCK>(a, degsum, count);
 }
 
+// fnb[i] = blocks of frontier vertex ids[i]; fnb[k] = 0
+__global__ void cz_frontier_blocks_kernel(const int32_t *__restrict__ ids, const int32_t *__restrict__ deg, int64_t k,
+                                          int64_t *__restrict__ fnb) {
+  for (int64_t i = (int64_t)blockIdx.x * CZ_THREADS + threadIdx.x; i <= k; i += (int64_t)gridDim.x * CZ_THREADS)
+    fnb[i] = i < k ? (int64_t)cz_nblocks(deg[ids[i]]) : 0;
+}
+
+// Block-parallel push (the edge-balanced push of the byte-coded lists): the
+// frontier's blocks are numbered through fpre (exclusive scan of blocks per
+// frontier vertex, fpre[k] = all) and every lane of the grid decodes whole
+// blocks, so one long list spreads over as many lanes as it has blocks.
+template <typename F>
+__global__ void __launch_bounds__(EM_BLOCK) cz_push_blocks_kernel(LevelArgs a, CzArgs z,
+                                                                  const int64_t *__restrict__ fpre, F f) {
+  __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
+  int32_t *row = lds[threadIdx.x / BYO_WAVE];
+  unsigned long long degsum = 0, count = 0;
+  const int64_t total = fpre[a.k];
+  // Lane l of wavefront gw takes blocks gw + nw * (l + 64 t): consecutive
+  // blocks (one long list) land in different wavefronts. A block of more than
+  // CZ_WAVE_MIN neighbours is decoded by the whole wavefront instead.
+  const int64_t nw = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
+  const int64_t gw = (int64_t)blockIdx.x * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
+  for (int64_t t0 = 0; gw + nw * t0 < total; t0 += BYO_WAVE) {  // uniform per wavefront
+    const int64_t b = gw + nw * (t0 + lane_id());
+    int32_t u = 0, d = 0, su = 0, j = 0, c = 0;
+    int64_t r = 0;
+    if (b < total) {
+      int64_t lo = 0, hi = a.k - 1;  // last i with fpre[i] <= b
+      while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (fpre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+      }
+      u = a.in_ids[lo];
+      d = a.deg[u];
+      su = f.src_value(u);
+      r = z.coff[u];
+      j = (int32_t)(b - fpre[lo]);
+      c = d - j * CZ_BLOCK < CZ_BLOCK ? d - j * CZ_BLOCK : CZ_BLOCK;
+    }
+    const bool wide = c > CZ_WAVE_MIN;
+    if (c > 0 && !wide)
+      cz_block_for<false>(z.bytes, r, u, d, cz_nblocks(d), j, [&](int32_t v) {
+        emit<F>(a, f.update(u, su, v, a.out_bits), v, degsum, count);
+        return false;
+      });
+    uint64_t pm = __ballot(wide);
+    while (pm) {
+      const int l = __ffsll((long long)pm) - 1;
+      pm &= pm - 1;
+      const int32_t ul = read_lane_i32(u, l), dl = read_lane_i32(d, l), sul = read_lane_i32(su, l);
+      const int32_t jl = read_lane_i32(j, l);
+      const int64_t rl = (int64_t)read_lane_u64((uint64_t)r, l);
+      const int32_t v = cz_wave_block(z.bytes, rl, z.coff[ul + 1], ul, dl, cz_nblocks(dl), jl, row);
+      emit<F>(a, v >= 0 && f.update(ul, sul, v, a.out_bits), v, degsum, count);
+    }
+  }
+  finish_level<EM_BLOCK>(a, degsum, count);
+}
+
 unsigned cz_pull_grid(int64_t words) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 3) / 4, 4096)); }
 
+// variant: BYO_V_PUSH_THREAD, BYO_V_PUSH_WAVE or BYO_V_PUSH_EDGE (blocks);
+// known_total: the frontier's degree sum (sizes the block-parallel grid)
 template <typename F>
-byo_status cz_launch_push(bool wave, const LevelArgs &a, const CzArgs &z, const F &f, hipStream_t s) {
+byo_status cz_launch_push(int variant, const byo_cz *cz, const LevelArgs &a, const CzArgs &z, const F &f,
+                          long long known_total, hipStream_t s) {
+  if (variant == BYO_V_PUSH_EDGE && a.k > 0) {
+    cz_frontier_blocks_kernel<<<cz_grid(a.k + 1), CZ_THREADS, 0, s>>>(a.in_ids, a.deg, a.k, cz->fnb);
+    BYO_HIP(hipGetLastError());
+    size_t q = 0;
+    BYO_HIP(rocprim::exclusive_scan(nullptr, q, cz->fnb, cz->fpre, (int64_t)0, (size_t)a.k + 1,
+                                    rocprim::plus<int64_t>(), s));
+    BYO_CHECK(q <= cz->scan_bytes, BYO_ESTATE, "frontier scan needs more workspace than sized at build");
+    BYO_HIP(rocprim::exclusive_scan(cz->scan_tmp, q, cz->fnb, cz->fpre, (int64_t)0, (size_t)a.k + 1,
+                                    rocprim::plus<int64_t>(), s));
+    // at most k + degsum / 64 blocks; about 16 per wavefront
+    const int64_t bound = a.k + std::max<long long>(known_total, 0) / CZ_BLOCK;
+    const int64_t per = 16 * (EM_BLOCK / BYO_WAVE);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((bound + per - 1) / per, 16384));
+    cz_push_blocks_kernel<F><<<grid, EM_BLOCK, 0, s>>>(a, z, cz->fpre, f);
+    BYO_HIP(hipGetLastError());
+    return BYO_OK;
+  }
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((a.k + EM_BLOCK - 1) / EM_BLOCK, 16384));
-  if (wave)
+  if (variant == BYO_V_PUSH_WAVE)
     cz_push_kernel<true, F><<<grid, EM_BLOCK, 0, s>>>(a, z, f);
   else
     cz_push_kernel<false, F><<<grid, EM_BLOCK, 0, s>>>(a, z, f);
@@ -455,14 +545,9 @@ byo_status cz_launch_push(bool wave, const LevelArgs &a, const CzArgs &z, const 
 }  // namespace
 
 int cz_variant(int v) {
-  switch (v) {
-    case BYO_V_PUSH_THREAD:
-    case BYO_V_PULL_THREAD:
-    case BYO_V_PULL_WAVE:
-      return v;
-    default:
-      return BYO_V_PUSH_WAVE;  // the parallel push over a list: its blocks
-  }
+  // the bucketed push has no byte-coded form: its wavefront and workgroup
+  // tiers become the wavefront push
+  return v == BYO_V_PUSH_BUCKET ? BYO_V_PUSH_WAVE : v;
 }
 
 byo_status cz_ensure(byo_graph *g, hipStream_t s, const byo_cz **out) {
@@ -484,10 +569,14 @@ void cz_free(byo_cz *z) {
   if (!z) return;
   if (z->coff) (void)hipFree(z->coff);
   if (z->bytes) (void)hipFree(z->bytes);
+  if (z->fnb) (void)hipFree(z->fnb);
+  if (z->fpre) (void)hipFree(z->fpre);
+  if (z->scan_tmp) (void)hipFree(z->scan_tmp);
   delete z;
 }
 
-byo_status cz_bfs_level(byo_graph *g, int variant, const bfs_state &st, const level_io &io, hipStream_t s) {
+byo_status cz_bfs_level(byo_graph *g, int variant, const bfs_state &st, const level_io &io, hipStream_t s,
+                        long long known_total) {
   const byo_cz *cz = nullptr;
   BYO_TRY(cz_ensure(g, s, &cz));
   LevelArgs a = cz_args(g, io);
@@ -506,10 +595,11 @@ byo_status cz_bfs_level(byo_graph *g, int variant, const bfs_state &st, const le
   }
   BYO_CHECK(io.in_ids || io.in_count == 0, BYO_EINVAL, "push needs a sparse input");
   ktimer_scope kt(BYO_K_BFS_PUSH, s);
-  return cz_launch_push(variant != BYO_V_PUSH_THREAD, a, z, f, s);
+  return cz_launch_push(variant, cz, a, z, f, known_total, s);
 }
 
-byo_status cz_cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, hipStream_t s) {
+byo_status cz_cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, hipStream_t s,
+                       long long known_total) {
   const byo_cz *cz = nullptr;
   BYO_TRY(cz_ensure(g, s, &cz));
   LevelArgs a = cz_args(g, io);
@@ -530,7 +620,7 @@ byo_status cz_cc_level(byo_graph *g, int variant, int32_t *label, const level_io
   BYO_CHECK(io.in_ids || io.in_count == 0, BYO_EINVAL, "push needs a sparse input");
   BYO_TRY(bitmap_clear(io.out_bits, a.words, s));
   ktimer_scope kt(BYO_K_CC_PUSH, s);
-  return cz_launch_push(variant != BYO_V_PUSH_THREAD, a, z, f, s);
+  return cz_launch_push(variant, cz, a, z, f, known_total, s);
 }
 
 }  // namespace byo

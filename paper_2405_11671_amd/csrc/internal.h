@@ -143,6 +143,10 @@ struct byo_cz {
   int64_t *coff = nullptr;   // [n + 1]
   uint8_t *bytes = nullptr;  // [coff[n]], padded
   int64_t nbytes = 0;
+  int64_t *fnb = nullptr;    // [n + 1] blocks per frontier vertex (block-parallel push)
+  int64_t *fpre = nullptr;   // [n + 1] their exclusive scan
+  void *scan_tmp = nullptr;  // scan workspace for n + 1 entries
+  size_t scan_bytes = 0;
 };
 }  // namespace byo
 
@@ -298,7 +302,8 @@ int api_variant(uint32_t omit, int v, bool early_exit_pull);
 // byte-coded CSR (cz.hip): built once per graph on first use and kept with it
 byo_status cz_ensure(byo_graph *g, hipStream_t s, const byo_cz **out);
 void cz_free(byo_cz *z);
-// the thread or wavefront form a variant takes over byte-coded lists
+// the form a variant takes over byte-coded lists (the bucketed push becomes
+// the wavefront push; the others keep their kind)
 int cz_variant(int v);
 
 // conversions (vset.hip)
@@ -345,8 +350,11 @@ byo_status bfs_level(byo_graph *g, int variant, const bfs_state &st, const level
 byo_status cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, const byo_opts &o,
                     hipStream_t s, long long known_total = -1);
 // the same levels over the byte-coded lists (variants as cz_variant maps them)
-byo_status cz_bfs_level(byo_graph *g, int variant, const bfs_state &st, const level_io &io, hipStream_t s);
-byo_status cz_cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, hipStream_t s);
+// known_total: the frontier's degree sum (sizes the block-parallel push)
+byo_status cz_bfs_level(byo_graph *g, int variant, const bfs_state &st, const level_io &io, hipStream_t s,
+                        long long known_total);
+byo_status cz_cc_level(byo_graph *g, int variant, int32_t *label, const level_io &io, hipStream_t s,
+                       long long known_total);
 // acc[v] = sum over u in N(v) of contrib[u] (pagerank.hip)
 byo_status pr_accumulate(byo_graph *g, const float *contrib, float *acc, hipStream_t s);
 byo_status cc_shortcut(byo_graph *g, int32_t *label, uint64_t *out_bits, byo_counters *ctr, hipStream_t s);

@@ -219,6 +219,7 @@ __global__ void __launch_bounds__(PR_BLOCK) pr_cz_pull_kernel(const int64_t *__r
   };
   float s = 0.0f;
   if (nb > 0) cz_block_batches<false>(bytes, r, v, d, nb, 0, [&](const int32_t *u) { return add(u, s); });
+  // blocks after the first: one per lane, lane-serial, then reduced
   uint64_t pm = __ballot(nb > 1);
   while (pm) {
     const int l = __ffsll((long long)pm) - 1;

@@ -346,7 +346,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
     }
     bs.level = level;
     if (o.compressed)
-      BYO_TRY(cz_bfs_level(g, v, bs, io, s));
+      BYO_TRY(cz_bfs_level(g, v, bs, io, s, fr.degsum));
     else
       BYO_TRY(bfs_level(g, v, bs, io, o, s, fr.degsum));
     lt.stop();
@@ -460,7 +460,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
       io.out_ids = shortcut ? nullptr : w.ids[nxt];
     }
     if (o.compressed)
-      BYO_TRY(cz_cc_level(g, v, d_label, io, s));
+      BYO_TRY(cz_cc_level(g, v, d_label, io, s, fr.degsum));
     else
       BYO_TRY(cc_level(g, v, d_label, io, o, s, fr.degsum));
     if (shortcut) BYO_TRY(cc_shortcut(g, d_label, w.bits[nxt], io.ctr, s));
