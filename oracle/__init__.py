@@ -62,6 +62,11 @@ def _load():
         lib.oracle_pagerank.restype = ctypes.c_int
         lib.oracle_msbfs.argtypes = [vp, i64p, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_msbfs.restype = ctypes.c_int
+        dblp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_bc_definition.argtypes = [vp, i64, dblp]
+        lib.oracle_bc_definition.restype = ctypes.c_int
+        lib.oracle_bc.argtypes = [vp, i64, dblp, dblp, i32p]
+        lib.oracle_bc.restype = ctypes.c_int
         lib.oracle_check_bfs.argtypes = [vp, i64, i32p, i32p]
         lib.oracle_check_bfs.restype = i64
         _lib = lib
@@ -143,6 +148,24 @@ class Graph:
         if rc != 0:
             raise ValueError(f"oracle_msbfs failed ({rc})")
         return depth[: self.n * k].reshape(self.n, k)
+
+    def bc(self, src: int):
+        """Brandes' recurrence: (sigma, delta, dist) from src, FP64."""
+        sigma = np.empty(max(self.n, 1), np.float64)
+        delta = np.empty(max(self.n, 1), np.float64)
+        dist = np.empty(max(self.n, 1), np.int32)
+        rc = _load().oracle_bc(self._h, int(src), _p(sigma, ctypes.c_double), _p(delta, ctypes.c_double),
+                               _p(dist, ctypes.c_int32))
+        if rc != 0:
+            raise ValueError(f"oracle_bc failed ({rc})")
+        return sigma[: self.n], delta[: self.n], dist[: self.n]
+
+    def bc_definition(self, src: int) -> np.ndarray:
+        """The pairwise definition of the dependencies (small graphs only)."""
+        delta = np.empty(max(self.n, 1), np.float64)
+        if _load().oracle_bc_definition(self._h, int(src), _p(delta, ctypes.c_double)) != 0:
+            raise ValueError("oracle_bc_definition failed")
+        return delta[: self.n]
 
     def check_bfs(self, src: int, depth: np.ndarray, parent: np.ndarray) -> int:
         depth = np.ascontiguousarray(depth, np.int32)

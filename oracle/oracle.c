@@ -22,6 +22,11 @@
  *   - CC: every vertex labelled with the smallest vertex ID in its component.
  *   - PageRank: T power-iteration steps in FP64 with uniform teleport and the
  *     mass of zero-degree vertices spread uniformly.
+ *   - Single-source betweenness (BC): the dependency of the source on every
+ *     vertex, delta_s(v) = sum over targets t of sigma_st(v) / sigma_st, where
+ *     sigma_st counts shortest s-t paths and sigma_st(v) those through v. Two
+ *     forms: the definition summed pair by pair (tiny graphs, to pin the
+ *     other), and Brandes' recurrence over the BFS levels.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -240,4 +245,79 @@ int64_t oracle_check_bfs(const oracle_graph *g, int64_t src, const int32_t *dept
   }
   free(dd); free(pp);
   return bad;
+}
+
+/* BFS from src: hop distances (-1 unreachable) and shortest-path counts
+ * sigma (1 at src, 0 unreachable), FP64 (exact integers below 2^53). When
+ * order is given it receives the vertices in visiting order (nondecreasing
+ * distance) and the function returns how many. */
+static int64_t bfs_paths(const oracle_graph *g, int64_t src, int32_t *dist, double *sigma, int32_t *order) {
+  int32_t *queue = order ? order : (int32_t *)malloc(sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1));
+  if (!queue) return -2;
+  for (int64_t v = 0; v < g->n; ++v) { dist[v] = -1; sigma[v] = 0.0; }
+  int64_t head = 0, tail = 0;
+  dist[src] = 0;
+  sigma[src] = 1.0;
+  queue[tail++] = (int32_t)src;
+  while (head < tail) {
+    int32_t u = queue[head++];
+    for (int64_t i = 0; i < g->len[u]; ++i) {
+      int32_t v = g->nb[u][i];
+      if (dist[v] == -1) { dist[v] = dist[u] + 1; queue[tail++] = v; }
+      if (dist[v] == dist[u] + 1) sigma[v] += sigma[u];
+    }
+  }
+  if (!order) free(queue);
+  return tail;
+}
+
+/* The definition, pair by pair: v lies on a shortest s-t path iff
+ * d(s,v) + d(v,t) = d(s,t), and then sigma_st(v) = sigma_sv * sigma_vt. One BFS
+ * from every vertex: O(n (n + m)), for small graphs only. delta[s] = 0 and
+ * delta[v] = 0 for v unreachable from s. */
+int oracle_bc_definition(const oracle_graph *g, int64_t s, double *delta) {
+  int64_t n = g->n;
+  if (s < 0 || s >= n) return -1;
+  int32_t *ds = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *dv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  double *ss = (double *)malloc(sizeof(double) * (size_t)n);
+  double *sv = (double *)malloc(sizeof(double) * (size_t)n);
+  if (!ds || !dv || !ss || !sv) { free(ds); free(dv); free(ss); free(sv); return -2; }
+  bfs_paths(g, s, ds, ss, NULL);
+  for (int64_t v = 0; v < n; ++v) {
+    delta[v] = 0.0;
+    if (v == s || ds[v] < 0) continue;
+    bfs_paths(g, v, dv, sv, NULL);
+    double sum = 0.0;
+    for (int64_t t = 0; t < n; ++t) {
+      if (t == s || t == v || ds[t] < 0 || dv[t] < 0) continue;
+      if (ds[v] + dv[t] == ds[t]) sum += ss[v] * sv[t] / ss[t];
+    }
+    delta[v] = sum;
+  }
+  free(ds); free(dv); free(ss); free(sv);
+  return 0;
+}
+
+/* Brandes' recurrence: with P(w) the neighbours of w one level closer to s,
+ * delta(v) = sum over w with v in P(w) of sigma(v) / sigma(w) * (1 + delta(w)),
+ * accumulated over the vertices in reverse visiting order; delta[s] = 0.
+ * Also returns sigma (path counts) and the hop distances. */
+int oracle_bc(const oracle_graph *g, int64_t s, double *sigma, double *delta, int32_t *dist) {
+  int64_t n = g->n;
+  if (s < 0 || s >= n) return -1;
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!order) return -2;
+  int64_t cnt = bfs_paths(g, s, dist, sigma, order);
+  for (int64_t v = 0; v < n; ++v) delta[v] = 0.0;
+  for (int64_t i = cnt - 1; i >= 0; --i) {
+    int32_t w = order[i];
+    for (int64_t j = 0; j < g->len[w]; ++j) {
+      int32_t v = g->nb[w][j];
+      if (dist[v] == dist[w] - 1) delta[v] += sigma[v] / sigma[w] * (1.0 + delta[w]);
+    }
+  }
+  delta[s] = 0.0;
+  free(order);
+  return 0;
 }

@@ -82,3 +82,45 @@ def pagerank_fixed_point(A, d):
     z = (~nz).astype(np.float64)
     lhs = np.eye(n) - d * (M + np.outer(np.ones(n), z) / n)
     return np.linalg.solve(lhs, np.full(n, (1.0 - d) / n))
+
+
+def all_shortest_paths(n, src, dst, s):
+    """Every shortest path from s, enumerated explicitly: {t: [path, ...]} with
+    paths as vertex tuples (plain Python breadth-first path extension)."""
+    adj = {v: set() for v in range(n)}
+    for u, v in simple_edges(n, src, dst):
+        adj[u].add(v)
+        adj[v].add(u)
+    paths = {s: [(s,)]}
+    frontier = [s]
+    seen = {s}
+    while frontier:
+        nxt = {}
+        for u in frontier:
+            for p in paths[u]:
+                for w in adj[u]:
+                    if w not in seen:
+                        nxt.setdefault(w, []).append(p + (w,))
+        for w, ps in nxt.items():
+            paths[w] = ps
+        seen |= set(nxt)
+        frontier = list(nxt)
+    return paths
+
+
+def dependency_by_enumeration(n, src, dst, s):
+    """delta_s(v) = sum over t != s, v of (shortest s-t paths through v) / (shortest s-t paths),
+    counted on the enumerated paths with exact fractions."""
+    from fractions import Fraction
+    paths = all_shortest_paths(n, src, dst, s)
+    delta = [Fraction(0)] * n
+    for t, ps in paths.items():
+        if t == s:
+            continue
+        for v in range(n):
+            if v in (s, t):
+                continue
+            through = sum(1 for p in ps if v in p)
+            if through:
+                delta[v] += Fraction(through, len(ps))
+    return delta, {t: len(ps) for t, ps in paths.items()}

@@ -301,6 +301,67 @@ def test_predict_argmin_respects_mask_and_ties():
 
 # ---------------------------------------------------------------- golden fixture
 
+# ---------------------------------------------------------------- single-source betweenness
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 9).flatmap(
+    lambda n: st.tuples(st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)),
+                                             max_size=2 * n))), st.integers(0, 10 ** 6))
+def test_bc_definition_matches_path_enumeration(case, s):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    s = s % n
+    want, counts = brute.dependency_by_enumeration(n, a, b, s)
+    got = g.bc_definition(s)
+    assert np.allclose(got, [float(x) for x in want], rtol=1e-12, atol=1e-12)
+    sigma, delta, dist = g.bc(s)
+    for v in range(n):
+        assert sigma[v] == counts.get(v, 0)
+    assert np.allclose(delta, [float(x) for x in want], rtol=1e-12, atol=1e-12)
+
+
+@settings(max_examples=40, deadline=None)
+@given(tiny_graphs, st.integers(0, 10 ** 6))
+def test_bc_recurrence_matches_definition(case, s):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    s = s % n
+    sigma, delta, dist = g.bc(s)
+    assert np.allclose(delta, g.bc_definition(s), rtol=1e-12, atol=1e-12)
+    want_d, _ = g.bfs(s)
+    assert np.array_equal(dist, want_d)
+    assert np.all((sigma > 0) == (want_d >= 0))
+
+
+def test_bc_closed_forms():
+    n = 12
+    path = [(i, i + 1) for i in range(n - 1)]
+    g, _, _ = G(n, path)
+    # from one end every vertex v carries the n-1-v targets beyond it
+    assert np.allclose(g.bc(0)[1], [0] + [n - 1 - v for v in range(1, n)])
+    # from vertex 4: its left side carries v targets, its right side n-1-v
+    want = [v for v in range(4)] + [0] + [n - 1 - v for v in range(5, n)]
+    assert np.allclose(g.bc(4)[1], want)
+    star = [(0, i) for i in range(1, n)]
+    g, _, _ = G(n, star)
+    assert np.allclose(g.bc(0)[1], 0)
+    # from a leaf, the centre carries the other n-2 leaves
+    assert np.allclose(g.bc(3)[1], [n - 2] + [0] * (n - 1))
+    complete = [(u, v) for u in range(7) for v in range(u + 1, 7)]
+    g, _, _ = G(7, complete)
+    assert np.allclose(g.bc(2)[1], 0)
+    # even cycle C_2k from 0: vertex 1 carries k-2 targets alone and half of the antipode
+    k = 6
+    cyc = [(i, (i + 1) % (2 * k)) for i in range(2 * k)]
+    g, _, _ = G(2 * k, cyc)
+    sigma, delta, _ = g.bc(0)
+    assert sigma[k] == 2 and delta[1] == pytest.approx(k - 2 + 0.5)
+    # disconnected: unreachable vertices keep 0
+    g, _, _ = G(5, [(0, 1), (1, 2), (3, 4)])
+    sigma, delta, dist = g.bc(0)
+    assert delta.tolist() == [0, 1, 0, 0, 0] and sigma.tolist() == [1, 1, 1, 0, 0]
+
+
 def test_golden_small_graph():
     import json
     import os
