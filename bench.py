@@ -142,6 +142,30 @@ def grid_workload(byo, gen, mlp_opts, side):
     return res
 
 
+def bc_workload(byo, g, srcs):
+    """Single-source betweenness (forward path counting + backward dependency
+    pass) on the benchmark graph: median ms per source over 3 rounds, and
+    GTEPS counting each reached undirected edge once per source."""
+    import torch
+    n = g.n
+    delta = torch.empty(n, dtype=torch.float64, device="cuda")
+    sigma = torch.empty(n, dtype=torch.float64, device="cuda")
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    run = lambda s: byo.bc(g, int(s), delta=delta, sigma=sigma, depth=depth)[3]  # noqa: E731
+    for s in srcs:
+        run(s)
+    per, edges = [], 0
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        edges = sum(run(s)["edges"] // 2 for s in srcs)
+        torch.cuda.synchronize()
+        per.append((time.perf_counter() - t) * 1e3 / len(srcs))
+    ms = float(np.median(per))
+    return {"sources": len(srcs), "ms_per_source": round(ms, 3),
+            "gteps": round(edges / len(srcs) / (ms * 1e-3) / 1e9, 2)}
+
+
 def batch_workload(byo, gen, count=64):
     """64 Erdos-Renyi graphs (n log-uniform in [2^10, 2^18], average degree in
     [4, 32]), BFS from the first non-isolated vertex of each: 64 separate
@@ -319,6 +343,7 @@ def parse():
                     help="compare the byte-coded CSR with the CSR instead of the benchmark step")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-bc", action="store_true")
     ap.add_argument("--grid-side", type=int, default=4096)
     ap.add_argument("--no-tiles", action="store_true",
                     help="PageRank and multi-source BFS over the CSR instead of the tile layout")
@@ -454,6 +479,7 @@ def main():
     pr_launches, pr_kms = kt["pr_pull"]
     pr_avg_ms = (pr_kms + kt["pr_chunk"][1]) / max(pr_launches, 1)   # tile kernel + apply kernel per step
     pr_bytes = 4 * m + 16 * n + 8          # per step: neighbours, offsets, contrib read + write, rank write
+    bc = None if args.no_bc else bc_workload(byo, g, srcs[:4])
     grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     batch = None if args.no_batch else batch_workload(byo, gen)
     detail = {
@@ -471,6 +497,7 @@ def main():
         "pr_step_avg_ms": pr_avg_ms, "pr_step_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
         "tile_layout_build_s": layout_s, "tiled": not args.no_tiles,
         "kernel_ms": {f: round(v[1], 3) for f, v in kt_all.items() if v[0]},
+        "bc": bc,
         "grid": grid,
         "batch64": batch,
     }

@@ -292,6 +292,24 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
  * named (hooking); cc_shortcut adds pointer jumping. Any path gives the same
  * labels. */
 byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *stream, byo_run_stats *stats);
+/* Single-source betweenness (Table algs-list, shortest-path problems): the
+ * dependency of src on every vertex, delta[v] = sum over targets t of
+ * sigma_st(v) / sigma_st, where sigma_st counts shortest src-t paths and
+ * sigma_st(v) those through v (Brandes' dependency; delta[src] = 0, and 0 for
+ * vertices src does not reach). sigma[v] = number of shortest src-v paths
+ * (integers, exact in FP64 below 2^53; 0 when unreachable); depth[v] = hop
+ * distance (-1 when unreachable).
+ * Forward: level-synchronous BFS that counts paths, push or pull per level by
+ * the sparse/dense cutoff (|U| + sum deg(U) > m / dense_divisor);
+ * selector = BYO_SEL_FIXED forces push (PUSH_*) or pull (PULL_*), the
+ * *_THREAD variants without wavefront-shared lists. Backward: one pull per
+ * level, deepest first. d_delta: device FP64 [n]; d_sigma (FP64 [n]) and
+ * d_depth (int32 [n]) are device buffers or NULL. Returns when done (it reads
+ * each level's size back). BYO_ELIMIT if max_levels is reached. stats:
+ * levels, reached, edges (sum of the frontiers' degrees), variants used. */
+byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double *d_sigma, int32_t *d_depth,
+                  const byo_opts *opts, void *stream, byo_run_stats *stats);
+
 /* PageRank, FP32, `iters` steps from 1/n: p'[v] = (1-d)/n + d * (sum over
  * u in N(v) of p[u]/deg(u) + D/n), D = mass on degree-0 vertices. */
 byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, float *d_rank, const byo_opts *opts,

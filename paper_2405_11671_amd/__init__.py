@@ -251,6 +251,21 @@ def pagerank(g: Graph, damping: float = 0.85, iters: int = 20, opts=None, rank=N
     return rank[: g.n], stt.as_dict()
 
 
+def bc(g: Graph, src: int, opts=None, delta=None, sigma=None, depth=None, **kw):
+    """Single-source betweenness from src: (delta, sigma, depth, stats); delta and sigma float64,
+    depth int32, device tensors."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    n1 = max(g.n, 1)
+    delta = torch.empty(n1, dtype=torch.float64, device="cuda") if delta is None else delta
+    sigma = torch.empty(n1, dtype=torch.float64, device="cuda") if sigma is None else sigma
+    depth = torch.empty(n1, dtype=torch.int32, device="cuda") if depth is None else depth
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_bc(g.handle, int(src), _ptr(delta), _ptr(sigma), _ptr(depth), ctypes.byref(o),
+                                  _stream(), ctypes.byref(stt)))
+    return delta[: g.n], sigma[: g.n], depth[: g.n], stt.as_dict()
+
+
 def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, opts=None, **kw) -> int:
     """edgeMap(G, U, F) into `out`; returns the variant that ran."""
     o = _opts(opts, kw)

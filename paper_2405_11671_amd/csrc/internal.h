@@ -181,6 +181,10 @@ struct byo_workspace {
   // degree-ordered destination-tile layouts, one per tile size 2^12 .. 2^14 (tiles.hip)
   byo::byo_tiles *tiles[3] = {nullptr, nullptr, nullptr};
   byo::byo_cz *cz = nullptr;           // byte-coded lists, built on first use
+  double *bc_coef = nullptr;           // [n] betweenness: (1 + delta) / sigma per vertex
+  double *bc_sigma = nullptr;          // [n] path counts when the caller passes none
+  int32_t *bc_depth = nullptr;         // [n] depths when the caller passes none
+  int32_t *bc_order = nullptr;         // [n] vertices level by level
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
 };
