@@ -67,6 +67,10 @@ def _load():
         lib.oracle_bc_definition.restype = ctypes.c_int
         lib.oracle_bc.argtypes = [vp, i64, dblp, dblp, i32p]
         lib.oracle_bc.restype = ctypes.c_int
+        lib.oracle_kcore_definition.argtypes = [vp, i32p]
+        lib.oracle_kcore_definition.restype = ctypes.c_int
+        lib.oracle_kcore.argtypes = [vp, i32p]
+        lib.oracle_kcore.restype = ctypes.c_int
         lib.oracle_check_bfs.argtypes = [vp, i64, i32p, i32p]
         lib.oracle_check_bfs.restype = i64
         _lib = lib
@@ -166,6 +170,20 @@ class Graph:
         if _load().oracle_bc_definition(self._h, int(src), _p(delta, ctypes.c_double)) != 0:
             raise ValueError("oracle_bc_definition failed")
         return delta[: self.n]
+
+    def kcore(self) -> np.ndarray:
+        """Coreness of every vertex by bucketed peeling."""
+        core = np.empty(max(self.n, 1), np.int32)
+        if _load().oracle_kcore(self._h, _p(core, ctypes.c_int32)) != 0:
+            raise MemoryError("oracle_kcore failed")
+        return core[: self.n]
+
+    def kcore_definition(self) -> np.ndarray:
+        """Coreness from the definition (small graphs only)."""
+        core = np.empty(max(self.n, 1), np.int32)
+        if _load().oracle_kcore_definition(self._h, _p(core, ctypes.c_int32)) != 0:
+            raise MemoryError("oracle_kcore_definition failed")
+        return core[: self.n]
 
     def check_bfs(self, src: int, depth: np.ndarray, parent: np.ndarray) -> int:
         depth = np.ascontiguousarray(depth, np.int32)

@@ -27,6 +27,11 @@
  *     sigma_st counts shortest s-t paths and sigma_st(v) those through v. Two
  *     forms: the definition summed pair by pair (tiny graphs, to pin the
  *     other), and Brandes' recurrence over the BFS levels.
+ *   - k-core: the coreness of every vertex, the largest k such that the vertex
+ *     belongs to the k-core (the maximal subgraph whose vertices all keep at
+ *     least k neighbours in it). Two forms: the definition, one deletion
+ *     fixpoint per k (small graphs, to pin the other), and peeling the vertex
+ *     of least remaining degree first with degree buckets.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -319,5 +324,89 @@ int oracle_bc(const oracle_graph *g, int64_t s, double *sigma, double *delta, in
   }
   delta[s] = 0.0;
   free(order);
+  return 0;
+}
+
+/* The definition: for k = 0, 1, 2, ... delete vertices with fewer than k
+ * remaining neighbours until none is left to delete; what survives is the
+ * k-core, and core[v] is the last k whose core still holds v. O(maxdeg * m)
+ * with a full pass per deletion round: small graphs only. */
+int oracle_kcore_definition(const oracle_graph *g, int32_t *core) {
+  int64_t n = g->n;
+  uint8_t *in = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+  int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!in || !d) { free(in); free(d); return -2; }
+  for (int64_t v = 0; v < n; ++v) core[v] = 0;
+  for (int64_t k = 1;; ++k) {
+    for (int64_t v = 0; v < n; ++v) in[v] = 1;
+    int changed = 1;
+    while (changed) {
+      changed = 0;
+      for (int64_t v = 0; v < n; ++v) {
+        if (!in[v]) continue;
+        int64_t c = 0;
+        for (int64_t i = 0; i < g->len[v]; ++i) c += in[g->nb[v][i]];
+        d[v] = c;
+      }
+      for (int64_t v = 0; v < n; ++v)
+        if (in[v] && d[v] < k) { in[v] = 0; changed = 1; }
+    }
+    int64_t left = 0;
+    for (int64_t v = 0; v < n; ++v)
+      if (in[v]) { core[v] = (int32_t)k; ++left; }
+    if (left == 0) break;
+  }
+  free(in);
+  free(d);
+  return 0;
+}
+
+/* Peeling: repeatedly remove a vertex of least remaining degree; its
+ * coreness is the largest such least degree seen so far. Degree buckets
+ * (doubly linked lists) make each step O(1) amortised: O(n + m) total. */
+int oracle_kcore(const oracle_graph *g, int32_t *core) {
+  int64_t n = g->n, maxd = 0;
+  for (int64_t v = 0; v < n; ++v) maxd = g->len[v] > maxd ? g->len[v] : maxd;
+  int64_t *deg = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *head = (int64_t *)malloc(sizeof(int64_t) * (size_t)(maxd + 1));
+  int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  uint8_t *gone = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!deg || !head || !next || !prev || !gone) {
+    free(deg); free(head); free(next); free(prev); free(gone);
+    return -2;
+  }
+  for (int64_t b = 0; b <= maxd; ++b) head[b] = -1;
+  for (int64_t v = 0; v < n; ++v) {  /* push v onto bucket deg[v] */
+    deg[v] = g->len[v];
+    prev[v] = -1;
+    next[v] = head[deg[v]];
+    if (head[deg[v]] >= 0) prev[head[deg[v]]] = v;
+    head[deg[v]] = v;
+  }
+  int64_t k = 0, b = 0;
+  for (int64_t done = 0; done < n; ++done) {
+    while (head[b] < 0) ++b;   /* least nonempty bucket; a removal lowers degrees by at most 1 */
+    int64_t v = head[b];
+    head[b] = next[v];
+    if (next[v] >= 0) prev[next[v]] = -1;
+    gone[v] = 1;
+    if (b > k) k = b;
+    core[v] = (int32_t)k;
+    for (int64_t i = 0; i < g->len[v]; ++i) {
+      int64_t u = g->nb[v][i];
+      if (gone[u]) continue;
+      /* move u from bucket deg[u] to deg[u] - 1 */
+      if (prev[u] >= 0) next[prev[u]] = next[u]; else head[deg[u]] = next[u];
+      if (next[u] >= 0) prev[next[u]] = prev[u];
+      --deg[u];
+      prev[u] = -1;
+      next[u] = head[deg[u]];
+      if (head[deg[u]] >= 0) prev[head[deg[u]]] = u;
+      head[deg[u]] = u;
+    }
+    if (b > 0) --b;            /* a neighbour may now sit one bucket lower */
+  }
+  free(deg); free(head); free(next); free(prev); free(gone);
   return 0;
 }

@@ -362,6 +362,75 @@ def test_bc_closed_forms():
     assert delta.tolist() == [0, 1, 0, 0, 0] and sigma.tolist() == [1, 1, 1, 0, 0]
 
 
+# ---------------------------------------------------------------- k-core
+
+def brute_kcore(n, a, b):
+    """Coreness from the definition with plain Python sets: for each k the
+    vertices left after deleting, one at a time, any vertex with fewer than k
+    remaining neighbours."""
+    E = brute.simple_edges(n, a, b)
+    adj = {v: set() for v in range(n)}
+    for u, v in E:
+        adj[u].add(v)
+        adj[v].add(u)
+    core = [0] * n
+    k = 1
+    while True:
+        alive = set(range(n))
+        stack = [v for v in alive if len(adj[v]) < k]
+        while stack:
+            v = stack.pop()
+            if v not in alive:
+                continue
+            alive.discard(v)
+            for u in adj[v]:
+                if u in alive and len(adj[u] & alive) < k:
+                    stack.append(u)
+        if not alive:
+            return core
+        for v in alive:
+            core[v] = k
+        k += 1
+
+
+@settings(max_examples=80, deadline=None)
+@given(tiny_graphs)
+def test_kcore_matches_brute_force_and_definition(case):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    want = brute_kcore(n, a, b)
+    assert g.kcore_definition().tolist() == want
+    assert g.kcore().tolist() == want
+
+
+def test_kcore_properties_on_larger_graphs():
+    rng = np.random.default_rng(7)
+    for n, m in ((300, 1500), (500, 4000)):
+        a = rng.integers(0, n, m).astype(np.int32)
+        b = rng.integers(0, n, m).astype(np.int32)
+        g = oracle.Graph(n, a, b)
+        core = g.kcore()
+        assert np.array_equal(core, g.kcore_definition())
+        # every vertex keeps at least core[v] neighbours of coreness >= core[v],
+        # and not core[v] + 1 neighbours of coreness >= core[v] + 1
+        for v in range(n):
+            nb = g.neighbors(v)
+            assert int((core[nb] >= core[v]).sum()) >= core[v]
+            assert int((core[nb] >= core[v] + 1).sum()) < core[v] + 1 or core[v] == g.degree(v)
+
+
+def test_kcore_closed_forms():
+    def run(n, pairs):
+        return G(n, pairs)[0].kcore().tolist()
+    assert run(6, [(u, v) for u in range(6) for v in range(u + 1, 6)]) == [5] * 6          # K6
+    assert run(8, [(i, i + 1) for i in range(7)]) == [1] * 8                               # path
+    assert run(9, [(0, i) for i in range(1, 9)]) == [1] * 9                                # star
+    assert run(10, [(i, (i + 1) % 10) for i in range(10)]) == [2] * 10                     # cycle
+    assert run(7, [(u, v) for u in range(3) for v in range(3, 7)]) == [3] * 7              # K_{3,4}
+    k4_tail = [(u, v) for u in range(4) for v in range(u + 1, 4)] + [(3, 4), (4, 5)]
+    assert run(7, k4_tail) == [3, 3, 3, 3, 1, 1, 0]                                        # K4, tail, isolated
+
+
 def test_golden_small_graph():
     import json
     import os
