@@ -166,6 +166,22 @@ def bc_workload(byo, g, srcs):
             "gteps": round(edges / len(srcs) / (ms * 1e-3) / 1e9, 2)}
 
 
+def kcore_workload(byo, g):
+    """k-core decomposition of the benchmark graph: median of 3 runs (ms),
+    sub-rounds, and the largest coreness."""
+    import torch
+    core = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    byo.kcore(g, core=core)
+    ts, st = [], None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = byo.kcore(g, core=core)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    return {"ms": round(float(np.median(ts)), 3), "sub_rounds": st["levels"], "max_core": int(core.max().item())}
+
+
 def batch_workload(byo, gen, count=64):
     """64 Erdos-Renyi graphs (n log-uniform in [2^10, 2^18], average degree in
     [4, 32]), BFS from the first non-isolated vertex of each: 64 separate
@@ -343,7 +359,7 @@ def parse():
                     help="compare the byte-coded CSR with the CSR instead of the benchmark step")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-bc", action="store_true")
+    ap.add_argument("--no-bc", action="store_true", help="skip the betweenness and k-core detail")
     ap.add_argument("--grid-side", type=int, default=4096)
     ap.add_argument("--no-tiles", action="store_true",
                     help="PageRank and multi-source BFS over the CSR instead of the tile layout")
@@ -480,6 +496,7 @@ def main():
     pr_avg_ms = (pr_kms + kt["pr_chunk"][1]) / max(pr_launches, 1)   # tile kernel + apply kernel per step
     pr_bytes = 4 * m + 16 * n + 8          # per step: neighbours, offsets, contrib read + write, rank write
     bc = None if args.no_bc else bc_workload(byo, g, srcs[:4])
+    kcore = None if args.no_bc else kcore_workload(byo, g)
     grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     batch = None if args.no_batch else batch_workload(byo, gen)
     detail = {
@@ -498,6 +515,7 @@ def main():
         "tile_layout_build_s": layout_s, "tiled": not args.no_tiles,
         "kernel_ms": {f: round(v[1], 3) for f, v in kt_all.items() if v[0]},
         "bc": bc,
+        "kcore": kcore,
         "grid": grid,
         "batch64": batch,
     }

@@ -310,6 +310,17 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
 byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double *d_sigma, int32_t *d_depth,
                   const byo_opts *opts, void *stream, byo_run_stats *stats);
 
+/* k-core decomposition (Table algs-list, substructure problems): d_core[v] =
+ * the coreness of v, the largest k such that v belongs to the k-core (the
+ * maximal subgraph in which every vertex keeps at least k neighbours); 0 for
+ * isolated vertices. Peeling: at each k, the alive vertices with remaining
+ * degree <= k are removed in edge-balanced push sub-rounds until none is
+ * left, k then jumping to the least remaining degree. d_core: device int32
+ * [n]. Returns when done (it reads each sub-round's size back). BYO_ELIMIT
+ * if max_levels sub-rounds do not finish. stats: levels = sub-rounds,
+ * edges = sum of the removed vertices' degrees. */
+byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *opts, void *stream, byo_run_stats *stats);
+
 /* PageRank, FP32, `iters` steps from 1/n: p'[v] = (1-d)/n + d * (sum over
  * u in N(v) of p[u]/deg(u) + D/n), D = mass on degree-0 vertices. */
 byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, float *d_rank, const byo_opts *opts,

@@ -266,6 +266,16 @@ def bc(g: Graph, src: int, opts=None, delta=None, sigma=None, depth=None, **kw):
     return delta[: g.n], sigma[: g.n], depth[: g.n], stt.as_dict()
 
 
+def kcore(g: Graph, opts=None, core=None, **kw):
+    """Coreness of every vertex (int32 device tensor) and stats."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    core = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if core is None else core
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_kcore(g.handle, _ptr(core), ctypes.byref(o), _stream(), ctypes.byref(stt)))
+    return core[: g.n], stt.as_dict()
+
+
 def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, opts=None, **kw) -> int:
     """edgeMap(G, U, F) into `out`; returns the variant that ran."""
     o = _opts(opts, kw)

@@ -185,6 +185,7 @@ struct byo_workspace {
   double *bc_sigma = nullptr;          // [n] path counts when the caller passes none
   int32_t *bc_depth = nullptr;         // [n] depths when the caller passes none
   int32_t *bc_order = nullptr;         // [n] vertices level by level
+  int32_t *kc_dcur = nullptr;          // [n] k-core: remaining degrees
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
 };
