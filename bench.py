@@ -239,14 +239,15 @@ PAPER_RMAT_ABCD = (0.5, 0.1, 0.1, 0.3)   # the paper's rMAT generator setting (S
 def api_ablation(byo, gen, args):
     """Container-API ablation (Section 4.2, Table api-components-avg): the same
     CSR container and host-driven level loop, with optional container functions
-    left out. BFS (total over the sources), connectivity and PageRank
-    (args.pr_iters steps) per graph and configuration, median of 3 timed runs
-    after one untimed run; slowdown = time / time with the full API. Summaries
-    per configuration over every (graph, algorithm) case: mean, 95th
-    percentile and maximum, as the table reports them."""
+    left out. BFS (total over the sources), connectivity, PageRank
+    (args.pr_iters steps), single-source betweenness and k-core per graph and
+    configuration, median of 3 timed runs after one untimed run; slowdown =
+    time / time with the full API. Summaries per configuration over every
+    (graph, algorithm) case: mean, 95th percentile and maximum, as the table
+    reports them."""
     configs = [(k, {"api_omit": v}) for k, v in sorted(byo.API_CONFIGS.items(), key=lambda kv: kv[1])]
     container_study(byo, gen, args, configs, "full", "container API (Table api-components-avg)",
-                    "slowdown over full API")
+                    "slowdown over full API", extra_algos=True)
 
 
 def compression_study(byo, gen, args):
@@ -257,7 +258,7 @@ def compression_study(byo, gen, args):
                     "byte-coded CSR against CSR", "slowdown over CSR")
 
 
-def container_study(byo, gen, args, configs, base_name, title, unit):
+def container_study(byo, gen, args, configs, base_name, title, unit, extra_algos=False):
     """Times BFS, connectivity and PageRank per graph and configuration (opts
     keyword sets); see api_ablation."""
     import torch
@@ -286,6 +287,11 @@ def container_study(byo, gen, args, configs, base_name, title, unit):
             "cc": lambda o: byo.cc(g, opts=o, label=label),
             "pagerank": lambda o: byo.pagerank(g, 0.85, args.pr_iters, opts=o, rank=rank),
         }
+        if extra_algos:
+            dl = torch.empty(n, dtype=torch.float64, device="cuda")
+            sg = torch.empty(n, dtype=torch.float64, device="cuda")
+            algos["bc"] = lambda o: byo.bc(g, srcs[0], opts=o, delta=dl, sigma=sg, depth=depth)
+            algos["kcore"] = lambda o: byo.kcore(g, opts=o, core=label)
         if any(kw.get("compressed") for _, kw in configs):
             g.cz_build()
             nbytes = ctypes.c_int64()
@@ -306,8 +312,8 @@ def container_study(byo, gen, args, configs, base_name, title, unit):
                     ts.append((time.perf_counter() - t) * 1e3)
                 cases.append({"graph": gname, "n": n, "m": m, "algo": aname, "config": cname,
                               "ms": round(float(np.median(ts)), 4)})
-            log(f"[study] {gname} {cname}: " + " ".join(f"{c['algo']}={c['ms']:.2f}ms" for c in cases[-3:]))
-        del g, depth, parent, label, rank
+            log(f"[study] {gname} {cname}: " + " ".join(f"{c['algo']}={c['ms']:.2f}ms" for c in cases[-len(algos):]))
+        del g, depth, parent, label, rank, algos
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
     base = {(c["graph"], c["algo"]): c["ms"] for c in cases if c["config"] == base_name}

@@ -466,6 +466,14 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
   BYO_TRY(ws_ensure_traversal(g));
   BYO_TRY(bc_buffers(g));
   byo_workspace &w = g->ws;
+  // Container-API ablation (Table api-components-avg): without degree() each
+  // level's frontier degrees are mapped (they size the cutoff and the
+  // edge-balanced passes); without num_edges() m is summed at every level;
+  // without a parallel map only the lane forms run. BC has no early exit.
+  const uint32_t omit = (uint32_t)o.api_omit;
+  const bool mapped = (omit & BYO_API_NO_DEGREE) != 0;
+  const int32_t *degs = g->deg;
+  if (mapped) BYO_TRY(api_degree_buffer(g, s, (int32_t **)&degs));
   const int64_t n = g->n, words = w.words;
   double *sigma = d_sigma ? d_sigma : w.bc_sigma;
   int32_t *depth = d_depth ? d_depth : w.bc_depth;
@@ -475,7 +483,7 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
   bc_src_bit_kernel<<<bc_grid(words, 256, 4096), 256, 0, s>>>(w.bits[0], words, (int32_t)src);
   BYO_HIP(hipGetLastError());
   int32_t src_deg = 0;
-  BYO_TRY(sync_read(s, g->deg + src, &src_deg, sizeof(src_deg)));
+  if (!mapped) BYO_TRY(sync_read(s, g->deg + src, &src_deg, sizeof(src_deg)));
 
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
@@ -485,8 +493,9 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
   // fixed PUSH_* / PULL_* variants pin the forward kernel and the backward
   // pass's kind (lane or wavefront-shared lists); otherwise pushes and the
   // backward pass are edge-balanced
-  const bool fixed = o.selector == BYO_SEL_FIXED;
-  const bool fixed_edges = fixed && (o.fixed_variant == BYO_V_PUSH_EDGE || o.fixed_variant == BYO_V_PUSH_BUCKET);
+  const bool fixed = o.selector == BYO_SEL_FIXED || (omit & BYO_API_NO_PAR_MAP);
+  const int fixed_variant = (omit & BYO_API_NO_PAR_MAP) ? BYO_V_PUSH_THREAD : o.fixed_variant;
+  const bool fixed_edges = fixed && (fixed_variant == BYO_V_PUSH_EDGE || fixed_variant == BYO_V_PUSH_BUCKET);
   int cur = 0;
   int32_t L = 0;
   while (true) {
@@ -494,20 +503,28 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
       if (stats) *stats = st;
       return fail(BYO_ELIMIT, "betweenness level cap reached");
     }
+    int64_t m_seen = g->m;
+    if (mapped) {
+      BYO_TRY(api_frontier_degrees(g, omit, w.bc_order + lo[L], nullptr, k, s, &degsum));
+      dsum[L] = degsum;
+      edges += degsum;
+    }
+    if (omit & BYO_API_NO_NUM_EDGES) BYO_TRY(api_num_edges(g, omit, degs, s, &m_seen));
     bool pull;
     bool wave = true, edges_push = !fixed || fixed_edges;
-    if (fixed) {
-      pull = o.fixed_variant == BYO_V_PULL_THREAD || o.fixed_variant == BYO_V_PULL_WAVE;
-      wave = o.fixed_variant != BYO_V_PUSH_THREAD && o.fixed_variant != BYO_V_PULL_THREAD;
+    const int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
+    if (fixed && !(omit & BYO_API_NO_PAR_MAP)) {
+      pull = fixed_variant == BYO_V_PULL_THREAD || fixed_variant == BYO_V_PULL_WAVE;
+      wave = fixed_variant != BYO_V_PUSH_THREAD && fixed_variant != BYO_V_PULL_THREAD;
     } else {
       // the sparse/dense cutoff: dense when |U| + sum deg(U) > m / divisor
-      const int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
-      pull = k + degsum > g->m / div;
+      pull = k + degsum > m_seen / div;
+      if (omit & BYO_API_NO_PAR_MAP) wave = false;
     }
     BcFwd a;
     a.off = g->off;
     a.nbr = g->nbr;
-    a.deg = g->deg;
+    a.deg = degs;  // (stale without degree(): the next level maps its own sum)
     a.in_ids = w.bc_order + lo[L];
     a.in_bits = w.bits[cur];
     a.k = k;
@@ -531,7 +548,7 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
       // the output bitmap is written by atomics: clear it first
       BYO_TRY(bitmap_clear(a.out_bits, words, s));
       if (edges_push) {
-        BYO_TRY(frontier_degree_scan(g, a.in_ids, k, w.scan, w.partial, w.partial_cap, s));
+        BYO_TRY(scan_degrees(degs, a.in_ids, k, w.scan, w.partial, w.partial_cap, s));
         bc_push_edges_kernel<<<bc_grid((degsum + BC_RUN - 1) / BC_RUN, BC_BLOCK, 16384), BC_BLOCK, 0, s>>>(
             a, w.scan);
         st.variant_count[BYO_V_PUSH_EDGE]++;
@@ -554,9 +571,9 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
     cnt.push_back((int64_t)c.count);
     dsum.push_back((int64_t)c.degsum);
     k = (int64_t)c.count;
-    degsum = (int64_t)c.degsum;
+    degsum = (int64_t)c.degsum;  // mapped again at the next level's start without degree()
     reached += k;
-    edges += degsum;
+    if (!mapped) edges += degsum;
     cur = 1 - cur;
   }
   // backward, deepest level first; the source (level 0) keeps delta = 0
@@ -565,11 +582,11 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
     const int32_t *ids = w.bc_order + lo[l];
     if (!fixed || fixed_edges) {
       // edge-balanced: sums into delta (still 0 on this level), then finished
-      BYO_TRY(frontier_degree_scan(g, ids, cnt[l], w.scan, w.partial, w.partial_cap, s));
+      BYO_TRY(scan_degrees(degs, ids, cnt[l], w.scan, w.partial, w.partial_cap, s));
       bc_back_edges_kernel<<<bc_grid((dsum[l] + BC_RUN - 1) / BC_RUN, BC_BLOCK, 16384), BC_BLOCK, 0, s>>>(
           g->off, g->nbr, ids, cnt[l], w.scan, depth, w.bc_coef, d_delta, l);
       bc_back_finish_kernel<<<bc_grid(cnt[l], 256, 16384), 256, 0, s>>>(ids, cnt[l], sigma, d_delta, w.bc_coef);
-    } else if (o.fixed_variant == BYO_V_PUSH_THREAD || o.fixed_variant == BYO_V_PULL_THREAD) {
+    } else if (fixed_variant == BYO_V_PUSH_THREAD || fixed_variant == BYO_V_PULL_THREAD) {
       bc_back_kernel<false><<<bc_grid(cnt[l], BC_BLOCK, 16384), BC_BLOCK, 0, s>>>(
           g->off, g->nbr, ids, cnt[l], depth, sigma, w.bc_coef, d_delta, l);
     } else {

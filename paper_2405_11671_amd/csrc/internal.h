@@ -323,6 +323,9 @@ byo_status fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
 byo_status fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 byo_status sync_read(hipStream_t s, const void *d_src, void *h_dst, size_t bytes);
 
+// the same over an explicit degree array
+byo_status scan_degrees(const int32_t *deg, const int32_t *ids, int64_t k, long long *scan, long long *partial,
+                        int64_t partial_cap, hipStream_t s);
 // exclusive scan of frontier degrees: scan[i] = sum_{j<i} deg(ids[j]); scan[k] = total
 byo_status frontier_degree_scan(const byo_graph *g, const int32_t *ids, int64_t k, long long *scan,
                                 long long *partial, int64_t partial_cap, hipStream_t s);

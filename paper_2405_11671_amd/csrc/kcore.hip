@@ -152,6 +152,40 @@ __global__ void __launch_bounds__(KC_BLOCK) kc_peel_kernel(const int64_t *__rest
   }
 }
 
+// Removal push, one lane per frontier vertex (a container without a parallel
+// map): the lane walks its whole list.
+__global__ void __launch_bounds__(KC_BLOCK) kc_peel_lane_kernel(const int64_t *__restrict__ off,
+                                                                const int32_t *__restrict__ nbr,
+                                                                const int32_t *__restrict__ deg,
+                                                                const int32_t *__restrict__ ids, int64_t kf, int32_t k,
+                                                                int32_t *dcur, const int32_t *core, int32_t *out,
+                                                                byo_counters *ctr, byo_counters *ctr_clear) {
+  unsigned long long degsum = 0;
+  for (int64_t i = (int64_t)blockIdx.x * KC_BLOCK + threadIdx.x; i - threadIdx.x < kf;
+       i += (int64_t)gridDim.x * KC_BLOCK) {
+    if (i < kf) {
+      const int32_t v = ids[i];
+      const int64_t end = off[v + 1];
+      for (int64_t e = off[v]; e < end; ++e) {
+        const int32_t u = nbr[e];
+        const bool joins = core[u] < 0 && atomicSub(&dcur[u], 1) == k + 1;
+        wave_append(joins, u, out, &ctr->count);
+        if (joins) degsum += (unsigned long long)deg[u];
+      }
+    }
+  }
+  const unsigned long long t = block_sum<unsigned long long, KC_BLOCK>(degsum);
+  if (threadIdx.x == 0) {
+    if (t) atomicAdd(&ctr->degsum, t);
+    if (blockIdx.x == 0 && ctr_clear) {
+      ctr_clear->count = 0;
+      ctr_clear->degsum = 0;
+      ctr_clear->aux0 = 0;
+      ctr_clear->aux1 = ULLONG_MAX;
+    }
+  }
+}
+
 __global__ void kc_reset_kernel(byo_counters *ctr) {
   if (threadIdx.x < BYO_COUNTER_SLOTS) {
     ctr[threadIdx.x].count = 0;
@@ -190,7 +224,18 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
   // remaining degrees, kept with the workspace
   if (!w.kc_dcur) BYO_HIP(hipMalloc(&w.kc_dcur, sizeof(int32_t) * (size_t)n));
   int32_t *dcur = w.kc_dcur;
-  kc_init_kernel<<<kc_grid(n, 256, 8192), 256, 0, s>>>(g->deg, n, dcur, d_core);
+  // Container-API ablation (Table api-components-avg): without degree() the
+  // run starts from every list counted by a map, and uses those counts where
+  // it needs degrees; without a parallel map a lane removes one vertex.
+  const uint32_t omit = (uint32_t)o.api_omit;
+  const bool par_map = !(omit & BYO_API_NO_PAR_MAP);
+  const int32_t *degs = g->deg;
+  if (omit & BYO_API_NO_DEGREE) {
+    int32_t *mdeg = nullptr;
+    BYO_TRY(api_map_degrees(g, omit, s, &mdeg));
+    degs = mdeg;
+  }
+  kc_init_kernel<<<kc_grid(n, 256, 8192), 256, 0, s>>>(degs, n, dcur, d_core);
   kc_reset_kernel<<<1, 64, 0, s>>>(w.ctr);
   BYO_HIP(hipGetLastError());
   const int64_t cap = o.max_levels > 0 ? o.max_levels : INT64_MAX;
@@ -218,7 +263,7 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
       if (remaining == 0) break;
       k = std::max<int64_t>(k + 1, (int64_t)c.aux1);
       kc_reset_kernel<<<1, 64, 0, s>>>(w.ctr);
-      kc_collect_kernel<<<kc_grid(n, KC_BLOCK, 4096), KC_BLOCK, 0, s>>>(dcur, d_core, g->deg, n, (int32_t)k,
+      kc_collect_kernel<<<kc_grid(n, KC_BLOCK, 4096), KC_BLOCK, 0, s>>>(dcur, d_core, degs, n, (int32_t)k,
                                                                          w.ids[cur], w.ctr + (slot % BYO_COUNTER_SLOTS));
       BYO_HIP(hipGetLastError());
       BYO_TRY(read(slot, &c));
@@ -232,17 +277,23 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
     }
     // remove the frontier at coreness k
     kc_mark_kernel<<<kc_grid(kf, 256, 8192), 256, 0, s>>>(w.ids[cur], kf, (int32_t)k, d_core);
-    BYO_TRY(frontier_degree_scan(g, w.ids[cur], kf, w.scan, w.partial, w.partial_cap, s));
     byo_counters *cs = w.ctr + (slot % BYO_COUNTER_SLOTS);
-    kc_peel_kernel<<<kc_grid((fdeg + KC_RUN - 1) / KC_RUN, KC_BLOCK, 16384), KC_BLOCK, 0, s>>>(
-        g->off, g->nbr, g->deg, w.ids[cur], kf, w.scan, (int32_t)k, dcur, d_core, w.ids[1 - cur], cs,
-        w.ctr + ((slot + 2) % BYO_COUNTER_SLOTS));
+    if (par_map) {
+      BYO_TRY(scan_degrees(degs, w.ids[cur], kf, w.scan, w.partial, w.partial_cap, s));
+      kc_peel_kernel<<<kc_grid((fdeg + KC_RUN - 1) / KC_RUN, KC_BLOCK, 16384), KC_BLOCK, 0, s>>>(
+          g->off, g->nbr, degs, w.ids[cur], kf, w.scan, (int32_t)k, dcur, d_core, w.ids[1 - cur], cs,
+          w.ctr + ((slot + 2) % BYO_COUNTER_SLOTS));
+    } else {
+      kc_peel_lane_kernel<<<kc_grid(kf, KC_BLOCK, 16384), KC_BLOCK, 0, s>>>(
+          g->off, g->nbr, degs, w.ids[cur], kf, (int32_t)k, dcur, d_core, w.ids[1 - cur], cs,
+          w.ctr + ((slot + 2) % BYO_COUNTER_SLOTS));
+    }
     BYO_HIP(hipGetLastError());
     byo_counters c;
     BYO_TRY(read(slot, &c));
     ++slot;
     ++rounds;
-    st.variant_count[BYO_V_PUSH_EDGE]++;
+    st.variant_count[par_map ? BYO_V_PUSH_EDGE : BYO_V_PUSH_THREAD]++;
     edges += fdeg;
     remaining -= kf;
     cur = 1 - cur;

@@ -171,15 +171,20 @@ __global__ void __launch_bounds__(CB_THREADS) deg_scan_write_kernel(const int32_
   if (blockIdx.x == 0 && threadIdx.x == 0) scan[k] = partial[nb];
 }
 
-byo_status frontier_degree_scan(const byo_graph *g, const int32_t *ids, int64_t k, long long *scan,
-                                long long *partial, int64_t partial_cap, hipStream_t s) {
+byo_status scan_degrees(const int32_t *deg, const int32_t *ids, int64_t k, long long *scan, long long *partial,
+                        int64_t partial_cap, hipStream_t s) {
   int64_t nb = std::max<int64_t>(1, (k + DS_TILE - 1) / DS_TILE);
   BYO_CHECK(nb + 1 <= partial_cap, BYO_EINVAL, "scan scratch too small");
-  deg_scan_reduce_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, g->deg, partial);
+  deg_scan_reduce_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, partial);
   scan_partials_kernel<<<1, CB_THREADS, 0, s>>>(partial, nb, nullptr);
-  deg_scan_write_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, g->deg, partial, nb, scan);
+  deg_scan_write_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, partial, nb, scan);
   BYO_HIP(hipGetLastError());
   return BYO_OK;
+}
+
+byo_status frontier_degree_scan(const byo_graph *g, const int32_t *ids, int64_t k, long long *scan,
+                                long long *partial, int64_t partial_cap, hipStream_t s) {
+  return scan_degrees(g->deg, ids, k, scan, partial, partial_cap, s);
 }
 
 __global__ void ids_range_check_kernel(const int32_t *__restrict__ ids, int64_t k, int64_t n,

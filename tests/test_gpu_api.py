@@ -150,3 +150,32 @@ def test_api_config_bypasses_tiled_and_graph_paths():
     r32, _ = byo.pagerank(g, 0.85, 20, api_omit=9, pr_blocked=1)
     r64 = og.pagerank(0.85, 20)
     assert np.max(np.abs(r32.cpu().numpy() - r64)) / np.max(np.abs(r64)) < PR_TOL
+
+
+@pytest.mark.parametrize("cfg,omit", CONFIGS, ids=CFG_IDS)
+@pytest.mark.parametrize("p", SUITE, ids=IDS)
+def test_bc_api_config(p, cfg, omit):
+    g, og = build(p)
+    for s in sources(og):
+        delta, sigma, depth, st = byo.bc(g, s, api_omit=omit)
+        ws, wd, wdist = og.bc(s)
+        assert np.array_equal(depth.cpu().numpy(), wdist), (p.name, cfg, s)
+        small = ws < 2.0 ** 53
+        assert np.array_equal(sigma.cpu().numpy()[small], ws[small])
+        scale = max(1.0, float(np.max(np.abs(wd), initial=0.0)))
+        assert np.max(np.abs(delta.cpu().numpy() - wd), initial=0.0) <= 1e-9 * scale
+        _, _, _, full = byo.bc(g, s)
+        assert st["edges"] == full["edges"]
+        if omit & byo.API_NO_PAR_MAP:
+            used = {k for k, c in st["variant_count"].items() if c}
+            assert used <= {"push_thread", "pull_thread"}, used
+
+
+@pytest.mark.parametrize("cfg,omit", CONFIGS, ids=CFG_IDS)
+@pytest.mark.parametrize("p", SUITE, ids=IDS)
+def test_kcore_api_config(p, cfg, omit):
+    g, og = build(p)
+    core, st = byo.kcore(g, api_omit=omit)
+    assert np.array_equal(core.cpu().numpy(), og.kcore()), (p.name, cfg)
+    if omit & byo.API_NO_PAR_MAP:
+        assert st["variant_count"]["push_edge"] == 0
