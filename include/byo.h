@@ -314,8 +314,9 @@ byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double *d_sigma, i
  * the coreness of v, the largest k such that v belongs to the k-core (the
  * maximal subgraph in which every vertex keeps at least k neighbours); 0 for
  * isolated vertices. Peeling: at each k, the alive vertices with remaining
- * degree <= k are removed in edge-balanced push sub-rounds until none is
- * left, k then jumping to the least remaining degree. d_core: device int32
+ * degree <= k are removed in push sub-rounds (edge-balanced when the
+ * frontier's degree sum is at least 2^15, else one vertex per lane) until
+ * none is left, k then jumping to the least remaining degree. d_core: device int32
  * [n]. Returns when done (it reads each sub-round's size back). BYO_ELIMIT
  * if max_levels sub-rounds do not finish. stats: levels = sub-rounds,
  * edges = sum of the removed vertices' degrees. */

@@ -300,6 +300,10 @@ __device__ __forceinline__ int64_t bc_last_le(const long long *__restrict__ scan
 }
 
 constexpr int BC_RUN = 16;  // consecutive edges per lane in the edge-balanced passes
+// below this degree sum a level takes the lane/wavefront forms: the
+// edge-balanced passes cost a degree scan (3 launches) per level, which
+// dominates on long chains of small levels (lattices)
+constexpr int64_t BC_EDGE_MIN = 1 << 15;
 
 // Edge-balanced push: the frontier's lists, concatenated (scan = exclusive
 // scan of their degrees, scan[k] = total), in runs of BC_RUN edges per lane.
@@ -492,7 +496,7 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
   int64_t k = 1, degsum = src_deg, reached = 1, edges = src_deg;
   // fixed PUSH_* / PULL_* variants pin the forward kernel and the backward
   // pass's kind (lane or wavefront-shared lists); otherwise pushes and the
-  // backward pass are edge-balanced
+  // backward pass are edge-balanced on levels with a large degree sum
   const bool fixed = o.selector == BYO_SEL_FIXED || (omit & BYO_API_NO_PAR_MAP);
   const int fixed_variant = (omit & BYO_API_NO_PAR_MAP) ? BYO_V_PUSH_THREAD : o.fixed_variant;
   const bool fixed_edges = fixed && (fixed_variant == BYO_V_PUSH_EDGE || fixed_variant == BYO_V_PUSH_BUCKET);
@@ -511,7 +515,7 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
     }
     if (omit & BYO_API_NO_NUM_EDGES) BYO_TRY(api_num_edges(g, omit, degs, s, &m_seen));
     bool pull;
-    bool wave = true, edges_push = !fixed || fixed_edges;
+    bool wave = true, edges_push = fixed_edges || (!fixed && degsum >= BC_EDGE_MIN);
     const int64_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
     if (fixed && !(omit & BYO_API_NO_PAR_MAP)) {
       pull = fixed_variant == BYO_V_PULL_THREAD || fixed_variant == BYO_V_PULL_WAVE;
@@ -580,7 +584,7 @@ extern "C" byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double 
   const int32_t deepest = (int32_t)lo.size() - 1;
   for (int32_t l = deepest; l >= 1; --l) {
     const int32_t *ids = w.bc_order + lo[l];
-    if (!fixed || fixed_edges) {
+    if (fixed_edges || (!fixed && dsum[l] >= BC_EDGE_MIN)) {
       // edge-balanced: sums into delta (still 0 on this level), then finished
       BYO_TRY(scan_degrees(degs, ids, cnt[l], w.scan, w.partial, w.partial_cap, s));
       bc_back_edges_kernel<<<bc_grid((dsum[l] + BC_RUN - 1) / BC_RUN, BC_BLOCK, 16384), BC_BLOCK, 0, s>>>(

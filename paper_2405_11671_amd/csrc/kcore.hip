@@ -9,9 +9,10 @@
 //    alive neighbour loses one remaining degree (atomic), and one that drops
 //    from k + 1 to k joins the next frontier; sub-rounds repeat at the same k
 //    until the frontier is empty.
-// The push is edge-balanced: runs of KC_RUN consecutive edges of the
-// frontier's concatenated lists per lane, so hubs (peeled late, in small
-// frontiers) spread over the grid.
+// The push is edge-balanced when the frontier's degree sum is large: runs of
+// KC_RUN consecutive edges of the frontier's concatenated lists per lane, so
+// hubs (peeled late, in small frontiers) spread over the grid; a frontier
+// with a small degree sum is removed one vertex per lane.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -24,6 +25,9 @@ namespace {
 
 constexpr int KC_BLOCK = 256;
 constexpr int KC_RUN = 16;
+// frontiers with a smaller degree sum take the lane kernel: the edge-balanced
+// one costs a degree scan (3 launches) per sub-round
+constexpr int64_t KC_EDGE_MIN = 1 << 15;
 
 // remaining degree = degree, coreness unknown (-1: alive)
 __global__ void kc_init_kernel(const int32_t *__restrict__ deg, int64_t n, int32_t *dcur, int32_t *core) {
@@ -278,7 +282,8 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
     // remove the frontier at coreness k
     kc_mark_kernel<<<kc_grid(kf, 256, 8192), 256, 0, s>>>(w.ids[cur], kf, (int32_t)k, d_core);
     byo_counters *cs = w.ctr + (slot % BYO_COUNTER_SLOTS);
-    if (par_map) {
+    const bool balanced = par_map && fdeg >= KC_EDGE_MIN;
+    if (balanced) {
       BYO_TRY(scan_degrees(degs, w.ids[cur], kf, w.scan, w.partial, w.partial_cap, s));
       kc_peel_kernel<<<kc_grid((fdeg + KC_RUN - 1) / KC_RUN, KC_BLOCK, 16384), KC_BLOCK, 0, s>>>(
           g->off, g->nbr, degs, w.ids[cur], kf, w.scan, (int32_t)k, dcur, d_core, w.ids[1 - cur], cs,
@@ -293,7 +298,7 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
     BYO_TRY(read(slot, &c));
     ++slot;
     ++rounds;
-    st.variant_count[par_map ? BYO_V_PUSH_EDGE : BYO_V_PUSH_THREAD]++;
+    st.variant_count[balanced ? BYO_V_PUSH_EDGE : BYO_V_PUSH_THREAD]++;
     edges += fdeg;
     remaining -= kf;
     cur = 1 - cur;

@@ -179,3 +179,4 @@ def test_kcore_api_config(p, cfg, omit):
     assert np.array_equal(core.cpu().numpy(), og.kcore()), (p.name, cfg)
     if omit & byo.API_NO_PAR_MAP:
         assert st["variant_count"]["push_edge"] == 0
+    assert sum(st["variant_count"].values()) == st["levels"]
