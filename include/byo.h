@@ -315,7 +315,8 @@ byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double *d_sigma, i
  * maximal subgraph in which every vertex keeps at least k neighbours); 0 for
  * isolated vertices. Peeling: at each k, the alive vertices with remaining
  * degree <= k are removed in push sub-rounds (edge-balanced when the
- * frontier's degree sum is at least 2^15, else one vertex per lane) until
+ * frontier's degree sum is at least 2^15 or a list is longer than 16, else
+ * one vertex per lane) until
  * none is left, k then jumping to the least remaining degree. d_core: device int32
  * [n]. Returns when done (it reads each sub-round's size back). BYO_ELIMIT
  * if max_levels sub-rounds do not finish. stats: levels = sub-rounds,

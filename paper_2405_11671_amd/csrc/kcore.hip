@@ -12,7 +12,7 @@
 // The push is edge-balanced when the frontier's degree sum is large: runs of
 // KC_RUN consecutive edges of the frontier's concatenated lists per lane, so
 // hubs (peeled late, in small frontiers) spread over the grid; a frontier
-// with a small degree sum is removed one vertex per lane.
+// with a small degree sum and no long list is removed one vertex per lane.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -25,9 +25,24 @@ namespace {
 
 constexpr int KC_BLOCK = 256;
 constexpr int KC_RUN = 16;
-// frontiers with a smaller degree sum take the lane kernel: the edge-balanced
-// one costs a degree scan (3 launches) per sub-round
+// frontiers with a smaller degree sum take the lane kernel (the edge-balanced
+// one costs a degree scan, 3 launches, per sub-round)
 constexpr int64_t KC_EDGE_MIN = 1 << 15;
+constexpr int64_t KC_LANE_MAX = 16;  // ... and no vertex of more neighbours than this (each decrement waits on an atomic)
+
+// block maximum of v into *dst (atomic); every thread calls it
+__device__ __forceinline__ void kc_block_max(unsigned long long v, unsigned long long *dst) {
+  v = wave_max(v);
+  __shared__ unsigned long long wm[KC_BLOCK / BYO_WAVE];
+  __syncthreads();
+  if (lane_id() == 0) wm[threadIdx.x / BYO_WAVE] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = wm[0];
+    for (int i = 1; i < KC_BLOCK / BYO_WAVE; ++i) b = wm[i] > b ? wm[i] : b;
+    if (b) atomicMax(dst, b);
+  }
+}
 
 // remaining degree = degree, coreness unknown (-1: alive)
 __global__ void kc_init_kernel(const int32_t *__restrict__ deg, int64_t n, int32_t *dcur, int32_t *core) {
@@ -73,15 +88,19 @@ __global__ void __launch_bounds__(KC_BLOCK) kc_collect_kernel(const int32_t *__r
                                                               const int32_t *__restrict__ core,
                                                               const int32_t *__restrict__ deg, int64_t n, int32_t k,
                                                               int32_t *out, byo_counters *ctr) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, dmax = 0;
   for (int64_t base = (int64_t)blockIdx.x * KC_BLOCK; base < n; base += (int64_t)gridDim.x * KC_BLOCK) {
     const int64_t v = base + threadIdx.x;
     const bool take = v < n && core[v] < 0 && dcur[v] <= k;
     wave_append(take, (int32_t)v, out, &ctr->count);
-    if (take) degsum += (unsigned long long)deg[v];
+    if (take) {
+      degsum += (unsigned long long)deg[v];
+      dmax = (unsigned long long)deg[v] > dmax ? (unsigned long long)deg[v] : dmax;
+    }
   }
   const unsigned long long t = block_sum<unsigned long long, KC_BLOCK>(degsum);
   if (threadIdx.x == 0 && t) atomicAdd(&ctr->degsum, t);
+  kc_block_max(dmax, &ctr->aux0);
 }
 
 // coreness k for the frontier (before any list is scanned)
@@ -112,7 +131,7 @@ __global__ void __launch_bounds__(KC_BLOCK) kc_peel_kernel(const int64_t *__rest
                                                            const long long *__restrict__ scan, int32_t k,
                                                            int32_t *dcur, const int32_t *core, int32_t *out,
                                                            byo_counters *ctr, byo_counters *ctr_clear) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, dmax = 0;
   const long long total = scan[kf];
   const int64_t nthreads = (int64_t)gridDim.x * KC_BLOCK;
   // uniform trip count per workgroup: the emission ballots see every lane
@@ -141,10 +160,14 @@ __global__ void __launch_bounds__(KC_BLOCK) kc_peel_kernel(const int64_t *__rest
         if (core[u] < 0) joins = atomicSub(&dcur[u], 1) == k + 1;
       }
       wave_append(joins, u, out, &ctr->count);
-      if (joins) degsum += (unsigned long long)deg[u];
+      if (joins) {
+        degsum += (unsigned long long)deg[u];
+        dmax = (unsigned long long)deg[u] > dmax ? (unsigned long long)deg[u] : dmax;
+      }
     }
   }
   const unsigned long long t = block_sum<unsigned long long, KC_BLOCK>(degsum);
+  kc_block_max(dmax, &ctr->aux0);
   if (threadIdx.x == 0) {
     if (t) atomicAdd(&ctr->degsum, t);
     if (blockIdx.x == 0 && ctr_clear) {
@@ -164,7 +187,7 @@ __global__ void __launch_bounds__(KC_BLOCK) kc_peel_lane_kernel(const int64_t *_
                                                                 const int32_t *__restrict__ ids, int64_t kf, int32_t k,
                                                                 int32_t *dcur, const int32_t *core, int32_t *out,
                                                                 byo_counters *ctr, byo_counters *ctr_clear) {
-  unsigned long long degsum = 0;
+  unsigned long long degsum = 0, dmax = 0;
   for (int64_t i = (int64_t)blockIdx.x * KC_BLOCK + threadIdx.x; i - threadIdx.x < kf;
        i += (int64_t)gridDim.x * KC_BLOCK) {
     if (i < kf) {
@@ -174,11 +197,15 @@ __global__ void __launch_bounds__(KC_BLOCK) kc_peel_lane_kernel(const int64_t *_
         const int32_t u = nbr[e];
         const bool joins = core[u] < 0 && atomicSub(&dcur[u], 1) == k + 1;
         wave_append(joins, u, out, &ctr->count);
-        if (joins) degsum += (unsigned long long)deg[u];
+        if (joins) {
+          degsum += (unsigned long long)deg[u];
+          dmax = (unsigned long long)deg[u] > dmax ? (unsigned long long)deg[u] : dmax;
+        }
       }
     }
   }
   const unsigned long long t = block_sum<unsigned long long, KC_BLOCK>(degsum);
+  kc_block_max(dmax, &ctr->aux0);
   if (threadIdx.x == 0) {
     if (t) atomicAdd(&ctr->degsum, t);
     if (blockIdx.x == 0 && ctr_clear) {
@@ -243,7 +270,7 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
   kc_reset_kernel<<<1, 64, 0, s>>>(w.ctr);
   BYO_HIP(hipGetLastError());
   const int64_t cap = o.max_levels > 0 ? o.max_levels : INT64_MAX;
-  int64_t remaining = n, k = -1, kf = 0, fdeg = 0, edges = 0;
+  int64_t remaining = n, k = -1, kf = 0, fdeg = 0, fmax = 0, edges = 0;
   int64_t slot = 0;  // counter slot of the next kernel that emits
   int cur = 0;
   int32_t rounds = 0;
@@ -274,6 +301,7 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
       ++slot;
       kf = (int64_t)c.count;
       fdeg = (int64_t)c.degsum;
+      fmax = (int64_t)c.aux0;
     }
     if (rounds >= cap) {
       if (stats) *stats = st;
@@ -282,7 +310,7 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
     // remove the frontier at coreness k
     kc_mark_kernel<<<kc_grid(kf, 256, 8192), 256, 0, s>>>(w.ids[cur], kf, (int32_t)k, d_core);
     byo_counters *cs = w.ctr + (slot % BYO_COUNTER_SLOTS);
-    const bool balanced = par_map && fdeg >= KC_EDGE_MIN;
+    const bool balanced = par_map && (fdeg >= KC_EDGE_MIN || fmax > KC_LANE_MAX);
     if (balanced) {
       BYO_TRY(scan_degrees(degs, w.ids[cur], kf, w.scan, w.partial, w.partial_cap, s));
       kc_peel_kernel<<<kc_grid((fdeg + KC_RUN - 1) / KC_RUN, KC_BLOCK, 16384), KC_BLOCK, 0, s>>>(
@@ -304,6 +332,7 @@ extern "C" byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *o
     cur = 1 - cur;
     kf = (int64_t)c.count;
     fdeg = (int64_t)c.degsum;
+    fmax = (int64_t)c.aux0;
   }
   st.levels = rounds;
   st.reached = n;
