@@ -67,6 +67,8 @@ def _load():
         lib.oracle_bc_definition.restype = ctypes.c_int
         lib.oracle_bc.argtypes = [vp, i64, dblp, dblp, i32p]
         lib.oracle_bc.restype = ctypes.c_int
+        lib.oracle_mis.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint8)]
+        lib.oracle_mis.restype = ctypes.c_int
         lib.oracle_kcore_definition.argtypes = [vp, i32p]
         lib.oracle_kcore_definition.restype = ctypes.c_int
         lib.oracle_kcore.argtypes = [vp, i32p]
@@ -170,6 +172,15 @@ class Graph:
         if _load().oracle_bc_definition(self._h, int(src), _p(delta, ctypes.c_double)) != 0:
             raise ValueError("oracle_bc_definition failed")
         return delta[: self.n]
+
+    def mis(self, prio) -> np.ndarray:
+        """Greedy maximal independent set in (prio, id) order: uint8 membership."""
+        prio = np.ascontiguousarray(prio, np.uint64)
+        assert prio.shape[0] >= self.n
+        out = np.empty(max(self.n, 1), np.uint8)
+        if _load().oracle_mis(self._h, _p(prio, ctypes.c_uint64), _p(out, ctypes.c_uint8)) != 0:
+            raise MemoryError("oracle_mis failed")
+        return out[: self.n]
 
     def kcore(self) -> np.ndarray:
         """Coreness of every vertex by bucketed peeling."""

@@ -27,6 +27,9 @@
  *     sigma_st counts shortest s-t paths and sigma_st(v) those through v. Two
  *     forms: the definition summed pair by pair (tiny graphs, to pin the
  *     other), and Brandes' recurrence over the BFS levels.
+ *   - MIS: the greedy maximal independent set in a given priority order
+ *     (lower priority value first, ties by vertex ID): scan the vertices in
+ *     that order and take each one none of whose neighbours was taken.
  *   - k-core: the coreness of every vertex, the largest k such that the vertex
  *     belongs to the k-core (the maximal subgraph whose vertices all keep at
  *     least k neighbours in it). Two forms: the definition, one deletion
@@ -408,5 +411,31 @@ int oracle_kcore(const oracle_graph *g, int32_t *core) {
     if (b > 0) --b;            /* a neighbour may now sit one bucket lower */
   }
   free(deg); free(head); free(next); free(prev); free(gone);
+  return 0;
+}
+
+/* Greedy maximal independent set in priority order: the vertices sorted by
+ * (prio, id) ascending are visited in turn, and a vertex joins the set when
+ * no neighbour has joined before it. in_set[v] = 1 if v joined, else 0. */
+static const uint64_t *g_mis_prio;
+static int cmp_mis(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  if (g_mis_prio[x] != g_mis_prio[y]) return g_mis_prio[x] < g_mis_prio[y] ? -1 : 1;
+  return x < y ? -1 : (x > y);
+}
+int oracle_mis(const oracle_graph *g, const uint64_t *prio, uint8_t *in_set) {
+  int64_t n = g->n;
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!order) return -2;
+  for (int64_t v = 0; v < n; ++v) { order[v] = (int32_t)v; in_set[v] = 0; }
+  g_mis_prio = prio;
+  qsort(order, (size_t)n, sizeof(int32_t), cmp_mis);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t v = order[i];
+    int taken = 0;
+    for (int64_t j = 0; j < g->len[v] && !taken; ++j) taken = in_set[g->nb[v][j]];
+    in_set[v] = taken ? 0 : 1;
+  }
+  free(order);
   return 0;
 }

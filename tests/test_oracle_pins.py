@@ -362,6 +362,52 @@ def test_bc_closed_forms():
     assert delta.tolist() == [0, 1, 0, 0, 0] and sigma.tolist() == [1, 1, 1, 0, 0]
 
 
+# ---------------------------------------------------------------- maximal independent set
+
+def brute_greedy_mis(n, a, b, prio):
+    """Greedy MIS with plain Python sets, vertices in (prio, id) order."""
+    E = brute.simple_edges(n, a, b)
+    adj = {v: set() for v in range(n)}
+    for u, v in E:
+        adj[u].add(v)
+        adj[v].add(u)
+    taken = set()
+    for v in sorted(range(n), key=lambda x: (int(prio[x]), x)):
+        if not adj[v] & taken:
+            taken.add(v)
+    return [1 if v in taken else 0 for v in range(n)]
+
+
+@settings(max_examples=80, deadline=None)
+@given(tiny_graphs, st.integers(0, 2 ** 32))
+def test_mis_matches_brute_force_and_is_maximal_independent(case, seed):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    prio = np.random.default_rng(seed).integers(0, 5, n).astype(np.uint64)   # many ties: id decides
+    got = g.mis(prio)
+    assert got.tolist() == brute_greedy_mis(n, a, b, prio)
+    for v in range(n):
+        nb = g.neighbors(v)
+        if got[v]:
+            assert not got[nb].any()            # independent
+        else:
+            assert got[nb].any()                # maximal
+
+
+def test_mis_closed_forms():
+    def run(n, pairs, prio):
+        return G(n, pairs)[0].mis(np.asarray(prio, np.uint64)).tolist()
+    path = [(i, i + 1) for i in range(6)]
+    assert run(7, path, range(7)) == [1, 0, 1, 0, 1, 0, 1]                  # in id order: every other vertex
+    assert run(7, path, [1, 0, 1, 0, 1, 0, 1]) == [0, 1, 0, 1, 0, 1, 0]    # odd vertices first
+    star = [(0, i) for i in range(1, 6)]
+    assert run(6, star, [0, 1, 1, 1, 1, 1]) == [1, 0, 0, 0, 0, 0]          # centre first
+    assert run(6, star, [9, 1, 1, 1, 1, 1]) == [0, 1, 1, 1, 1, 1]          # leaves first
+    k5 = [(u, v) for u in range(5) for v in range(u + 1, 5)]
+    assert run(5, k5, [3, 2, 0, 4, 1]) == [0, 0, 1, 0, 0]                  # the earliest vertex alone
+    assert run(4, [], [0, 0, 0, 0]) == [1, 1, 1, 1]                          # no edges: everything
+
+
 # ---------------------------------------------------------------- k-core
 
 def brute_kcore(n, a, b):
