@@ -182,6 +182,24 @@ def kcore_workload(byo, g):
     return {"ms": round(float(np.median(ts)), 3), "sub_rounds": st["levels"], "max_core": int(core.max().item())}
 
 
+def mis_workload(byo, g):
+    """Greedy maximal independent set of the benchmark graph in a seeded random
+    priority order: median of 3 runs (ms), rounds, and the set's size."""
+    import torch
+    prio = torch.from_numpy(np.random.default_rng(3).integers(0, 2 ** 63, g.n, dtype=np.uint64).view(np.int64))
+    prio = prio.to("cuda")
+    out = torch.empty(g.n, dtype=torch.uint8, device="cuda")
+    byo.mis(g, prio, in_set=out)
+    ts, st = [], None
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = byo.mis(g, prio, in_set=out)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    return {"ms": round(float(np.median(ts)), 3), "rounds": st["levels"], "size": int(out.sum().item())}
+
+
 def batch_workload(byo, gen, count=64):
     """64 Erdos-Renyi graphs (n log-uniform in [2^10, 2^18], average degree in
     [4, 32]), BFS from the first non-isolated vertex of each: 64 separate
@@ -365,7 +383,7 @@ def parse():
                     help="compare the byte-coded CSR with the CSR instead of the benchmark step")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-bc", action="store_true", help="skip the betweenness and k-core detail")
+    ap.add_argument("--no-bc", action="store_true", help="skip the betweenness, k-core and MIS detail")
     ap.add_argument("--grid-side", type=int, default=4096)
     ap.add_argument("--no-tiles", action="store_true",
                     help="PageRank and multi-source BFS over the CSR instead of the tile layout")
@@ -503,6 +521,7 @@ def main():
     pr_bytes = 4 * m + 16 * n + 8          # per step: neighbours, offsets, contrib read + write, rank write
     bc = None if args.no_bc else bc_workload(byo, g, srcs[:4])
     kcore = None if args.no_bc else kcore_workload(byo, g)
+    mis = None if args.no_bc else mis_workload(byo, g)
     grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     batch = None if args.no_batch else batch_workload(byo, gen)
     detail = {
@@ -522,6 +541,7 @@ def main():
         "kernel_ms": {f: round(v[1], 3) for f, v in kt_all.items() if v[0]},
         "bc": bc,
         "kcore": kcore,
+        "mis": mis,
         "grid": grid,
         "batch64": batch,
     }

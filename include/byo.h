@@ -323,6 +323,19 @@ byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double *d_sigma, i
  * edges = sum of the removed vertices' degrees. */
 byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *opts, void *stream, byo_run_stats *stats);
 
+/* Maximal independent set (Table algs-list, covering problems): the greedy
+ * MIS in priority order, the vertices taken in ascending (d_prio[v], v) order,
+ * each joining unless a neighbour joined before it. The caller supplies the
+ * order (e.g. seeded random 64-bit priorities), so the result is unique for
+ * it. Rounds: an undecided vertex is out once an earlier neighbour is in, in
+ * once every earlier neighbour is out. d_prio: device uint64 [n];
+ * d_in_set: device uint8 [n], 1 = in the set. selector = BYO_SEL_FIXED with
+ * a *_THREAD variant scans every list by one lane, else lists longer than 32
+ * are shared by the wavefront. Returns when done; BYO_ELIMIT if max_levels
+ * rounds do not finish. stats: levels = rounds. */
+byo_status byo_mis(byo_graph *g, const uint64_t *d_prio, uint8_t *d_in_set, const byo_opts *opts, void *stream,
+                   byo_run_stats *stats);
+
 /* PageRank, FP32, `iters` steps from 1/n: p'[v] = (1-d)/n + d * (sum over
  * u in N(v) of p[u]/deg(u) + D/n), D = mass on degree-0 vertices. */
 byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, float *d_rank, const byo_opts *opts,

@@ -276,6 +276,21 @@ def kcore(g: Graph, opts=None, core=None, **kw):
     return core[: g.n], stt.as_dict()
 
 
+def mis(g: Graph, prio, opts=None, in_set=None, **kw):
+    """Greedy maximal independent set in (prio, id) order: (uint8 device tensor, stats).
+    prio: uint64 priorities, a device tensor (int64 dtype holding the bits) or a numpy array."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    if isinstance(prio, np.ndarray):
+        prio = torch.from_numpy(np.ascontiguousarray(prio, np.uint64).view(np.int64)).to("cuda")
+    assert prio.numel() >= g.n and prio.element_size() == 8
+    in_set = torch.empty(max(g.n, 1), dtype=torch.uint8, device="cuda") if in_set is None else in_set
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_mis(g.handle, _ptr(prio), _ptr(in_set), ctypes.byref(o), _stream(),
+                                   ctypes.byref(stt)))
+    return in_set[: g.n], stt.as_dict()
+
+
 def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, opts=None, **kw) -> int:
     """edgeMap(G, U, F) into `out`; returns the variant that ran."""
     o = _opts(opts, kw)

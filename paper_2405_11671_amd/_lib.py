@@ -120,6 +120,7 @@ SIGNATURES = {
     "byo_graph_stats": (st, [vp, i64p, i64p, dblp, dblp]),
     "byo_bc": (st, [vp, i64, vp, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_kcore": (st, [vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
+    "byo_mis": (st, [vp, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_cz_build": (st, [vp, vp]),
     "byo_cz_bytes": (st, [vp, i64p]),
     "byo_cz_copy": (st, [vp, vp, vp]),
