@@ -69,6 +69,8 @@ def _load():
         lib.oracle_bc.restype = ctypes.c_int
         lib.oracle_mis.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_mis.restype = ctypes.c_int
+        lib.oracle_coloring.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32p]
+        lib.oracle_coloring.restype = ctypes.c_int
         lib.oracle_kcore_definition.argtypes = [vp, i32p]
         lib.oracle_kcore_definition.restype = ctypes.c_int
         lib.oracle_kcore.argtypes = [vp, i32p]
@@ -180,6 +182,15 @@ class Graph:
         out = np.empty(max(self.n, 1), np.uint8)
         if _load().oracle_mis(self._h, _p(prio, ctypes.c_uint64), _p(out, ctypes.c_uint8)) != 0:
             raise MemoryError("oracle_mis failed")
+        return out[: self.n]
+
+    def coloring(self, prio) -> np.ndarray:
+        """Greedy colouring in (prio, id) order: int32 colours from 0."""
+        prio = np.ascontiguousarray(prio, np.uint64)
+        assert prio.shape[0] >= self.n
+        out = np.empty(max(self.n, 1), np.int32)
+        if _load().oracle_coloring(self._h, _p(prio, ctypes.c_uint64), _p(out, ctypes.c_int32)) != 0:
+            raise MemoryError("oracle_coloring failed")
         return out[: self.n]
 
     def kcore(self) -> np.ndarray:

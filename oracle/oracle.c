@@ -30,6 +30,8 @@
  *   - MIS: the greedy maximal independent set in a given priority order
  *     (lower priority value first, ties by vertex ID): scan the vertices in
  *     that order and take each one none of whose neighbours was taken.
+ *   - Colouring: the greedy colouring in the same kind of priority order: each
+ *     vertex in turn takes the smallest colour no earlier neighbour holds.
  *   - k-core: the coreness of every vertex, the largest k such that the vertex
  *     belongs to the k-core (the maximal subgraph whose vertices all keep at
  *     least k neighbours in it). Two forms: the definition, one deletion
@@ -437,5 +439,33 @@ int oracle_mis(const oracle_graph *g, const uint64_t *prio, uint8_t *in_set) {
     in_set[v] = taken ? 0 : 1;
   }
   free(order);
+  return 0;
+}
+
+/* Greedy colouring in priority order: vertices sorted by (prio, id) ascending
+ * take, in turn, the smallest colour (0, 1, ...) that no neighbour coloured
+ * before them holds. color[v] >= 0. */
+int oracle_coloring(const oracle_graph *g, const uint64_t *prio, int32_t *color) {
+  int64_t n = g->n, maxd = 0;
+  for (int64_t v = 0; v < n; ++v) maxd = g->len[v] > maxd ? g->len[v] : maxd;
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *seen = (int64_t *)malloc(sizeof(int64_t) * (size_t)(maxd + 2));
+  if (!order || !seen) { free(order); free(seen); return -2; }
+  for (int64_t v = 0; v < n; ++v) { order[v] = (int32_t)v; color[v] = -1; }
+  for (int64_t c = 0; c < maxd + 2; ++c) seen[c] = -1;
+  g_mis_prio = prio;
+  qsort(order, (size_t)n, sizeof(int32_t), cmp_mis);
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t v = order[i];
+    for (int64_t j = 0; j < g->len[v]; ++j) {
+      int32_t c = color[g->nb[v][j]];
+      if (c >= 0) seen[c] = v;   /* colour c is taken around v */
+    }
+    int32_t c = 0;
+    while (seen[c] == v) ++c;
+    color[v] = c;
+  }
+  free(order);
+  free(seen);
   return 0;
 }

@@ -408,6 +408,53 @@ def test_mis_closed_forms():
     assert run(4, [], [0, 0, 0, 0]) == [1, 1, 1, 1]                          # no edges: everything
 
 
+# ---------------------------------------------------------------- colouring
+
+def brute_greedy_coloring(n, a, b, prio):
+    E = brute.simple_edges(n, a, b)
+    adj = {v: set() for v in range(n)}
+    for u, v in E:
+        adj[u].add(v)
+        adj[v].add(u)
+    color = {}
+    for v in sorted(range(n), key=lambda x: (int(prio[x]), x)):
+        used = {color[u] for u in adj[v] if u in color}
+        c = 0
+        while c in used:
+            c += 1
+        color[v] = c
+    return [color[v] for v in range(n)]
+
+
+@settings(max_examples=80, deadline=None)
+@given(tiny_graphs, st.integers(0, 2 ** 32))
+def test_coloring_matches_brute_force_and_is_proper(case, seed):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    prio = np.random.default_rng(seed).integers(0, 4, n).astype(np.uint64)
+    got = g.coloring(prio)
+    assert got.tolist() == brute_greedy_coloring(n, a, b, prio)
+    for v in range(n):
+        nb = g.neighbors(v)
+        assert not np.any(got[nb] == got[v])            # proper
+        assert got[v] <= g.degree(v)                      # at most degree + 1 colours
+
+
+def test_coloring_closed_forms():
+    def run(n, pairs, prio):
+        return G(n, pairs)[0].coloring(np.asarray(prio, np.uint64)).tolist()
+    k5 = [(u, v) for u in range(5) for v in range(u + 1, 5)]
+    assert run(5, k5, [3, 2, 0, 4, 1]) == [3, 2, 0, 4, 1]                  # K5: colour = rank in the order
+    path = [(i, i + 1) for i in range(6)]
+    assert run(7, path, range(7)) == [0, 1, 0, 1, 0, 1, 0]                  # bipartite in id order
+    # an order that forces a third colour on a path: v0, v3 take 0, v1 takes 1, v2 (beside 1 and 0) takes 2
+    assert run(4, [(0, 1), (1, 2), (2, 3)], [0, 2, 3, 1]) == [0, 1, 2, 0]
+    star = [(0, i) for i in range(1, 6)]
+    assert run(6, star, [9, 1, 1, 1, 1, 1]) == [1, 0, 0, 0, 0, 0]          # leaves first, centre takes 1
+    cyc = [(i, (i + 1) % 5) for i in range(5)]
+    assert run(5, cyc, range(5)) == [0, 1, 0, 1, 2]                         # odd cycle needs 3
+
+
 # ---------------------------------------------------------------- k-core
 
 def brute_kcore(n, a, b):
