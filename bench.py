@@ -183,8 +183,9 @@ def kcore_workload(byo, g):
 
 
 def mis_workload(byo, g):
-    """Greedy maximal independent set of the benchmark graph in a seeded random
-    priority order: median of 3 runs (ms), rounds, and the set's size."""
+    """Greedy maximal independent set and greedy colouring of the benchmark
+    graph in one seeded random priority order: median of 3 runs (ms), rounds,
+    the set's size and the number of colours."""
     import torch
     prio = torch.from_numpy(np.random.default_rng(3).integers(0, 2 ** 63, g.n, dtype=np.uint64).view(np.int64))
     prio = prio.to("cuda")
@@ -197,7 +198,20 @@ def mis_workload(byo, g):
         _, st = byo.mis(g, prio, in_set=out)
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t) * 1e3)
-    return {"ms": round(float(np.median(ts)), 3), "rounds": st["levels"], "size": int(out.sum().item())}
+    res = {"ms": round(float(np.median(ts)), 3), "rounds": st["levels"], "size": int(out.sum().item())}
+    # greedy colouring in the same order
+    color = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    byo.coloring(g, prio, color=color)
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = byo.coloring(g, prio, color=color)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    res.update({"coloring_ms": round(float(np.median(ts)), 3), "coloring_rounds": st["levels"],
+                "colours": int(color.max().item()) + 1})
+    return res
 
 
 def batch_workload(byo, gen, count=64):

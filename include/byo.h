@@ -336,6 +336,16 @@ byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *opts, void *
 byo_status byo_mis(byo_graph *g, const uint64_t *d_prio, uint8_t *d_in_set, const byo_opts *opts, void *stream,
                    byo_run_stats *stats);
 
+/* Graph colouring (Table algs-list, covering problems): the greedy colouring
+ * in priority order, the vertices taken in ascending (d_prio[v], v) order,
+ * each taking the smallest colour (0, 1, ...) no earlier neighbour holds;
+ * unique for the order. Rounds: an uncoloured vertex whose earlier neighbours
+ * are all coloured takes the least colour missing among them. d_prio: device
+ * uint64 [n]; d_color: device int32 [n]. Variants and limits as byo_mis.
+ * stats: levels = rounds. */
+byo_status byo_coloring(byo_graph *g, const uint64_t *d_prio, int32_t *d_color, const byo_opts *opts, void *stream,
+                        byo_run_stats *stats);
+
 /* PageRank, FP32, `iters` steps from 1/n: p'[v] = (1-d)/n + d * (sum over
  * u in N(v) of p[u]/deg(u) + D/n), D = mass on degree-0 vertices. */
 byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, float *d_rank, const byo_opts *opts,

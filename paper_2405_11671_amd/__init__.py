@@ -291,6 +291,20 @@ def mis(g: Graph, prio, opts=None, in_set=None, **kw):
     return in_set[: g.n], stt.as_dict()
 
 
+def coloring(g: Graph, prio, opts=None, color=None, **kw):
+    """Greedy colouring in (prio, id) order: (int32 device tensor, stats). prio as for mis()."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    if isinstance(prio, np.ndarray):
+        prio = torch.from_numpy(np.ascontiguousarray(prio, np.uint64).view(np.int64)).to("cuda")
+    assert prio.numel() >= g.n and prio.element_size() == 8
+    color = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if color is None else color
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_coloring(g.handle, _ptr(prio), _ptr(color), ctypes.byref(o), _stream(),
+                                        ctypes.byref(stt)))
+    return color[: g.n], stt.as_dict()
+
+
 def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, opts=None, **kw) -> int:
     """edgeMap(G, U, F) into `out`; returns the variant that ran."""
     o = _opts(opts, kw)
