@@ -71,6 +71,8 @@ def _load():
         lib.oracle_mis.restype = ctypes.c_int
         lib.oracle_coloring.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32p]
         lib.oracle_coloring.restype = ctypes.c_int
+        lib.oracle_densest.argtypes = [vp, ctypes.c_double, i64p, i64p, ctypes.POINTER(ctypes.c_uint8)]
+        lib.oracle_densest.restype = i64
         lib.oracle_kcore_definition.argtypes = [vp, i32p]
         lib.oracle_kcore_definition.restype = ctypes.c_int
         lib.oracle_kcore.argtypes = [vp, i32p]
@@ -192,6 +194,15 @@ class Graph:
         if _load().oracle_coloring(self._h, _p(prio, ctypes.c_uint64), _p(out, ctypes.c_int32)) != 0:
             raise MemoryError("oracle_coloring failed")
         return out[: self.n]
+
+    def densest(self, eps: float = 0.001):
+        """Peeling rounds: (best |E(S)|, best |S|, rounds, membership of that S)."""
+        be, bv = ctypes.c_int64(), ctypes.c_int64()
+        inb = np.empty(max(self.n, 1), np.uint8)
+        r = _load().oracle_densest(self._h, float(eps), ctypes.byref(be), ctypes.byref(bv), _p(inb, ctypes.c_uint8))
+        if r < 0:
+            raise MemoryError("oracle_densest failed")
+        return be.value, bv.value, int(r), inb[: self.n]
 
     def kcore(self) -> np.ndarray:
         """Coreness of every vertex by bucketed peeling."""

@@ -32,6 +32,11 @@
  *     that order and take each one none of whose neighbours was taken.
  *   - Colouring: the greedy colouring in the same kind of priority order: each
  *     vertex in turn takes the smallest colour no earlier neighbour holds.
+ *   - Approximate densest subgraph: peeling rounds. S starts as all vertices;
+ *     each round records the density |E(S)| / |S| and removes every vertex of
+ *     S with fewer than 2 (1 + eps) |E(S)| / |S| neighbours in S; the best
+ *     recorded density is the answer (within 2 (1 + eps) of the densest);
+ *     the rounds stop when S is empty or has no edge left.
  *   - k-core: the coreness of every vertex, the largest k such that the vertex
  *     belongs to the k-core (the maximal subgraph whose vertices all keep at
  *     least k neighbours in it). Two forms: the definition, one deletion
@@ -468,4 +473,48 @@ int oracle_coloring(const oracle_graph *g, const uint64_t *prio, int32_t *color)
   free(order);
   free(seen);
   return 0;
+}
+
+/* Approximate densest subgraph by peeling rounds (see the header). Returns
+ * the number of rounds; best_e / best_v = the best density seen (|E(S)| and
+ * |S| of that round); in_best[v] = 1 for the vertices of that S. The removal
+ * test is computed in FP64 exactly as written: (double)deg_S(v) <
+ * 2.0 * (1.0 + eps) * ((double)E / (double)S). */
+int64_t oracle_densest(const oracle_graph *g, double eps, int64_t *best_e, int64_t *best_v, uint8_t *in_best) {
+  int64_t n = g->n;
+  uint8_t *in = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+  uint8_t *drop = (uint8_t *)malloc((size_t)(n > 0 ? n : 1));
+  int64_t *d = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!in || !drop || !d) { free(in); free(drop); free(d); return -2; }
+  for (int64_t v = 0; v < n; ++v) { in[v] = 1; in_best[v] = 1; d[v] = g->len[v]; }
+  *best_e = 0;
+  *best_v = n > 0 ? n : 1;
+  int64_t rounds = 0, S = n;
+  while (S > 0) {
+    int64_t E2 = 0;
+    for (int64_t v = 0; v < n; ++v)
+      if (in[v]) E2 += d[v];
+    const int64_t E = E2 / 2;
+    ++rounds;
+    /* E / S > best_e / best_v, compared exactly */
+    if ((__int128)E * (__int128)(*best_v) > (__int128)(*best_e) * (__int128)S) {
+      *best_e = E;
+      *best_v = S;
+      for (int64_t v = 0; v < n; ++v) in_best[v] = in[v];
+    }
+    if (E == 0) break;  /* no edge left: nothing would fall below the threshold 0 */
+    const double thr = 2.0 * (1.0 + eps) * ((double)E / (double)S);
+    for (int64_t v = 0; v < n; ++v) drop[v] = in[v] && (double)d[v] < thr;
+    for (int64_t v = 0; v < n; ++v) {
+      if (!drop[v]) continue;
+      in[v] = 0;
+      --S;
+      for (int64_t i = 0; i < g->len[v]; ++i) {
+        int32_t u = g->nb[v][i];
+        if (in[u] || drop[u]) --d[u];
+      }
+    }
+  }
+  free(in); free(drop); free(d);
+  return rounds;
 }

@@ -455,6 +455,52 @@ def test_coloring_closed_forms():
     assert run(5, cyc, range(5)) == [0, 1, 0, 1, 2]                         # odd cycle needs 3
 
 
+# ---------------------------------------------------------------- approximate densest subgraph
+
+def brute_max_density(n, a, b):
+    """Exact densest subgraph by enumerating every vertex subset (tiny n)."""
+    from fractions import Fraction
+    E = brute.simple_edges(n, a, b)
+    best = Fraction(0)
+    for mask in range(1, 1 << n):
+        k = bin(mask).count("1")
+        e = sum(1 for u, v in E if (mask >> u) & 1 and (mask >> v) & 1)
+        best = max(best, Fraction(e, k))
+    return best
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.integers(1, 10).flatmap(
+    lambda n: st.tuples(st.just(n), st.lists(st.tuples(st.integers(0, n - 1), st.integers(0, n - 1)),
+                                             max_size=3 * n))), st.sampled_from([0.001, 0.1, 0.5]))
+def test_densest_within_its_bound_of_the_exact_optimum(case, eps):
+    from fractions import Fraction
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    be, bv, rounds, inb = g.densest(eps)
+    got = Fraction(be, bv)
+    opt = brute_max_density(n, a, b)
+    assert got <= opt
+    assert got * Fraction(2) * (1 + Fraction(eps)) >= opt
+    # the reported set has exactly that many vertices and inner edges
+    E = brute.simple_edges(n, a, b)
+    if be > 0:
+        assert int(inb.sum()) == bv
+        assert sum(1 for u, v in E if inb[u] and inb[v]) == be
+
+
+def test_densest_closed_forms():
+    k6 = [(u, v) for u in range(6) for v in range(u + 1, 6)]
+    be, bv, rounds, _ = G(6, k6)[0].densest(0.001)
+    assert (be, bv, rounds) == (15, 6, 1)                  # K6: density 5/2, peeled whole in one round
+    k5_tail = [(u, v) for u in range(5) for v in range(u + 1, 5)] + [(4, 5), (5, 6), (6, 7), (7, 8)]
+    be, bv, _, inb = G(9, k5_tail)[0].densest(0.001)
+    assert be * 5 == bv * 10 or be / bv >= 2.0             # K5's density 2 is reached
+    assert be / bv == 2.0 and inb[:5].all() and not inb[6:].any()
+    be, bv, rounds, _ = G(4, [])[0].densest(0.1)
+    assert be == 0 and rounds == 1
+
+
 # ---------------------------------------------------------------- k-core
 
 def brute_kcore(n, a, b):
