@@ -336,6 +336,19 @@ byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *opts, void *
 byo_status byo_mis(byo_graph *g, const uint64_t *d_prio, uint8_t *d_in_set, const byo_opts *opts, void *stream,
                    byo_run_stats *stats);
 
+/* Approximate densest subgraph (Table algs-list, substructure problems):
+ * peeling rounds. S starts as every vertex; each round records |S| and
+ * |E(S)| and removes every vertex of S with fewer than
+ * 2 (1 + eps) |E(S)| / |S| neighbours in S (that test in FP64, exactly as
+ * written); the rounds stop when S is empty or edgeless, or when a round
+ * removes nothing. *best_edges and
+ * *best_vertices = |E(S)| and |S| of the densest S seen (0 and n when no round
+ * has an edge), within 2 (1 + eps) of the densest subgraph; d_in_best (device
+ * uint8 [n] or NULL) = its membership. eps in [0, 1e6). Returns when done;
+ * BYO_ELIMIT if max_levels rounds do not finish. stats: levels = rounds. */
+byo_status byo_densest(byo_graph *g, double eps, uint8_t *d_in_best, int64_t *best_edges, int64_t *best_vertices,
+                       const byo_opts *opts, void *stream, byo_run_stats *stats);
+
 /* Graph colouring (Table algs-list, covering problems): the greedy colouring
  * in priority order, the vertices taken in ascending (d_prio[v], v) order,
  * each taking the smallest colour (0, 1, ...) no earlier neighbour holds;

@@ -36,7 +36,8 @@
  *     each round records the density |E(S)| / |S| and removes every vertex of
  *     S with fewer than 2 (1 + eps) |E(S)| / |S| neighbours in S; the best
  *     recorded density is the answer (within 2 (1 + eps) of the densest);
- *     the rounds stop when S is empty or has no edge left.
+ *     the rounds stop when S is empty, has no edge left, or a round removes
+ *     nothing (possible when eps = 0 and S is regular).
  *   - k-core: the coreness of every vertex, the largest k such that the vertex
  *     belongs to the k-core (the maximal subgraph whose vertices all keep at
  *     least k neighbours in it). Two forms: the definition, one deletion
@@ -504,7 +505,12 @@ int64_t oracle_densest(const oracle_graph *g, double eps, int64_t *best_e, int64
     }
     if (E == 0) break;  /* no edge left: nothing would fall below the threshold 0 */
     const double thr = 2.0 * (1.0 + eps) * ((double)E / (double)S);
-    for (int64_t v = 0; v < n; ++v) drop[v] = in[v] && (double)d[v] < thr;
+    int64_t dropped = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      drop[v] = in[v] && (double)d[v] < thr;
+      dropped += drop[v];
+    }
+    if (dropped == 0) break;  /* a round that removes nothing leaves S as it is */
     for (int64_t v = 0; v < n; ++v) {
       if (!drop[v]) continue;
       in[v] = 0;

@@ -305,6 +305,18 @@ def coloring(g: Graph, prio, opts=None, color=None, **kw):
     return color[: g.n], stt.as_dict()
 
 
+def densest(g: Graph, eps: float = 0.001, opts=None, in_best=None, **kw):
+    """Approximate densest subgraph by peeling: (best |E(S)|, best |S|, uint8 membership tensor, stats)."""
+    torch = _torch()
+    o = _opts(opts, kw)
+    in_best = torch.empty(max(g.n, 1), dtype=torch.uint8, device="cuda") if in_best is None else in_best
+    be, bv = ctypes.c_int64(), ctypes.c_int64()
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_densest(g.handle, float(eps), _ptr(in_best), ctypes.byref(be), ctypes.byref(bv),
+                                       ctypes.byref(o), _stream(), ctypes.byref(stt)))
+    return be.value, bv.value, in_best[: g.n], stt.as_dict()
+
+
 def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, opts=None, **kw) -> int:
     """edgeMap(G, U, F) into `out`; returns the variant that ran."""
     o = _opts(opts, kw)

@@ -122,6 +122,7 @@ SIGNATURES = {
     "byo_kcore": (st, [vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_mis": (st, [vp, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_coloring": (st, [vp, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
+    "byo_densest": (st, [vp, dbl, vp, i64p, i64p, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_cz_build": (st, [vp, vp]),
     "byo_cz_bytes": (st, [vp, i64p]),
     "byo_cz_copy": (st, [vp, vp, vp]),

@@ -163,7 +163,7 @@ void ws_free(byo_workspace &w) {
   void *dev[] = {w.visited, w.bits[0], w.bits[1], w.ids[0], w.ids[1], w.scan, w.partial, w.ctr, w.misc,
                  w.contrib[0], w.contrib[1], w.dpart, w.base, w.heavy_rows, w.chunk_row, w.chunk_beg,
                  w.row_chunk0, w.chunk_sum, w.api_deg, w.api_heavy, w.api_pre, w.api_aux,
-                 w.bc_coef, w.bc_sigma, w.bc_depth, w.bc_order, w.kc_dcur};
+                 w.bc_coef, w.bc_sigma, w.bc_depth, w.bc_order, w.kc_dcur, w.ds_deg, w.ds_alive};
   for (void *p : dev)
     if (p) (void)hipFree(p);
   if (w.h_ctr) (void)hipHostFree(w.h_ctr);

@@ -186,6 +186,8 @@ struct byo_workspace {
   int32_t *bc_depth = nullptr;         // [n] depths when the caller passes none
   int32_t *bc_order = nullptr;         // [n] vertices level by level
   int32_t *kc_dcur = nullptr;          // [n] k-core: remaining degrees
+  int32_t *ds_deg = nullptr;           // [n] densest subgraph: degrees inside S
+  uint8_t *ds_alive = nullptr;         // [n] densest subgraph: membership of S
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
 };

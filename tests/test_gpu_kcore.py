@@ -44,3 +44,17 @@ def test_kcore_round_cap():
     g = byo.Graph.from_pairs(graphs.path(1000))
     with pytest.raises(byo.ByoError):
         byo.kcore(g, max_levels=3)
+
+
+@pytest.mark.parametrize("eps", [0.001, 0.1])
+@pytest.mark.parametrize("p", SUITE, ids=IDS)
+def test_densest_matches_oracle(p, eps):
+    """Peeling rounds are deterministic: best |E(S)|, |S|, round count and the
+    best set equal the oracle's exactly."""
+    g = byo.Graph.from_pairs(p, validate=True)
+    og = oracle.Graph.from_pairs(p)
+    be, bv, inb, st = byo.densest(g, eps)
+    we, wv, wr, winb = og.densest(eps)
+    assert (be, bv, st["levels"]) == (we, wv, wr), p.name
+    assert np.array_equal(inb.cpu().numpy(), winb), p.name
+    print(p.name, eps, "density", round(be / bv, 4), "rounds", wr)

@@ -499,6 +499,9 @@ def test_densest_closed_forms():
     assert be / bv == 2.0 and inb[:5].all() and not inb[6:].any()
     be, bv, rounds, _ = G(4, [])[0].densest(0.1)
     assert be == 0 and rounds == 1
+    # eps = 0 on a regular graph: nothing falls below the average, the first round ends the run
+    be, bv, rounds, _ = G(8, [(i, (i + 1) % 8) for i in range(8)])[0].densest(0.0)
+    assert (be, bv, rounds) == (8, 8, 1)
 
 
 # ---------------------------------------------------------------- k-core
