@@ -54,6 +54,18 @@ def test_argument_errors_are_status_codes():
     assert b"exactly one" in lib.byo_last_error()
     assert lib.byo_bfs(None, 0, None, None, None, None, None) == -1
     assert lib.byo_num_vertices(None) == -1
+    # the other algorithms and the byte-coded container check their pointers
+    # before any device work
+    assert lib.byo_bc(None, 0, None, None, None, None, None, None) == -1
+    assert lib.byo_kcore(None, None, None, None, None) == -1
+    assert lib.byo_mis(None, None, None, None, None, None) == -1
+    assert lib.byo_coloring(None, None, None, None, None, None) == -1
+    assert lib.byo_densest(None, 0.1, None, None, None, None, None, None) == -1
+    assert lib.byo_cz_build(None, None) == -1
+    assert lib.byo_cz_bytes(None, None) == -1
+    assert lib.byo_cz_copy(None, None, None) == -1
+    assert lib.byo_cz_decode(None, 0, None, None) == -1
+    assert b"null" in lib.byo_last_error()
 
 
 @pytest.mark.parametrize("p", [gen.er_pairs(1 << 12, 8), gen.rmat_pairs(11), gen.grid_pairs(33, 17, 0.1),
