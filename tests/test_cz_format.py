@@ -122,8 +122,14 @@ def test_wave_decoder_algorithm_on_random_blocks():
     for trial in range(300):
         v = int(rng.integers(0, 2 ** 31 - 1))
         d = int(rng.integers(1, 200))
-        spread = int(rng.choice([2 ** 7, 2 ** 14, 2 ** 21, 2 ** 28, 2 ** 31 - 1]))
-        nbrs = np.unique(rng.integers(0, spread, size=3 * d))[:d]
+        spread = int(rng.choice([2 ** 7, 2 ** 14, 2 ** 21, 2 ** 28, 2 ** 31 - 1, 0]))
+        if spread:
+            nbrs = np.unique(rng.integers(0, spread, size=d))
+        else:
+            # gaps in [2^22, 2^23): 4 bytes each, so a full block is 257 bytes (two passes)
+            d = min(d, 250)
+            nbrs = np.cumsum(rng.integers(2 ** 22, 2 ** 23, size=d))
+            nbrs = nbrs[nbrs < 2 ** 31 - 1]
         nbrs = sorted({int(x) for x in nbrs} - {v})
         if not nbrs:
             continue
