@@ -73,6 +73,10 @@ def _load():
         lib.oracle_coloring.restype = ctypes.c_int
         lib.oracle_densest.argtypes = [vp, ctypes.c_double, i64p, i64p, ctypes.POINTER(ctypes.c_uint8)]
         lib.oracle_densest.restype = i64
+        lib.oracle_ldd.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+        lib.oracle_ldd.restype = ctypes.c_int
+        lib.oracle_ldd_definition.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+        lib.oracle_ldd_definition.restype = ctypes.c_int
         lib.oracle_kcore_definition.argtypes = [vp, i32p]
         lib.oracle_kcore_definition.restype = ctypes.c_int
         lib.oracle_kcore.argtypes = [vp, i32p]
@@ -203,6 +207,16 @@ class Graph:
         if r < 0:
             raise MemoryError("oracle_densest failed")
         return be.value, bv.value, int(r), inb[: self.n]
+
+    def ldd(self, delta, definition: bool = False) -> np.ndarray:
+        """Shifted clustering: cluster[v] = argmin_u dist(u, v) - delta[u] (ties: smaller u)."""
+        delta = np.ascontiguousarray(delta, np.float64)
+        assert delta.shape[0] >= self.n
+        out = np.empty(max(self.n, 1), np.int32)
+        fn = _load().oracle_ldd_definition if definition else _load().oracle_ldd
+        if fn(self._h, _p(delta, ctypes.c_double), _p(out, ctypes.c_int32)) != 0:
+            raise MemoryError("oracle_ldd failed")
+        return out[: self.n]
 
     def kcore(self) -> np.ndarray:
         """Coreness of every vertex by bucketed peeling."""

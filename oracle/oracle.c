@@ -38,6 +38,11 @@
  *     recorded density is the answer (within 2 (1 + eps) of the densest);
  *     the rounds stop when S is empty, has no edge left, or a round removes
  *     nothing (possible when eps = 0 and S is regular).
+ *   - Low-diameter decomposition (Miller, Peng and Xu's shifted clustering):
+ *     given shifts delta (the exponential draws are an input), vertex v joins
+ *     the centre u minimising dist(u, v) - delta[u], ties to the smaller u.
+ *     Two forms: that definition pair by pair (small graphs) and one
+ *     shifted-start Dijkstra over the unweighted graph.
  *   - k-core: the coreness of every vertex, the largest k such that the vertex
  *     belongs to the k-core (the maximal subgraph whose vertices all keep at
  *     least k neighbours in it). Two forms: the definition, one deletion
@@ -523,4 +528,81 @@ int64_t oracle_densest(const oracle_graph *g, double eps, int64_t *best_e, int64
   }
   free(in); free(drop); free(d);
   return rounds;
+}
+
+/* Low-diameter decomposition, the definition: for every v, the u in v's
+ * component minimising dist(u, v) - delta[u] (ties: smaller u); one BFS per
+ * u, O(n (n + m)). cluster[v] = that u. */
+int oracle_ldd_definition(const oracle_graph *g, const double *delta, int32_t *cluster) {
+  int64_t n = g->n;
+  int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  double *sig = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *best = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  if (!dist || !sig || !best) { free(dist); free(sig); free(best); return -2; }
+  for (int64_t v = 0; v < n; ++v) { cluster[v] = -1; best[v] = 0.0; }
+  for (int64_t u = 0; u < n; ++u) {
+    bfs_paths(g, u, dist, sig, NULL);
+    for (int64_t v = 0; v < n; ++v) {
+      if (dist[v] < 0) continue;
+      double key = (double)dist[v] - delta[u];
+      if (cluster[v] < 0 || key < best[v]) { best[v] = key; cluster[v] = (int32_t)u; }
+      /* u ascends, so an equal key keeps the smaller centre already there */
+    }
+  }
+  free(dist); free(sig); free(best);
+  return 0;
+}
+
+/* The same clustering by one Dijkstra: every vertex u enters as its own
+ * centre at hop 0; settling v in order of (key, centre) gives each neighbour w
+ * the candidate (hop(v) + 1, centre(v)), so each vertex is settled with its
+ * least (dist(u, v) - delta[u], u): the predecessor of v on a shortest path
+ * from v's best centre has that same centre as its own best. Binary heap,
+ * O((n + m) log n). */
+/* a candidate: v reached from centre at hop distance dist; its key is
+ * (double)dist - delta[centre], computed as in the definition */
+typedef struct { int32_t dist; int32_t centre; int32_t v; } ldd_item;
+static const double *g_ldd_delta;
+static int ldd_less(const ldd_item *a, const ldd_item *b) {
+  double ka = (double)a->dist - g_ldd_delta[a->centre], kb = (double)b->dist - g_ldd_delta[b->centre];
+  if (ka != kb) return ka < kb;
+  return a->centre < b->centre;
+}
+int oracle_ldd(const oracle_graph *g, const double *delta, int32_t *cluster) {
+  int64_t n = g->n, cap = n + g->m + 1, size = 0;
+  ldd_item *heap = (ldd_item *)malloc(sizeof(ldd_item) * (size_t)cap);
+  uint8_t *done = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!heap || !done) { free(heap); free(done); return -2; }
+  g_ldd_delta = delta;
+  #define LDD_PUSH(D, C, V) do {                                               \
+    int64_t i_ = size++;                                                       \
+    heap[i_].dist = (D); heap[i_].centre = (C); heap[i_].v = (V);              \
+    while (i_ > 0 && ldd_less(&heap[i_], &heap[(i_ - 1) / 2])) {               \
+      ldd_item t_ = heap[i_]; heap[i_] = heap[(i_ - 1) / 2]; heap[(i_ - 1) / 2] = t_; \
+      i_ = (i_ - 1) / 2;                                                       \
+    }                                                                          \
+  } while (0)
+  for (int64_t v = 0; v < n; ++v) { cluster[v] = -1; LDD_PUSH(0, (int32_t)v, (int32_t)v); }
+  while (size > 0) {
+    ldd_item top = heap[0];
+    heap[0] = heap[--size];
+    for (int64_t i = 0;;) {  /* sift down */
+      int64_t l = 2 * i + 1, r = l + 1, m = i;
+      if (l < size && ldd_less(&heap[l], &heap[m])) m = l;
+      if (r < size && ldd_less(&heap[r], &heap[m])) m = r;
+      if (m == i) break;
+      ldd_item t = heap[i]; heap[i] = heap[m]; heap[m] = t;
+      i = m;
+    }
+    if (done[top.v]) continue;
+    done[top.v] = 1;
+    cluster[top.v] = top.centre;
+    for (int64_t i = 0; i < g->len[top.v]; ++i) {
+      int32_t w = g->nb[top.v][i];
+      if (!done[w]) LDD_PUSH(top.dist + 1, top.centre, w);
+    }
+  }
+  #undef LDD_PUSH
+  free(heap); free(done);
+  return 0;
 }

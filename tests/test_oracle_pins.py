@@ -504,6 +504,41 @@ def test_densest_closed_forms():
     assert (be, bv, rounds) == (8, 8, 1)
 
 
+# ---------------------------------------------------------------- low-diameter decomposition
+
+@settings(max_examples=80, deadline=None)
+@given(tiny_graphs, st.integers(0, 2 ** 32), st.sampled_from([0.05, 0.5, 2.0]))
+def test_ldd_dijkstra_matches_definition_and_clusters_are_connected(case, seed, beta):
+    n, pairs = case
+    g, a, b = G(n, pairs)
+    delta = np.random.default_rng(seed).exponential(1.0 / beta, n)
+    got = g.ldd(delta)
+    assert got.tolist() == g.ldd(delta, definition=True).tolist()
+    D = brute.floyd_warshall_hops(brute.adjacency_matrix(n, a, b))
+    for v in range(n):
+        c = int(got[v])
+        assert D[c, v] >= 0                               # a centre in v's component
+        keys = [(D[u, v] - delta[u], u) for u in range(n) if D[u, v] >= 0]
+        assert (D[c, v] - delta[c], c) == min(keys)       # the least shifted distance
+        # connected clusters: some neighbour one hop closer to c is in c's cluster
+        if c != v:
+            assert any(D[c, u] == D[c, v] - 1 and got[u] == c for u in g.neighbors(v))
+
+
+def test_ldd_closed_forms():
+    path = [(i, i + 1) for i in range(9)]
+    g, _, _ = G(10, path)
+    assert g.ldd(np.zeros(10)).tolist() == list(range(10))              # equal shifts: every vertex alone
+    big = np.zeros(10)
+    big[4] = 100.0
+    assert g.ldd(big).tolist() == [4] * 10                              # one dominant shift takes everything
+    two = np.zeros(10)
+    two[0], two[9] = 5.0, 5.0
+    assert g.ldd(two).tolist() == [0] * 5 + [9] * 5                     # two equal centres split the path
+    g2, _, _ = G(6, [(0, 1), (1, 2), (3, 4), (4, 5)])
+    assert g2.ldd(np.full(6, 50.0) - np.arange(6)).tolist() == [0, 0, 0, 3, 3, 3]   # per component
+
+
 # ---------------------------------------------------------------- k-core
 
 def brute_kcore(n, a, b):
