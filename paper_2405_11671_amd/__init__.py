@@ -30,7 +30,18 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _ptr(t):
+def _ptr(t, need: int = 0, size: int | None = None):
+    """Device pointer of a tensor the library will read or write, checked
+    first: a host tensor, a non-contiguous view, a wrong element size or fewer
+    than `need` elements raise ValueError here instead of reaching a kernel."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("buffers passed to the library must be device (cuda) tensors")
+    if not t.is_contiguous():
+        raise ValueError("buffers passed to the library must be contiguous")
+    if size is not None and t.element_size() != size:
+        raise ValueError(f"buffer elements of {t.element_size()} bytes where {size} are needed")
+    if t.numel() < need:
+        raise ValueError(f"buffer of {t.numel()} elements where {need} are needed")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -181,7 +192,7 @@ class VSet:
         return self
 
     def set_bitmap(self, bits_t):
-        _lib.check(_lib.load().byo_vset_from_bitmap(self._h, _ptr(bits_t), _stream()))
+        _lib.check(_lib.load().byo_vset_from_bitmap(self._h, _ptr(bits_t, (self.g.n + 63) // 64, 8), _stream()))
         return self
 
     def fill(self):
@@ -225,7 +236,8 @@ def bfs(g: Graph, src: int, opts=None, depth=None, parent=None, **kw):
     depth = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if depth is None else depth
     parent = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if parent is None else parent
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_bfs(g.handle, int(src), _ptr(depth), _ptr(parent), ctypes.byref(o), _stream(),
+    _lib.check(_lib.load().byo_bfs(g.handle, int(src), _ptr(depth, g.n, 4), _ptr(parent, g.n, 4), ctypes.byref(o),
+                                   _stream(),
                                    ctypes.byref(stt)))
     return depth[: g.n], parent[: g.n], stt.as_dict()
 
@@ -236,7 +248,7 @@ def cc(g: Graph, opts=None, label=None, **kw):
     o = _opts(opts, kw)
     label = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if label is None else label
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_cc(g.handle, _ptr(label), ctypes.byref(o), _stream(), ctypes.byref(stt)))
+    _lib.check(_lib.load().byo_cc(g.handle, _ptr(label, g.n, 4), ctypes.byref(o), _stream(), ctypes.byref(stt)))
     return label[: g.n], stt.as_dict()
 
 
@@ -246,7 +258,7 @@ def pagerank(g: Graph, damping: float = 0.85, iters: int = 20, opts=None, rank=N
     o = _opts(opts, kw)
     rank = torch.empty(max(g.n, 1), dtype=torch.float32, device="cuda") if rank is None else rank
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_pagerank(g.handle, float(damping), int(iters), _ptr(rank), ctypes.byref(o),
+    _lib.check(_lib.load().byo_pagerank(g.handle, float(damping), int(iters), _ptr(rank, g.n, 4), ctypes.byref(o),
                                         _stream(), ctypes.byref(stt)))
     return rank[: g.n], stt.as_dict()
 
@@ -261,7 +273,8 @@ def bc(g: Graph, src: int, opts=None, delta=None, sigma=None, depth=None, **kw):
     sigma = torch.empty(n1, dtype=torch.float64, device="cuda") if sigma is None else sigma
     depth = torch.empty(n1, dtype=torch.int32, device="cuda") if depth is None else depth
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_bc(g.handle, int(src), _ptr(delta), _ptr(sigma), _ptr(depth), ctypes.byref(o),
+    _lib.check(_lib.load().byo_bc(g.handle, int(src), _ptr(delta, g.n, 8), _ptr(sigma, g.n, 8), _ptr(depth, g.n, 4),
+                                  ctypes.byref(o),
                                   _stream(), ctypes.byref(stt)))
     return delta[: g.n], sigma[: g.n], depth[: g.n], stt.as_dict()
 
@@ -272,7 +285,7 @@ def kcore(g: Graph, opts=None, core=None, **kw):
     o = _opts(opts, kw)
     core = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if core is None else core
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_kcore(g.handle, _ptr(core), ctypes.byref(o), _stream(), ctypes.byref(stt)))
+    _lib.check(_lib.load().byo_kcore(g.handle, _ptr(core, g.n, 4), ctypes.byref(o), _stream(), ctypes.byref(stt)))
     return core[: g.n], stt.as_dict()
 
 
@@ -286,7 +299,7 @@ def mis(g: Graph, prio, opts=None, in_set=None, **kw):
     assert prio.numel() >= g.n and prio.element_size() == 8
     in_set = torch.empty(max(g.n, 1), dtype=torch.uint8, device="cuda") if in_set is None else in_set
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_mis(g.handle, _ptr(prio), _ptr(in_set), ctypes.byref(o), _stream(),
+    _lib.check(_lib.load().byo_mis(g.handle, _ptr(prio, g.n, 8), _ptr(in_set, g.n, 1), ctypes.byref(o), _stream(),
                                    ctypes.byref(stt)))
     return in_set[: g.n], stt.as_dict()
 
@@ -300,7 +313,7 @@ def coloring(g: Graph, prio, opts=None, color=None, **kw):
     assert prio.numel() >= g.n and prio.element_size() == 8
     color = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if color is None else color
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_coloring(g.handle, _ptr(prio), _ptr(color), ctypes.byref(o), _stream(),
+    _lib.check(_lib.load().byo_coloring(g.handle, _ptr(prio, g.n, 8), _ptr(color, g.n, 4), ctypes.byref(o), _stream(),
                                         ctypes.byref(stt)))
     return color[: g.n], stt.as_dict()
 
@@ -312,7 +325,7 @@ def densest(g: Graph, eps: float = 0.001, opts=None, in_best=None, **kw):
     in_best = torch.empty(max(g.n, 1), dtype=torch.uint8, device="cuda") if in_best is None else in_best
     be, bv = ctypes.c_int64(), ctypes.c_int64()
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_densest(g.handle, float(eps), _ptr(in_best), ctypes.byref(be), ctypes.byref(bv),
+    _lib.check(_lib.load().byo_densest(g.handle, float(eps), _ptr(in_best, g.n, 1), ctypes.byref(be), ctypes.byref(bv),
                                        ctypes.byref(o), _stream(), ctypes.byref(stt)))
     return be.value, bv.value, in_best[: g.n], stt.as_dict()
 
@@ -327,15 +340,15 @@ def edge_map(g: Graph, U: VSet, fn: int, state, out: VSet, variant: int = -1, op
 
 
 def bfs_fn_state(parent_t, depth_t, visited_t, level: int):
-    return _lib.BfsFn(parent_t.data_ptr(), depth_t.data_ptr(), visited_t.data_ptr(), int(level))
+    return _lib.BfsFn(_ptr(parent_t, 0, 4).value, _ptr(depth_t, 0, 4).value, _ptr(visited_t, 0, 8).value, int(level))
 
 
 def cc_fn_state(label_t):
-    return _lib.CcFn(label_t.data_ptr())
+    return _lib.CcFn(_ptr(label_t, 0, 4).value)
 
 
 def pr_fn_state(contrib_t, acc_t):
-    return _lib.PrFn(contrib_t.data_ptr(), acc_t.data_ptr())
+    return _lib.PrFn(_ptr(contrib_t, 0, 4).value, _ptr(acc_t, 0, 4).value)
 
 
 def msbfs(g: Graph, srcs, opts=None, depth=None, **kw):
@@ -346,7 +359,7 @@ def msbfs(g: Graph, srcs, opts=None, depth=None, **kw):
     k = int(srcs.shape[0])
     depth = torch.empty(max(g.n * k, 1), dtype=torch.uint8, device="cuda") if depth is None else depth
     stt = _lib.RunStats()
-    _lib.check(_lib.load().byo_msbfs(g.handle, srcs.ctypes.data, k, _ptr(depth), ctypes.byref(o), _stream(),
+    _lib.check(_lib.load().byo_msbfs(g.handle, srcs.ctypes.data, k, _ptr(depth, g.n * k, 1), ctypes.byref(o), _stream(),
                                      ctypes.byref(stt)))
     return depth[: g.n * k].view(g.n, k), stt.as_dict()
 
@@ -435,7 +448,8 @@ class Batch:
         depth = torch.empty(self.n, dtype=torch.int32, device="cuda") if depth is None else depth
         parent = torch.empty(self.n, dtype=torch.int32, device="cuda") if parent is None else parent
         stt = _lib.RunStats()
-        _lib.check(_lib.load().byo_batch_bfs(self._h, srcs.ctypes.data, _ptr(depth), _ptr(parent), ctypes.byref(o),
+        _lib.check(_lib.load().byo_batch_bfs(self._h, srcs.ctypes.data, _ptr(depth, self.n, 4), _ptr(parent, self.n, 4),
+                                             ctypes.byref(o),
                                              _stream(), ctypes.byref(stt)))
         return depth, parent, stt.as_dict()
 
@@ -444,7 +458,8 @@ class Batch:
         o = _opts(opts, kw)
         label = torch.empty(self.n, dtype=torch.int32, device="cuda") if label is None else label
         stt = _lib.RunStats()
-        _lib.check(_lib.load().byo_batch_cc(self._h, _ptr(label), ctypes.byref(o), _stream(), ctypes.byref(stt)))
+        _lib.check(_lib.load().byo_batch_cc(self._h, _ptr(label, self.n, 4), ctypes.byref(o), _stream(),
+                                            ctypes.byref(stt)))
         return label, stt.as_dict()
 
     def split(self, t):

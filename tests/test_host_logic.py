@@ -49,3 +49,39 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=300, cwd=ROOT)
     assert r.returncode != 0
     assert "one GPU" in r.stdout + r.stderr
+
+
+class _FakeDeviceTensor:
+    """Stands in for a CUDA tensor on a machine without one."""
+
+    def __init__(self, numel, element_size, contiguous=True):
+        self._n, self._e, self._c = numel, element_size, contiguous
+        self.is_cuda = True
+
+    def is_contiguous(self):
+        return self._c
+
+    def element_size(self):
+        return self._e
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 0x1000
+
+
+def test_buffers_are_checked_before_they_reach_the_library():
+    import pytest
+    import torch
+
+    import paper_2405_11671_amd as byo
+    with pytest.raises(ValueError, match="device"):
+        byo._ptr(torch.zeros(4))                                  # host memory
+    with pytest.raises(ValueError, match="contiguous"):
+        byo._ptr(_FakeDeviceTensor(8, 4, contiguous=False))
+    with pytest.raises(ValueError, match="bytes"):
+        byo._ptr(_FakeDeviceTensor(8, 8), 8, 4)                   # int64 where int32 is needed
+    with pytest.raises(ValueError, match="elements"):
+        byo._ptr(_FakeDeviceTensor(7, 4), 8, 4)                   # too short
+    assert byo._ptr(_FakeDeviceTensor(8, 4), 8, 4).value == 0x1000
