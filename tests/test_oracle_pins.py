@@ -539,6 +539,34 @@ def test_ldd_closed_forms():
     assert g2.ldd(np.full(6, 50.0) - np.arange(6)).tolist() == [0, 0, 0, 3, 3, 3]   # per component
 
 
+@pytest.mark.parametrize("beta", [0.05, 0.2, 1.0])
+@pytest.mark.parametrize("shape", ["grid", "rmat"])
+def test_ldd_cut_probability_within_the_exponential_shift_bound(shape, beta):
+    """With shifts drawn from an exponential distribution of rate beta, an edge
+    ends up between two clusters with probability at most 1 - exp(-beta)
+    (Miller, Peng and Xu, 2013: the midpoint of an edge keeps one centre
+    unless its two least shifted distances lie within 1 of each other, and by
+    memorylessness that happens with probability at most 1 - exp(-beta)).
+    The mean cut fraction over seeded draws must stay within that bound plus
+    three standard errors. Every centre is also its own centre: a vertex u
+    that beat c at c would, by the triangle inequality and the smaller-id tie
+    rule, also beat c at every vertex that chose c."""
+    from paper_2405_11671_amd import gen
+    p = gen.grid_pairs(60, 60, 0.0, seed=1) if shape == "grid" else gen.rmat_pairs(12, 8, seed=3)
+    og = oracle.Graph.from_pairs(p)
+    src, dst = np.asarray(p.src), np.asarray(p.dst)
+    src, dst = src[src != dst], dst[src != dst]
+    fractions = []
+    for seed in range(16):
+        delta = np.random.default_rng(seed).exponential(1.0 / beta, og.n)
+        c = og.ldd(delta)
+        assert np.array_equal(c[c], c)
+        fractions.append(np.mean(c[src] != c[dst]))
+    mean = float(np.mean(fractions))
+    se = float(np.std(fractions)) / math.sqrt(len(fractions))
+    assert mean <= 1.0 - math.exp(-beta) + 3.0 * se, (shape, beta, mean, se)
+
+
 # ---------------------------------------------------------------- k-core
 
 def brute_kcore(n, a, b):
