@@ -333,6 +333,32 @@ def test_bc_recurrence_matches_definition(case, s):
     assert np.all((sigma > 0) == (want_d >= 0))
 
 
+@pytest.mark.parametrize("shape", ["rmat", "lattice", "star"])
+def test_bc_dependencies_sum_to_interior_path_lengths(shape):
+    """Summed over v, the dependencies of a source s count, for each reachable
+    target t, the average number of interior vertices on a shortest s-t path,
+    which is d(s, t) - 1 for every such path. So the sum of delta_s equals the
+    sum of d(s, t) - 1 over reachable t != s, with the distances taken here from
+    scipy's breadth-first search; the source's own dependency is 0. This holds
+    at any size, beyond what path enumeration can reach."""
+    from paper_2405_11671_amd import gen
+    from tests import graphs
+    p = {"rmat": lambda: gen.rmat_pairs(12, 8, seed=3), "lattice": lambda: gen.grid_pairs(40, 50, 0.2, seed=2),
+         "star": lambda: graphs.star(500)}[shape]()
+    og = oracle.Graph.from_pairs(p)
+    n = og.n
+    src, dst = np.asarray(p.src), np.asarray(p.dst)
+    A = sp.coo_matrix((np.ones(len(src)), (src, dst)), shape=(n, n)).tocsr()
+    for s in sorted({0, int(np.argmax(og.degrees())), n // 2}):
+        D = csg.shortest_path(A, directed=False, unweighted=True, indices=s)
+        reach = np.isfinite(D)
+        reach[s] = False
+        want = float(np.sum(D[reach] - 1))
+        sigma, delta, dist = og.bc(s)
+        assert delta[s] == 0.0
+        assert abs(float(np.sum(delta)) - want) <= 1e-12 * max(1.0, want), (shape, s)
+
+
 def test_bc_closed_forms():
     n = 12
     path = [(i, i + 1) for i in range(n - 1)]
