@@ -515,6 +515,31 @@ def test_densest_within_its_bound_of_the_exact_optimum(case, eps):
         assert sum(1 for u, v in E if inb[u] and inb[v]) == be
 
 
+@pytest.mark.parametrize("eps", [0.001, 0.1, 1.0])
+@pytest.mark.parametrize("shape", ["rmat", "lattice", "star"])
+def test_densest_bracketed_by_the_maximum_core_at_scale(shape, eps):
+    """Beyond exhaustive sizes: a densest subgraph has minimum degree at least
+    its density rho* (dropping a vertex of smaller degree would raise it), so it
+    lies inside the ceil(rho*)-core and rho* <= k_max; the k_max-core has every
+    degree >= k_max, so rho* >= k_max / 2. Peeling returns at least
+    rho* / (2(1 + eps)). The reported set must also hold exactly the reported
+    vertex and inner-edge counts, counted here over the edge list."""
+    from paper_2405_11671_amd import gen
+    from tests import graphs
+    p = {"rmat": lambda: gen.rmat_pairs(12, 8, seed=3), "lattice": lambda: gen.grid_pairs(40, 50, 0.2, seed=2),
+         "star": lambda: graphs.star(500)}[shape]()
+    og = oracle.Graph.from_pairs(p)
+    kmax = int(og.kcore().max())
+    be, bv, rounds, inb = og.densest(eps)
+    assert kmax * bv <= 4 * (1 + eps) * be + 1e-9 * bv and be <= kmax * bv, (shape, eps, be, bv, kmax)
+    src, dst = np.asarray(p.src, np.int64), np.asarray(p.dst, np.int64)
+    keep = src != dst
+    und = np.unique(np.minimum(src[keep], dst[keep]) * og.n + np.maximum(src[keep], dst[keep]))
+    a, b = und // og.n, und % og.n
+    assert int(inb.sum()) == bv
+    assert int(np.sum(inb[a].astype(bool) & inb[b].astype(bool))) == be
+
+
 def test_densest_closed_forms():
     k6 = [(u, v) for u in range(6) for v in range(u + 1, 6)]
     be, bv, rounds, _ = G(6, k6)[0].densest(0.001)
