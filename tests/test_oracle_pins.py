@@ -466,6 +466,45 @@ def test_coloring_matches_brute_force_and_is_proper(case, seed):
         assert got[v] <= g.degree(v)                      # at most degree + 1 colours
 
 
+def _earlier_edges(p, n, prio):
+    """Every undirected edge as (later, earlier) in (prio, id) order."""
+    src, dst = np.asarray(p.src, np.int64), np.asarray(p.dst, np.int64)
+    keep = src != dst
+    und = np.unique(np.minimum(src[keep], dst[keep]) * n + np.maximum(src[keep], dst[keep]))
+    a, b = und // n, und % n
+    pa, pb = prio[a].astype(np.int64), prio[b].astype(np.int64)
+    a_first = (pa < pb) | ((pa == pb) & (a < b))
+    return np.where(a_first, b, a), np.where(a_first, a, b)
+
+
+@pytest.mark.parametrize("shape", ["rmat", "lattice"])
+def test_mis_and_coloring_local_characterisations_at_scale(shape):
+    """Beyond exhaustive sizes, each greedy result is checked by the local
+    condition that fixes it uniquely, over an edge list, in numpy:
+    - MIS: v is in the set exactly when no neighbour earlier in (prio, id)
+      order is (the lexicographically first maximal independent set);
+    - colouring: each colour is the least one missing among the earlier
+      neighbours' colours, so none of them shares it and the distinct smaller
+      colours among them number exactly the colour itself."""
+    from paper_2405_11671_amd import gen
+    p = gen.rmat_pairs(13, 8, seed=4) if shape == "rmat" else gen.grid_pairs(60, 70, 0.15, seed=3)
+    og = oracle.Graph.from_pairs(p)
+    n = og.n
+    for seed in range(3):
+        prio = np.random.default_rng(seed).integers(0, 3, n).astype(np.uint64)   # heavy ties: id decides
+        late, early = _earlier_edges(p, n, prio)
+        mis = og.mis(prio).astype(bool)
+        blocked = np.zeros(n, bool)
+        np.logical_or.at(blocked, late, mis[early])
+        assert np.array_equal(mis, ~blocked), (shape, seed)
+        col = og.coloring(prio).astype(np.int64)
+        assert not np.any(col[late] == col[early])
+        lower = col[early] < col[late]
+        pairs = np.unique(late[lower] * (int(col.max()) + 1) + col[early][lower])
+        have = np.bincount(pairs // (int(col.max()) + 1), minlength=n)
+        assert np.array_equal(have, col), (shape, seed)
+
+
 def test_coloring_closed_forms():
     def run(n, pairs, prio):
         return G(n, pairs)[0].coloring(np.asarray(prio, np.uint64)).tolist()
