@@ -1,10 +1,13 @@
 """CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
-Plain single-threaded reference for what the GPU traversal path computes
-(BFS, min-ID connected components, FP64 PageRank, multi-source BFS, and the
-selector MLP). Only the test suite, the smoke check and the benchmark's CPU
-baseline leg may import this package. It shares no code with the product
-library: ``oracle.c`` is compiled on its own by gcc, and ``mlp.py`` is numpy.
+Plain single-threaded reference for what the GPU traversal path computes:
+BFS, min-ID connected components, FP64 PageRank, multi-source BFS,
+single-source betweenness, k-core, greedy MIS and colouring, the approximate
+densest subgraph, low-diameter decomposition, the selector MLP (``mlp.py``)
+and batch edge updates (``updates.py``). Only the test suite, the smoke check
+and the benchmark's CPU baseline leg may import this package. It shares no
+code with the product library: ``oracle.c`` is compiled on its own by gcc,
+and ``mlp.py`` and ``updates.py`` are numpy.
 """
 from __future__ import annotations
 
