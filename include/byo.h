@@ -193,6 +193,7 @@ byo_status byo_csr_from_pairs(const int32_t *h_src, const int32_t *h_dst, int64_
 byo_status byo_graph_from_csr(const int64_t *off, const int32_t *nbr, int64_t n, int64_t m, uint32_t flags,
                               void *stream, byo_graph **out);
 void byo_graph_destroy(byo_graph *g);
+/* n and m; -1 for a null graph, with the message in byo_last_error. */
 int64_t byo_num_vertices(const byo_graph *g);        /* n (required API) */
 int64_t byo_num_edges(const byo_graph *g);           /* m = directed entries (optional API) */
 byo_status byo_degree(const byo_graph *g, int64_t v, int64_t *out);  /* |N(v)|, syncs */

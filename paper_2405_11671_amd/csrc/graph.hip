@@ -406,8 +406,14 @@ void byo_graph_destroy(byo_graph *g) {
   delete g;
 }
 
-int64_t byo_num_vertices(const byo_graph *g) { return g ? g->n : -1; }
-int64_t byo_num_edges(const byo_graph *g) { return g ? g->m : -1; }
+int64_t byo_num_vertices(const byo_graph *g) {
+  if (!g) { set_error("null graph"); return -1; }
+  return g->n;
+}
+int64_t byo_num_edges(const byo_graph *g) {
+  if (!g) { set_error("null graph"); return -1; }
+  return g->m;
+}
 
 byo_status byo_degree(const byo_graph *g, int64_t v, int64_t *out) {
   BYO_CHECK(g && out, BYO_EINVAL, "null argument");

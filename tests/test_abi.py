@@ -68,6 +68,48 @@ def test_argument_errors_are_status_codes():
     assert b"null" in lib.byo_last_error()
 
 
+NO_HANDLE = {"byo_last_error", "byo_version", "byo_heuristic_choice"}
+# no handle, but they switch process-wide state (tracing, kernel timers, the
+# loaded selector) that later tests in the same process may rely on
+STATEFUL = {"byo_selector_clear", "byo_trace_enable", "byo_ktimer_enable", "byo_ktimer_select", "byo_ktimer_reset"}
+DESTROY = {"byo_graph_destroy", "byo_vset_destroy", "byo_batch_destroy"}
+
+
+def test_every_entry_point_rejects_null_arguments_before_device_work():
+    """Each declared function, called with null pointers and zero scalars on a
+    host with no GPU, returns the argument-error status (or -1 for the
+    counts) with a message, rather than crashing or reaching the device; the
+    destroy calls accept null, and the pure calls that take no handle succeed.
+    The calls that switch process-wide state are left uncalled."""
+    lib = _lib.load()
+    sigs = dict(_lib.SIGNATURES)
+    sigs.update(_lib.extra_signatures())
+    h = ctypes.c_void_p()
+    off = np.array([0, 0], np.int64)
+    for name in sorted(declared_functions() - STATEFUL):
+        _, args = sigs[name]
+        vals = []
+        for a in args:
+            if a in (ctypes.c_double, ctypes.c_float):
+                vals.append(0.0)
+            elif a not in (ctypes.c_void_p, ctypes.c_char_p) and isinstance(a, type) and \
+                    issubclass(a, ctypes._SimpleCData):
+                vals.append(0)
+            else:
+                vals.append(None)
+        # leave a different message behind, so a stale one cannot pass below
+        assert lib.byo_graph_from_csr(off.ctypes.data, None, 1, 0, 0, None, ctypes.byref(h)) == -1
+        r = getattr(lib, name)(*vals)
+        if name in DESTROY or name == "byo_opts_default":
+            assert r is None, name
+        elif name in NO_HANDLE:
+            assert r is not None and r != -1, (name, r)
+        else:
+            assert r == -1, (name, r)
+            msg = lib.byo_last_error()
+            assert b"null" in msg or b"bad argument" in msg, (name, msg)
+
+
 @pytest.mark.parametrize("p", [gen.er_pairs(1 << 12, 8), gen.rmat_pairs(11), gen.grid_pairs(33, 17, 0.1),
                                graphs.star(500, centre=7), graphs.empty(9)], ids=lambda p: p.name)
 def test_host_csr_build_matches_oracle_sets(p):
