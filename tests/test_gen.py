@@ -73,3 +73,36 @@ def test_batch_specs_ranges():
     for n, d, s in specs:
         assert 2 ** 10 - 1 <= n <= 2 ** 18 + 1 and 4 <= d <= 32
     assert specs == gen.batch_specs(64, seed=3)
+
+
+M64 = (1 << 64) - 1
+GAMMA = 0x9e3779b97f4a7c15
+
+
+def _mix(z):
+    z = ((z ^ (z >> 30)) * 0xbf58476d1ce4e5b9) & M64
+    z = ((z ^ (z >> 27)) * 0x94d049bb133111eb) & M64
+    return z ^ (z >> 31)
+
+
+def _splitmix64(state, k):
+    """SplitMix64 (Steele, Lea and Flood, 2014): add the golden gamma, then mix."""
+    out = []
+    for _ in range(k):
+        state = (state + GAMMA) & M64
+        out.append(_mix(state))
+    return out
+
+
+def test_draws_are_splitmix64_from_a_per_stream_state():
+    """The published SplitMix64 sequence from state 0 begins e220a8397b1dcdaf,
+    6e789e6aa1b965f4, 06c45d188009454f; the generator's draw i of a (seed,
+    stream) is output i of SplitMix64 started from a state mixed out of the
+    seed and stream, so every draw is a pure function of the three."""
+    assert _splitmix64(0, 3) == [0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4, 0x06c45d188009454f]
+    for seed in (0, 1, 12345, 2 ** 63 + 5):
+        for stream in (1, 2, 5):
+            state = _mix((seed * GAMMA + stream * 0xd1b54a32d192ed03 + 0x632be59bd9b4e019) & M64)
+            assert [gen.draw(seed, stream, i) for i in range(20)] == _splitmix64(state, 20), (seed, stream)
+    assert gen.draw(7, 1, 1000) == gen.draw(7, 1, 1000)          # no hidden state between calls
+    assert gen.unit(7, 1, 3) == (gen.draw(7, 1, 3) >> 11) / 2.0 ** 53
