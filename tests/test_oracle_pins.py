@@ -640,18 +640,29 @@ def test_ldd_cut_probability_within_the_exponential_shift_bound(shape, beta):
     The mean cut fraction over seeded draws must stay within that bound plus
     three standard errors. Every centre is also its own centre: a vertex u
     that beat c at c would, by the triangle inequality and the smaller-id tie
-    rule, also beat c at every vertex that chose c."""
+    rule, also beat c at every vertex that chose c. And since a vertex's
+    centre beat the vertex itself, hop(c, v) <= delta_c - delta_v, with the
+    hops taken from scipy's breadth-first search."""
     from paper_2405_11671_amd import gen
     p = gen.grid_pairs(60, 60, 0.0, seed=1) if shape == "grid" else gen.rmat_pairs(12, 8, seed=3)
     og = oracle.Graph.from_pairs(p)
     src, dst = np.asarray(p.src), np.asarray(p.dst)
     src, dst = src[src != dst], dst[src != dst]
+    A = sp.coo_matrix((np.ones(src.size), (src, dst)), shape=(og.n, og.n)).tocsr()
     fractions = []
     for seed in range(16):
         delta = np.random.default_rng(seed).exponential(1.0 / beta, og.n)
         c = og.ldd(delta)
         assert np.array_equal(c[c], c)
         fractions.append(np.mean(c[src] != c[dst]))
+        centres, size = np.unique(c, return_counts=True)
+        big = centres[size > 1]                 # a singleton cluster meets the bound with hop 0
+        if seed < 2:
+            # a centre beat the vertex itself: hop(c, v) <= delta_c - delta_v
+            D = csg.shortest_path(A, directed=False, unweighted=True, indices=big)
+            vs = np.flatnonzero(np.isin(c, big))
+            hop = D[np.searchsorted(big, c[vs]), vs]
+            assert np.all(hop <= delta[c[vs]] - delta[vs] + 1e-9), (shape, beta, seed)
     mean = float(np.mean(fractions))
     se = float(np.std(fractions)) / math.sqrt(len(fractions))
     assert mean <= 1.0 - math.exp(-beta) + 3.0 * se, (shape, beta, mean, se)
