@@ -194,6 +194,35 @@ def test_pagerank_closed_forms():
     assert np.allclose(p[1:], (1 - pc) / k, rtol=0, atol=1e-14)
 
 
+def test_pagerank_closed_forms_at_scale():
+    """A star is a two-state chain: the centre receives every leaf's whole
+    mass and the leaves share the centre's, so from the uniform start
+    p_c(t + 1) = (1 - d)/n + d (1 - p_c(t)), that is
+    p_c(T) = p* + (1/n - p*)(-d)^T with p* = ((1 - d)/n + d)/(1 + d), and each
+    leaf holds (1 - p_c)/k. A 4-regular torus keeps the uniform vector at every
+    step. Both at sizes where an indexing or accumulation slip would show."""
+    k, d = 200_000, 0.85
+    n = k + 1
+    g = oracle.Graph(n, np.zeros(k, np.int32), np.arange(1, n, dtype=np.int32))
+    ps = ((1 - d) / n + d) / (1 + d)
+    # the centre sums k terms of total mass <= 1 in sequence: rounding within
+    # (k - 1) u (Higham's bound for recursive summation, u = 2^-53); a dropped
+    # or misplaced term would move it by at least 1/n
+    tol_c = 2 * k * 2.0 ** -53
+    for T in (1, 2, 5, 20):
+        p = g.pagerank(d, T)
+        pc = ps + (1.0 / n - ps) * (-d) ** T
+        assert abs(p[0] - pc) < tol_c, T
+        assert np.max(np.abs(p[1:] - (1 - pc) / k)) < 2 * tol_c / k, T
+    R, C = 300, 300
+    v = np.arange(R * C, dtype=np.int32)
+    right = (v // C) * C + (v % C + 1) % C
+    down = (v + C) % (R * C)
+    t = oracle.Graph(R * C, np.concatenate([v, v]), np.concatenate([right, down]).astype(np.int32))
+    assert np.all(t.degrees() == 4)
+    assert np.max(np.abs(t.pagerank(d, 20) - 1.0 / (R * C))) < 1e-18
+
+
 def test_pagerank_one_step_exact_fractions():
     # path 0-1-2 plus isolated 3, one step from 1/4 each, in exact rationals
     g, _, _ = G(4, [(0, 1), (1, 2)])
