@@ -287,6 +287,28 @@ byo_status byo_edge_map(byo_graph *g, byo_vset *U, byo_edge_fn F, const void *F_
  * neighbour at depth - 1 (parent[src] = src, -1 unreached). */
 byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
                    void *stream, byo_run_stats *stats);
+/* BFS for callers that cannot allocate: code recorded under stream capture,
+ * tight serving loops and harnesses that forbid hipMalloc. Same result
+ * conventions, level loop and kernels as byo_bfs (host-driven CSR levels,
+ * selector as opts chooses), but it allocates no device or pinned host
+ * memory and does not touch the graph's lazily allocated workspace: every
+ * per-run buffer (visited and frontier bitmaps, frontier lists, the frontier
+ * degree scan, block partials, level counters) lives in one device array of
+ * the library's, about 34 MiB, that each device the library runs on keeps
+ * until the process ends. Limits and errors:
+ *  - n must be at most BYO_NOALLOC_MAX_N (2^21), else BYO_EINVAL;
+ *  - opts (nullable) must leave use_graph, small_frontier, compressed and
+ *    api_omit at 0 (those paths allocate), else BYO_EINVAL;
+ *  - the graph must live on the current device, else BYO_EINVAL;
+ *  - level records and kernel timers are not kept for this call.
+ * Every call on one device shares that device's array, and the array keeps
+ * the last call's contents (each call re-initialises what it reads): calls
+ * that overlap on one device, from several streams or threads, race and give
+ * wrong results. The call reads a few counters back per level, so it
+ * synchronises `stream` like byo_bfs. */
+#define BYO_NOALLOC_MAX_N (1 << 21)
+byo_status byo_bfs_noalloc(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_parent, const byo_opts *opts,
+                           void *stream, byo_run_stats *stats);
 /* Connectivity by min-label propagation over edgeMap: label[v] = smallest
  * vertex ID in v's component. With tiled = 1, dense rounds run over the tile
  * layout, and a vertex whose label drops also lowers the vertex its old label

@@ -16,7 +16,7 @@ from ._lib import (API_CONFIGS, API_NO_DEGREE, API_NO_EARLY_EXIT, API_NO_NUM_EDG
                    V_PULL_THREAD, V_PULL_WAVE, V_PUSH_BUCKET, V_PUSH_EDGE, V_PUSH_THREAD, V_PUSH_WAVE, VARIANTS,
                    default_opts)
 
-__all__ = ["Graph", "VSet", "bfs", "cc", "pagerank", "edge_map", "csr_from_pairs", "default_opts", "ByoError",
+__all__ = ["Graph", "VSet", "bfs", "bfs_noalloc", "cc", "pagerank", "edge_map", "csr_from_pairs", "default_opts", "ByoError",
            "VARIANTS", "NUM_VARIANTS", "API_CONFIGS"]
 
 
@@ -240,6 +240,16 @@ def bfs(g: Graph, src: int, opts=None, depth=None, parent=None, **kw):
                                    _stream(),
                                    ctypes.byref(stt)))
     return depth[: g.n], parent[: g.n], stt.as_dict()
+
+
+def bfs_noalloc(g: Graph, src: int, depth, parent, opts=None, **kw):
+    """BFS that allocates nothing (byo_bfs_noalloc) into caller-owned int32
+    device tensors of at least n elements; returns the run statistics."""
+    o = _opts(opts, kw)
+    stt = _lib.RunStats()
+    _lib.check(_lib.load().byo_bfs_noalloc(g.handle, int(src), _ptr(depth, g.n, 4), _ptr(parent, g.n, 4),
+                                           ctypes.byref(o), _stream(), ctypes.byref(stt)))
+    return stt.as_dict()
 
 
 def cc(g: Graph, opts=None, label=None, **kw):

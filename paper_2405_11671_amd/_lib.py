@@ -32,6 +32,7 @@ API_CONFIGS = {
 }
 F_BFS, F_CC_MIN, F_PR_ACC = 0, 1, 2
 HOST_INPUT, DEVICE_COPY, DEVICE_BORROW, VALIDATE = 0x1, 0x2, 0x4, 0x8
+NOALLOC_MAX_N = 1 << 21  # BYO_NOALLOC_MAX_N
 
 STATUS = {0: "BYO_OK", -1: "BYO_EINVAL", -2: "BYO_ENOMEM", -3: "BYO_EHIP", -4: "BYO_ELIMIT", -5: "BYO_ESTATE"}
 
@@ -137,6 +138,7 @@ SIGNATURES = {
     "byo_vset_to_bitmap": (st, [vp, vp, vp]),
     "byo_edge_map": (st, [vp, vp, i32, vp, vp, i32, ctypes.POINTER(Opts), vp, i32p]),
     "byo_bfs": (st, [vp, i64, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
+    "byo_bfs_noalloc": (st, [vp, i64, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_cc": (st, [vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_pagerank": (st, [vp, dbl, i32, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
 }

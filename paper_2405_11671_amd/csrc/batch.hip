@@ -130,7 +130,7 @@ byo_status byo_batch_bfs(byo_batch *b, const int64_t *h_srcs, int32_t *d_depth, 
   if (o.use_graph && o.api_omit == 0 && !o.compressed)
     BYO_TRY(bfs_graph_run(b->g, srcs, d_depth, d_parent, o, s, stats));
   else
-    BYO_TRY(bfs_run(b->g, srcs, d_depth, d_parent, o, s, stats));
+    BYO_TRY(bfs_run(b->g, srcs.data(), (int64_t)srcs.size(), d_depth, d_parent, o, s, stats));
   return localize(b, d_parent, s);
 }
 

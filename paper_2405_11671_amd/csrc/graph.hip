@@ -33,8 +33,16 @@ byo_status hip_fail(hipError_t e, const char *what, const char *file, int line) 
 constexpr size_t SYNC_STAGE_BYTES = 1 << 16;
 static thread_local void *g_stage = nullptr;
 
+// Calls made inside a no_alloc_scope (noalloc.hip) must not allocate: their
+// reads go straight to the caller's memory (a pageable copy), and level
+// records and kernel timers, which take events from a pool, are off.
+static thread_local int g_noalloc = 0;
+bool noalloc_active() { return g_noalloc > 0; }
+no_alloc_scope::no_alloc_scope() { ++g_noalloc; }
+no_alloc_scope::~no_alloc_scope() { --g_noalloc; }
+
 byo_status sync_read(hipStream_t s, const void *d_src, void *h_dst, size_t bytes) {
-  if (bytes <= SYNC_STAGE_BYTES) {
+  if (bytes <= SYNC_STAGE_BYTES && !noalloc_active()) {
     if (!g_stage) BYO_HIP(hipHostMalloc(&g_stage, SYNC_STAGE_BYTES, hipHostMallocDefault));
     BYO_HIP(hipMemcpyAsync(g_stage, d_src, bytes, hipMemcpyDeviceToHost, s));
     BYO_HIP(hipStreamSynchronize(s));

@@ -324,6 +324,16 @@ int64_t compaction_blocks(int64_t words);
 byo_status fill_i32(int32_t *p, int64_t count, int32_t value, hipStream_t s);
 byo_status fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 byo_status sync_read(hipStream_t s, const void *d_src, void *h_dst, size_t bytes);
+// While one of these is alive on a thread, the library's helpers on that
+// thread allocate nothing: sync_read copies into pageable caller memory and
+// the optional level records and kernel timers stay off (graph.hip).
+struct no_alloc_scope {
+  no_alloc_scope();
+  ~no_alloc_scope();
+  no_alloc_scope(const no_alloc_scope &) = delete;
+  no_alloc_scope &operator=(const no_alloc_scope &) = delete;
+};
+bool noalloc_active();
 
 // the same over an explicit degree array
 byo_status scan_degrees(const int32_t *deg, const int32_t *ids, int64_t k, long long *scan, long long *partial,
@@ -460,7 +470,7 @@ byo_status bfs_sources_init(byo_graph *g, const int32_t *d_srcs, int64_t ns, int
                             hipStream_t s);
 
 // BFS from distinct sources (traverse.hip)
-byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
+byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,
                    const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 // learned selector (selector.hip)

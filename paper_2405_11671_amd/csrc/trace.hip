@@ -23,8 +23,8 @@ int64_t g_launches[BYO_K_COUNT] = {0};
 double g_ms[BYO_K_COUNT] = {0};
 }  // namespace
 
-bool trace_on() { return g_trace_on; }
-bool ktimer_on() { return g_ktimer_on; }
+bool trace_on() { return g_trace_on && !noalloc_active(); }
+bool ktimer_on() { return g_ktimer_on && !noalloc_active(); }
 
 hipEvent_t event_get() {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -50,7 +50,7 @@ void trace_push(const byo_level_record &r) {
 }
 
 ktimer_scope::ktimer_scope(int fam, hipStream_t st) : family(fam), s(st) {
-  if (!g_ktimer_on || !((g_ktimer_mask >> fam) & 1u)) return;
+  if (!ktimer_on() || !((g_ktimer_mask >> fam) & 1u)) return;
   a = event_get();
   if (a) (void)hipEventRecord(a, s);
 }

@@ -245,12 +245,11 @@ byo_status bfs_sources_init(byo_graph *g, const int32_t *d_srcs, int64_t ns, int
 
 // BFS from a set of distinct sources (a single source, or one per graph of a
 // batch laid out as a disjoint union).
-byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_depth, int32_t *d_parent,
+byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,
                    const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
   BYO_TRY(ws_ensure_traversal(g));
   byo_workspace &w = g->ws;
   int64_t n = g->n;
-  int64_t ns = (int64_t)srcs.size();
   api_scope api(g, o.api_omit);
   BYO_TRY(api.begin(s));
   BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
@@ -259,7 +258,7 @@ byo_status bfs_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t *d_de
   BYO_TRY(fill_i32(d_parent, n, -1, s));
   BYO_TRY(fill_i32(d_depth, n, -1, s));
   // sources staged through the spare frontier list
-  BYO_HIP(hipMemcpyAsync(w.ids[1], srcs.data(), sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
+  BYO_HIP(hipMemcpyAsync(w.ids[1], srcs, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
   bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
       w.visited, g->zero_bits, n, w.words, srcs[0]);
   bfs_visited_sources_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(w.visited, w.ids[1], ns);
@@ -384,7 +383,7 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   if (opts) o = *opts;
   std::vector<int32_t> srcs(1, (int32_t)src);
   if (o.use_graph && o.api_omit == 0 && !o.compressed) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
-  return bfs_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
+  return bfs_run(g, srcs.data(), (int64_t)srcs.size(), d_depth, d_parent, o, (hipStream_t)stream, stats);
 }
 
 byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *stream, byo_run_stats *stats) {
