@@ -56,13 +56,19 @@ def test_bfs_cc_rmat22_full(rmat22):
         assert np.array_equal(lab.cpu().numpy(), want), tiled
 
 
+# eight columns in each of the four 64-source words of the benchmark's
+# 256-source batch (first and last lane of every word included)
+MS_COLUMNS = [64 * w + j for w in range(4) for j in (0, 9, 18, 27, 36, 45, 54, 63)]
+
+
 def test_msbfs_rmat22_sampled_columns(rmat22):
     p, g, og = rmat22
     srcs = gen.pick_sources(p, 256, seed=2)
-    for tiled in (0, 1):
+    assert len(srcs) == 256
+    want = {j: og.bfs(int(srcs[j]))[0] for j in MS_COLUMNS}
+    for tiled in (1, 0):
         D, st = byo.msbfs(g, srcs, tiled=tiled)
         D = D.cpu().numpy()
-        for j in (0, 63, 64, 200, 255):
-            want, _ = og.bfs(int(srcs[j]))
-            assert np.array_equal(D[:, j], np.where(want < 0, 255, want)), (tiled, j)
+        for j in MS_COLUMNS:
+            assert np.array_equal(D[:, j], np.where(want[j] < 0, 255, want[j])), (tiled, j)
         assert st["reached"] == int((D != 255).sum())
