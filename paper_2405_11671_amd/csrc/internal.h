@@ -203,6 +203,14 @@ struct byo_graph {
   int64_t max_deg = 0, isolated = 0;
   double mean_deg = 0.0, cv_deg = 0.0;
   byo_workspace ws;
+  // batch updates (update.hip): an update writes the new CSR into the spare
+  // arrays and swaps them in; the previous arrays, when the graph owns them,
+  // become the spares of the next update
+  int64_t nbr_cap = 0;             // entries the current nbr array holds
+  int64_t *spare_off = nullptr;    // [n + 1]
+  int32_t *spare_nbr = nullptr;    // [spare_cap]
+  int64_t spare_cap = 0;
+  void *upd = nullptr;             // the update path's buffers
 };
 
 // vertexSubset: which representations are current is tracked by flags.
@@ -222,6 +230,12 @@ struct byo_vset {
 namespace byo {
 
 byo_status ws_ensure_traversal(byo_graph *g);
+// degree array, degree-0 bitmap and statistics (max degree, isolated count,
+// mean, coefficient of variation) from the current offsets; d_tmp: 8 device
+// words of scratch. Syncs (graph.hip).
+byo_status graph_refresh_stats(byo_graph *g, unsigned long long *d_tmp, hipStream_t s);
+// buffers of the batch-update path (update.hip)
+void upd_free(void *p);
 byo_status ws_ensure_pagerank(byo_graph *g, hipStream_t s);
 void ws_free(byo_workspace &ws);
 void ms_release(byo_workspace &ws);
@@ -250,13 +264,13 @@ struct byo_tiles {
   int32_t *rnbr = nullptr;    // [m] its neighbours, relabelled
   void *partial = nullptr;    // chunk results, sized by the user (tiles_partial)
   size_t partial_bytes = 0;
-  // PageRank apply plan: one word per apply workgroup, its first relabelled
-  // vertex with bit 0 set for a many-chunk tile (64 vertices, chunk sums
-  // split four ways) and clear otherwise (1024 vertices); adpart holds one
-  // dangling partial per apply workgroup.
+  // PageRank apply plan over the tiles cut into several chunks: one word per
+  // apply workgroup, its first relabelled vertex with bit 0 set for a
+  // many-chunk tile (64 vertices, chunk sums split four ways) and clear
+  // otherwise (1024 vertices).
   int32_t *aplan = nullptr;   // [napply]
-  float *adpart = nullptr;    // [napply]
   int64_t napply = 0;
+  int64_t wtail = 0;          // first relabelled vertex of the trailing tiles without entries (n if none)
 };
 // Relabelled source and tile-local destination of entry e. The caller's
 // wavefront reads one whole group (e / 64 is the same in every lane), so the
@@ -286,8 +300,9 @@ byo_status cc_tiled_run(byo_graph *g, int32_t *d_label, const byo_opts &o, hipSt
 void tiles_release(byo_workspace &w);
 // tiled PageRank step (pagerank_tile.hip); opt = byo_opts::pr_blocked
 int pr_tile_shift(const byo_graph *g, int32_t opt);
-byo_status pr_tile_step(byo_graph *g, byo_tiles *p, const float *contrib, float damping, float *contrib_next,
-                        float *out, const float *dpart_in, int64_t nparts_in, hipStream_t s);
+// bs = the step constant (1-d)/n + d*D/n
+byo_status pr_tile_step(byo_graph *g, byo_tiles *p, const float *contrib, float bs, float damping,
+                        float *contrib_next, float *out, hipStream_t s);
 
 // container-API ablation (api.hip): degree / num_edges obtained without the
 // container's degree() / num_edges(), and the variants the parallel-map
@@ -475,6 +490,9 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 // learned selector (selector.hip)
 bool selector_ready();
+// Device copy of the installed weights (params, mu, sd) on the current
+// device, or null; *version changes whenever weights are set or cleared.
+const float *selector_device_weights(uint64_t *version);
 // Learned choice for one level, computed on the host from the level's
 // features (the host-driven loop holds them already); -1 if no weights are
 // installed or the prediction is not finite.

@@ -400,11 +400,18 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     // the tiled step runs in the layout's relabelled vertex order
     pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(tl->rdeg, n, w.words, w.contrib[0], w.dpart);
     BYO_HIP(hipGetLastError());
+    // The degree-0 vertices receive nothing, so each holds the step constant
+    // after every step (1/n before the first): the dangling mass D is their
+    // count times it, and the constants follow on the host, in double.
+    const double nd = (double)n, n0 = (double)g->isolated;
+    double p_iso = 1.0 / nd;
     int c = 0;
     for (int32_t t = 0; t < iters; ++t) {
       bool last = t + 1 == iters;
-      BYO_TRY(pr_tile_step(g, tl, w.contrib[c], (float)damping, last ? nullptr : w.contrib[1 - c],
-                           last ? d_rank : nullptr, t == 0 ? w.dpart : tl->adpart, t == 0 ? nb : tl->napply, s));
+      const double bs = (1.0 - damping) / nd + damping * (n0 * p_iso) / nd;
+      BYO_TRY(pr_tile_step(g, tl, w.contrib[c], (float)bs, (float)damping, last ? nullptr : w.contrib[1 - c],
+                           last ? d_rank : nullptr, s));
+      p_iso = bs;
       c = 1 - c;
     }
     return BYO_OK;

@@ -36,7 +36,7 @@ bool tiles_wanted(const byo_graph *g) { return g->n >= (1ll << 16) && g->m >= 4 
 
 static void tiles_free(byo_tiles *p) {
   void *d[] = {p->ent, p->anchor, p->rdeg, p->orig, p->cbeg, p->bfirst, p->cblk, p->cflag, p->rlabel,
-               p->scratch, p->partial, p->roff, p->rnbr, p->aplan, p->adpart};
+               p->scratch, p->partial, p->roff, p->rnbr, p->aplan};
   for (void *x : d)
     if (x) (void)hipFree(x);
   delete p;
@@ -318,19 +318,25 @@ static byo_status tiles_build(const byo_graph *g, byo_tiles *p, hipStream_t s) {
   BYO_HIP(hipMemcpyAsync(p->cbeg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice, s));
   BYO_HIP(hipMemcpyAsync(p->bfirst, bfirst.data(), sizeof(int32_t) * bfirst.size(), hipMemcpyHostToDevice, s));
   BYO_HIP(hipMemcpyAsync(p->cblk, cblk.data(), sizeof(int32_t) * cblk.size(), hipMemcpyHostToDevice, s));
-  // PageRank apply plan: a tile with more than 8 chunks (the highest-degree
-  // destinations) gets 64-vertex workgroups so that its many chunk sums are
-  // spread over many workgroups; the others get 1024-vertex workgroups
+  // PageRank apply plan, over the tiles cut into several chunks (a tile of
+  // one chunk is finished by its chunk's workgroup): a tile with more than 8
+  // chunks (the highest-degree destinations) gets 64-vertex workgroups so
+  // that its many chunk sums are spread over many workgroups; the others get
+  // 1024-vertex workgroups
   std::vector<int32_t> plan;
+  int64_t btail = nblk;  // tiles from btail on have no entries
+  while (btail > 0 && bfirst[(size_t)btail] == bfirst[(size_t)btail - 1]) --btail;
+  p->wtail = std::min<int64_t>(n, btail << shift);
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t k = bfirst[(size_t)b + 1] - bfirst[(size_t)b];
+    if (k <= 1) continue;
     const int64_t v0 = b << shift, v1 = std::min<int64_t>(n, (b + 1) << shift);
     for (int64_t v = v0; v < v1; v += k > 8 ? 64 : 1024) plan.push_back((int32_t)v | (k > 8 ? 1 : 0));
   }
   p->napply = (int64_t)plan.size();
-  BYO_HIP(hipMalloc(&p->aplan, sizeof(int32_t) * plan.size()));
-  BYO_HIP(hipMalloc(&p->adpart, sizeof(float) * plan.size()));
-  BYO_HIP(hipMemcpyAsync(p->aplan, plan.data(), sizeof(int32_t) * plan.size(), hipMemcpyHostToDevice, s));
+  BYO_HIP(hipMalloc(&p->aplan, sizeof(int32_t) * std::max<size_t>(plan.size(), 1)));
+  if (!plan.empty())
+    BYO_HIP(hipMemcpyAsync(p->aplan, plan.data(), sizeof(int32_t) * plan.size(), hipMemcpyHostToDevice, s));
   // the temporaries and the host vectors must outlive the queued work
   BYO_HIP(hipStreamSynchronize(s));
   return BYO_OK;
