@@ -14,11 +14,13 @@ Single-source BFS from 16 sources is timed separately, with the threshold
 heuristic ("plain") and with the learned selector, and reported in "detail"
 next to the batched rate.
 
-Prints ONE JSON line. `--probe pr` instead runs a few PageRank steps and a
-plain 512 MiB device copy, for hardware-counter runs (bytes per dispatch).
+Prints ONE JSON line. `--probe pr|ms|cc|all` instead runs a few tiled
+PageRank steps, multi-source BFS or connectivity calls and a plain 512 MiB
+device copy, for hardware-counter runs (bytes per dispatch).
 `--ablation` instead replays the container-API configurations of the paper's
-Table api-components-avg, and `--compression` compares the byte-coded CSR with
-the CSR (one JSON line of per-case times and slowdowns each).
+Table api-components-avg, `--compression` compares the byte-coded CSR with
+the CSR (one JSON line of per-case times and slowdowns each), and `--inserts`
+measures batch-insert throughput against batch size.
 """
 from __future__ import annotations
 
@@ -360,13 +362,85 @@ def container_study(byo, gen, args, configs, base_name, title, unit, extra_algos
           flush=True)
 
 
-def probe_pr(g, n, iters):
+def insert_study(byo, gen, args):
+    """Batch-insert throughput against batch size (Section 6.6, fig
+    inserts_with_sort): on the RMAT graph of the benchmark (the stand-in for
+    the paper's billion-edge base graph), a batch of pairs drawn from an RMAT
+    generator with (a, b, c, d) = (0.5, 0.1, 0.1, 0.3) is inserted and then
+    deleted, three times per batch size; edges per second = batch pairs / time
+    of the call (the batch's sort included, as in the paper's measurement).
+    The three batch forms are timed on the same batches."""
+    import torch
+    pairs = gen.rmat_pairs(args.scale, 16, gen.GRAPH500_ABCD, seed=1, permute=True)
+    off, nbr = byo.csr_from_pairs(pairs.n, pairs.src, pairs.dst)
+    n = pairs.n
+    del pairs
+    torch.cuda.init()
+    g = byo.Graph.from_csr(off, nbr)
+    m0 = g.m
+    del off, nbr
+    sizes = [10 ** e for e in range(1, 9)]
+    big = gen.rmat_pairs(args.scale, max(1, sizes[-1] >> args.scale) + 1, (0.5, 0.1, 0.1, 0.3), seed=9)
+    src_all = torch.from_numpy(big.src).to("cuda")
+    dst_all = torch.from_numpy(big.dst).to("cuda")
+    del big
+    cases = []
+    for k in sizes:
+        s_, d_ = src_all[:k].contiguous(), dst_all[:k].contiguous()
+        ins, dele, added = [], [], []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            added.append(g.insert_batch(s_, d_))
+            torch.cuda.synchronize()
+            ins.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            g.delete_batch(s_, d_)
+            torch.cuda.synchronize()
+            dele.append(time.perf_counter() - t)
+        forms = {}
+        for name, form in (("sort", byo.FORM_SORT), ("semisort", byo.FORM_SEMISORT),
+                           ("grouped_sort", byo.FORM_GROUPED_SORT)):
+            byo.batch_order(s_, d_, n, form)
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                byo.batch_order(s_, d_, n, form)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            forms[name] = round(float(np.median(ts)) * 1e3, 4)
+        ti, td = float(np.median(ins)), float(np.median(dele))
+        cases.append({"batch": k, "insert_ms": round(ti * 1e3, 4), "delete_ms": round(td * 1e3, 4),
+                      "insert_edges_per_s": round(k / ti, 1), "delete_edges_per_s": round(k / td, 1),
+                      "entries_added": int(np.median(added)), "m_after": g.m, "order_ms": forms})
+        log(f"[inserts] batch {k}: insert {ti * 1e3:.3f} ms ({k / ti:.3g} edges/s), delete {td * 1e3:.3f} ms")
+    print(json.dumps({"study": "batch inserts (Section 6.6)", "unit": "edges/s",
+                      "graph": f"rmat-{args.scale} n={n} m={m0}", "cases": cases}), flush=True)
+
+
+def probe(g, n, what, ms_srcs, iters=3):
+    """Short runs for hardware-counter passes (bytes per dispatch): the tiled
+    PageRank (a 1-step call that builds the layout, then an `iters`-step
+    call), the tiled 256-source BFS and the tiled connectivity (each once to
+    warm up, once more), then a plain 512 MiB elementwise kernel to calibrate
+    the counters."""
     import torch
     import paper_2405_11671_amd as byo
-    rank = torch.empty(n, dtype=torch.float32, device="cuda")
-    byo.pagerank(g, 0.85, 1, rank=rank, pr_blocked=1)    # builds the tile layout
-    torch.cuda.synchronize()
-    byo.pagerank(g, 0.85, iters, rank=rank, pr_blocked=1)
+    tiled = byo.default_opts(pr_blocked=1, tiled=1)
+    if what in ("pr", "all"):
+        rank = torch.empty(n, dtype=torch.float32, device="cuda")
+        byo.pagerank(g, 0.85, 1, rank=rank, opts=tiled)    # builds the tile layout
+        torch.cuda.synchronize()
+        byo.pagerank(g, 0.85, iters, rank=rank, opts=tiled)
+    if what in ("ms", "all"):
+        depth = torch.empty(n * len(ms_srcs), dtype=torch.uint8, device="cuda")
+        for _ in range(2):
+            byo.msbfs(g, ms_srcs, opts=tiled, depth=depth)
+    if what in ("cc", "all"):
+        label = torch.empty(n, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            byo.cc(g, opts=tiled, label=label)
     # calibration: an elementwise kernel that reads 512 MiB and writes 512 MiB
     a = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -374,7 +448,7 @@ def probe_pr(g, n, iters):
     torch.cuda.synchronize()
     torch.neg(a, out=b)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "pr", "iters": iters, "copy_bytes": 512 << 20}), flush=True)
+    print(json.dumps({"probe": what, "iters": iters, "copy_bytes": 512 << 20}), flush=True)
 
 
 def parse():
@@ -390,14 +464,17 @@ def parse():
     ap.add_argument("--cpu-sample-sources", type=int, default=6)
     ap.add_argument("--cpu-sample-pr-iters", type=int, default=6)
     ap.add_argument("--verbose", action="store_true")
-    ap.add_argument("--probe", choices=["pr"], default=None)
+    ap.add_argument("--probe", choices=["pr", "ms", "cc", "all"], default=None)
     ap.add_argument("--ablation", action="store_true",
                     help="replay the container-API configurations instead of the benchmark step")
     ap.add_argument("--compression", action="store_true",
                     help="compare the byte-coded CSR with the CSR instead of the benchmark step")
+    ap.add_argument("--inserts", action="store_true",
+                    help="batch-insert throughput against batch size instead of the benchmark step")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-bc", action="store_true", help="skip the betweenness, k-core and MIS detail")
+    ap.add_argument("--no-bc", action="store_true", help="skip the betweenness and k-core detail")
+    ap.add_argument("--mis", action="store_true", help="also time greedy MIS and colouring (outside the hot path)")
     ap.add_argument("--grid-side", type=int, default=4096)
     ap.add_argument("--no-tiles", action="store_true",
                     help="PageRank and multi-source BFS over the CSR instead of the tile layout")
@@ -417,6 +494,9 @@ def main():
     import paper_2405_11671_amd as byo
     from paper_2405_11671_amd import gen
 
+    if args.inserts:
+        insert_study(byo, gen, args)
+        return
     if args.ablation or args.compression:
         torch.cuda.init()
         (api_ablation if args.ablation else compression_study)(byo, gen, args)
@@ -430,8 +510,8 @@ def main():
     torch.cuda.init()
     g = byo.Graph.from_csr(off, nbr)
     torch.cuda.synchronize()
-    if args.probe == "pr":
-        probe_pr(g, n, 3)
+    if args.probe:
+        probe(g, n, args.probe, gen.pick_sources(pairs, args.ms_sources, seed=2))
         return
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -532,10 +612,30 @@ def main():
     cc_ms = float(np.median([r["cc_ms"] for r in rec]))
     pr_launches, pr_kms = kt["pr_pull"]
     pr_avg_ms = (pr_kms + kt["pr_chunk"][1]) / max(pr_launches, 1)   # tile kernel + apply kernel per step
-    pr_bytes = 4 * m + 16 * n + 8          # per step: neighbours, offsets, contrib read + write, rank write
+    # compulsory bytes of one PageRank step (the hot-path scope's count): the
+    # neighbour lists 4m, the offsets 8(n+1), the rank or contribution read
+    # 4n, the contribution write and read 8n, the rank write 4n
+    pr_bytes = 4 * m + 8 * (n + 1) + 16 * n
+    # what the tiled step itself must touch: entry words 4m, relabelled degrees,
+    # contributions read and written (no offsets: the layout has none)
+    pr_bytes_tiled = 4 * m + 12 * n
+    # the other tile passes of the step, per launch, from the untimed step's
+    # kernel timers: a dense multi-source level and a tiled connectivity round
+    # each stream the entry words once (4m); connectivity also reads each
+    # label once (4n). Lower bounds on their bytes.
+    fam_bytes = {"msbfs_pull": (4 * m, "4m: one pass over the entry words"),
+                 "cc_pull": (4 * m + 4 * n, "4m + 4n: the entry words and each label once")}
+    family_roofline = {}
+    for fam, (nbytes, model) in fam_bytes.items():
+        launches, kms = kt_all.get(fam, (0, 0.0))
+        if launches:
+            avg = kms / launches
+            family_roofline[fam] = {"launches": launches, "avg_launch_ms": round(avg, 4), "bytes_model": model,
+                                    "achieved_gbs": round(nbytes / (avg * 1e-3) / 1e9, 1),
+                                    "frac": round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     bc = None if args.no_bc else bc_workload(byo, g, srcs[:4])
     kcore = None if args.no_bc else kcore_workload(byo, g)
-    mis = None if args.no_bc else mis_workload(byo, g)
+    mis = mis_workload(byo, g) if args.mis else None
     grid = None if args.no_grid else grid_workload(byo, gen, mlp_opts, args.grid_side)
     batch = None if args.no_batch else batch_workload(byo, gen)
     detail = {
@@ -551,8 +651,11 @@ def main():
         "learned_vs_plain": float(np.median(learned)) / float(np.median(plain)),
         "batched_vs_plain": rec[0]["ms_edges"] / (ms_ms * 1e-3) / 1e9 / float(np.median(plain)),
         "pr_step_avg_ms": pr_avg_ms, "pr_step_alg_gbs": pr_bytes / (pr_avg_ms * 1e-3) / 1e9,
+        "pr_step_tiled_bytes": pr_bytes_tiled,
+        "pr_step_tiled_frac": pr_bytes_tiled / (pr_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "tile_layout_build_s": layout_s, "tiled": not args.no_tiles,
         "kernel_ms": {f: round(v[1], 3) for f, v in kt_all.items() if v[0]},
+        "family_roofline": family_roofline,
         "bc": bc,
         "kcore": kcore,
         "mis": mis,

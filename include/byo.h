@@ -95,7 +95,9 @@ typedef struct byo_opts {
                              plus 24 per vertex of device memory) and kept with the graph,
                              one layout per tile size. */
   int32_t use_graph;      /* BFS: 1 = device-side level control replayed from a captured
-                             hipGraph (threshold rule on the device), 0 = host loop (default) */
+                             hipGraph (push or pull chosen on the device: the threshold
+                             rule, or with selector = BYO_SEL_MLP the learned network
+                             evaluated there), 0 = host loop (default) */
   int32_t tiled;          /* multi-source BFS and connectivity: 1 = dense levels / rounds over
                              the degree-ordered tile layout (the kind PageRank's pr_blocked
                              uses; multi-source BFS always with tiles of 2^12 vertices) when
@@ -203,10 +205,57 @@ byo_status byo_get_neighbors(const byo_graph *g, int64_t v, int32_t *h_buf, int6
 /* Device pointers to the CSR arrays and the int32 degree array deg[n]. */
 byo_status byo_graph_arrays(const byo_graph *g, const int64_t **d_off, const int32_t **d_nbr,
                             const int32_t **d_deg);
-/* Degree statistics computed at creation: max degree, number of isolated
- * vertices, mean and coefficient of variation of the degree. */
+/* Host copies of the CSR: h_off (n + 1 int64) and h_nbr (m int32), caller
+ * owned (after batch updates, the updated container). Waits for the device. */
+byo_status byo_graph_copy(const byo_graph *g, int64_t *h_off, int32_t *h_nbr);
+/* Degree statistics computed at creation (and after each batch update): max
+ * degree, number of isolated vertices, mean and coefficient of variation of
+ * the degree. */
 byo_status byo_graph_stats(const byo_graph *g, int64_t *max_deg, int64_t *isolated, double *mean,
                            double *cv);
+
+/* ------------------------------------------------------------------------
+ * Batch updates (Section 4.1, "Translating graph batch-update API into the
+ * set API", and Section 4.2, "Required functionality for updates": the
+ * container's insert_sorted_batch / delete_sorted_batch, the framework
+ * sorting the batch first).
+ *
+ * A batch is k pairs (d_src[i], d_dst[i]) in device memory (int32; caller
+ * owned, only read). Each pair with src != dst names the undirected edge
+ * {src, dst}: both directions are inserted or deleted together, so the
+ * container stays symmetric and simple. Self-pairs change nothing and
+ * repeated pairs act once; inserting an existing edge or deleting a missing
+ * one changes nothing. The graph is updated in place as seen by the caller:
+ * the CSR arrays (byo_graph_arrays), m, the degree array and the statistics
+ * are those of the new edge set afterwards, rows still strictly increasing.
+ * Derived structures (tile layouts, byte-coded lists, captured level graphs,
+ * traversal workspace) are dropped and rebuilt on next use. A graph created
+ * with BYO_DEVICE_BORROW stops using the caller's arrays at its first update
+ * (they are left untouched). *changed (nullable) receives the number of
+ * directed entries added or removed (twice the undirected edges).
+ * Errors: BYO_EINVAL (and the graph unchanged) if a pair names a vertex
+ * outside [0, n) or k < 0; BYO_ENOMEM if the new arrays do not fit.
+ * Syncs `stream`. Cost: the batch's sort plus one pass over the CSR (the rows
+ * shift in the packed arrays), about 8 bytes per entry moved.
+ * ---------------------------------------------------------------------- */
+byo_status byo_graph_insert_batch(byo_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t k,
+                                  void *stream, int64_t *changed);
+byo_status byo_graph_delete_batch(byo_graph *g, const int32_t *d_src, const int32_t *d_dst, int64_t k,
+                                  void *stream, int64_t *changed);
+
+/* The three forms in which the framework can hand a batch to a container
+ * (Section 4.1). Each output holds the input's pairs, each as often:
+ *  - BYO_FORM_SORT: ascending (src, dst), the global sort;
+ *  - BYO_FORM_SEMISORT: the pairs of one source next to each other (here the
+ *    groups come out in ascending source order and a group keeps its pairs'
+ *    input order; other containers may accept any group order);
+ *  - BYO_FORM_GROUPED_SORT: grouped by source, each group ascending by dst.
+ * IDs must lie in [0, n) (else BYO_EINVAL); n < 2^31. Outputs are device
+ * arrays of k int32 the caller owns, distinct from the inputs; every pointer
+ * must be non-null, also for k = 0. Syncs. */
+typedef enum { BYO_FORM_SORT = 0, BYO_FORM_SEMISORT = 1, BYO_FORM_GROUPED_SORT = 2 } byo_batch_form;
+byo_status byo_batch_order(const int32_t *d_src, const int32_t *d_dst, int64_t k, int64_t n, int32_t form,
+                           int32_t *d_out_src, int32_t *d_out_dst, void *stream);
 
 /* ------------------------------------------------------------------------
  * Byte-coded CSR: the compressed container of Section 2 ("compressed

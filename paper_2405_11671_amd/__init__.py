@@ -11,12 +11,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (API_CONFIGS, API_NO_DEGREE, API_NO_EARLY_EXIT, API_NO_NUM_EDGES, API_NO_PAR_EARLY_EXIT,
+from ._lib import (FORM_GROUPED_SORT, FORM_SEMISORT, FORM_SORT, API_CONFIGS, API_NO_DEGREE, API_NO_EARLY_EXIT, API_NO_NUM_EDGES, API_NO_PAR_EARLY_EXIT,
                    API_NO_PAR_MAP, ByoError, F_BFS, F_CC_MIN, F_PR_ACC, NUM_VARIANTS, SEL_FIXED, SEL_HEURISTIC, SEL_MLP,
                    V_PULL_THREAD, V_PULL_WAVE, V_PUSH_BUCKET, V_PUSH_EDGE, V_PUSH_THREAD, V_PUSH_WAVE, VARIANTS,
                    default_opts)
 
-__all__ = ["Graph", "VSet", "bfs", "bfs_noalloc", "cc", "pagerank", "edge_map", "csr_from_pairs", "default_opts", "ByoError",
+__all__ = ["Graph", "VSet", "bfs", "bfs_noalloc", "batch_order", "cc", "pagerank", "edge_map", "csr_from_pairs", "default_opts", "ByoError",
            "VARIANTS", "NUM_VARIANTS", "API_CONFIGS"]
 
 
@@ -158,6 +158,34 @@ class Graph:
         _lib.check(_lib.load().byo_cz_decode(self._h, int(v), _ptr(out), _stream()))
         return out[: self.degree(v)]
 
+    def csr(self):
+        """Host copies (off int64[n+1], nbr int32[m]) of the current CSR."""
+        m = self.num_edges()
+        off = np.empty(self.n + 1, np.int64)
+        nbr = np.empty(max(m, 1), np.int32)
+        _lib.check(_lib.load().byo_graph_copy(self._h, off.ctypes.data, nbr.ctypes.data))
+        return off, nbr[:m]
+
+    def _update(self, fn, src, dst):
+        k = int(src.numel())
+        if int(dst.numel()) != k:
+            raise ValueError("source and target batches differ in length")
+        changed = ctypes.c_int64()
+        _lib.check(fn(self._h, _ptr(src, k, 4) if k else None, _ptr(dst, k, 4) if k else None, k, _stream(),
+                      ctypes.byref(changed)))
+        self.m = self.num_edges()
+        return changed.value
+
+    def insert_batch(self, src, dst) -> int:
+        """Insert the undirected edges {src[i], dst[i]} (int32 device tensors);
+        returns the number of directed entries added."""
+        return self._update(_lib.load().byo_graph_insert_batch, src, dst)
+
+    def delete_batch(self, src, dst) -> int:
+        """Delete the undirected edges {src[i], dst[i]}; returns the number of
+        directed entries removed."""
+        return self._update(_lib.load().byo_graph_delete_batch, src, dst)
+
     def device_arrays(self):
         """(off, nbr, deg) device pointers as ints."""
         o, nb, d = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
@@ -240,6 +268,19 @@ def bfs(g: Graph, src: int, opts=None, depth=None, parent=None, **kw):
                                    _stream(),
                                    ctypes.byref(stt)))
     return depth[: g.n], parent[: g.n], stt.as_dict()
+
+
+def batch_order(src, dst, n: int, form: int):
+    """The batch (int32 device tensors) in one of the three batch forms
+    (FORM_SORT, FORM_SEMISORT, FORM_GROUPED_SORT): new (src, dst) tensors."""
+    torch = _torch()
+    k = int(src.numel())
+    out_s = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
+    out_d = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
+    if k:
+        _lib.check(_lib.load().byo_batch_order(_ptr(src, k, 4), _ptr(dst, k, 4), k, int(n), int(form), _ptr(out_s),
+                                               _ptr(out_d), _stream()))
+    return out_s[:k], out_d[:k]
 
 
 def bfs_noalloc(g: Graph, src: int, depth, parent, opts=None, **kw):

@@ -33,6 +33,8 @@ API_CONFIGS = {
 F_BFS, F_CC_MIN, F_PR_ACC = 0, 1, 2
 HOST_INPUT, DEVICE_COPY, DEVICE_BORROW, VALIDATE = 0x1, 0x2, 0x4, 0x8
 NOALLOC_MAX_N = 1 << 21  # BYO_NOALLOC_MAX_N
+# batch forms (byo_batch_order)
+FORM_SORT, FORM_SEMISORT, FORM_GROUPED_SORT = 0, 1, 2
 
 STATUS = {0: "BYO_OK", -1: "BYO_EINVAL", -2: "BYO_ENOMEM", -3: "BYO_EHIP", -4: "BYO_ELIMIT", -5: "BYO_ESTATE"}
 
@@ -119,6 +121,10 @@ SIGNATURES = {
     "byo_get_neighbors": (st, [vp, i64, vp, i64, i64p]),
     "byo_graph_arrays": (st, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp)]),
     "byo_graph_stats": (st, [vp, i64p, i64p, dblp, dblp]),
+    "byo_graph_copy": (st, [vp, vp, vp]),
+    "byo_graph_insert_batch": (st, [vp, vp, vp, i64, vp, i64p]),
+    "byo_graph_delete_batch": (st, [vp, vp, vp, i64, vp, i64p]),
+    "byo_batch_order": (st, [vp, vp, i64, i64, i32, vp, vp, vp]),
     "byo_bc": (st, [vp, i64, vp, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_kcore": (st, [vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),
     "byo_mis": (st, [vp, vp, vp, ctypes.POINTER(Opts), vp, ctypes.POINTER(RunStats)]),

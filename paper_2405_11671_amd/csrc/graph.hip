@@ -207,6 +207,33 @@ byo_status ws_ensure_traversal(byo_graph *g) {
   return BYO_OK;
 }
 
+// statistics from degree_stats_kernel's {max degree, degree-0 count, sum of
+// squared degrees}
+void set_degree_stats(byo_graph *g, const unsigned long long *h) {
+  g->max_deg = (int64_t)h[0];
+  g->isolated = (int64_t)h[1];
+  g->mean_deg = 0.0;
+  g->cv_deg = 0.0;
+  if (g->n > 0) {
+    g->mean_deg = (double)g->m / (double)g->n;
+    double ex2 = (double)h[2] / (double)g->n;
+    double var = std::max(0.0, ex2 - g->mean_deg * g->mean_deg);
+    g->cv_deg = g->mean_deg > 0 ? std::sqrt(var) / g->mean_deg : 0.0;
+  }
+}
+
+byo_status graph_refresh_stats(byo_graph *g, unsigned long long *d_tmp, hipStream_t s) {
+  BYO_HIP(hipMemsetAsync(d_tmp, 0, sizeof(unsigned long long) * 8, s));
+  if (g->n > 0) {
+    degree_stats_kernel<<<grid_for(g->n, 256, 2048), 256, 0, s>>>(g->off, g->n, g->deg, g->zero_bits, d_tmp);
+    BYO_HIP(hipGetLastError());
+  }
+  unsigned long long h[3] = {0, 0, 0};
+  BYO_TRY(sync_read(s, d_tmp, h, sizeof(h)));
+  set_degree_stats(g, h);
+  return BYO_OK;
+}
+
 }  // namespace byo
 
 using namespace byo;
@@ -389,14 +416,8 @@ byo_status byo_graph_from_csr(const int64_t *off, const int32_t *nbr, int64_t n,
   if ((flags & BYO_VALIDATE) && h_tmp[4])
     return done(fail(BYO_EINVAL, "CSR rows malformed: " + std::to_string(h_tmp[4]) +
                                      " entries out of range, unsorted, repeated, self-loops or asymmetric"));
-  g->max_deg = (int64_t)h_tmp[0];
-  g->isolated = (int64_t)h_tmp[1];
-  if (n > 0) {
-    g->mean_deg = (double)m / (double)n;
-    double ex2 = (double)h_tmp[2] / (double)n;
-    double var = std::max(0.0, ex2 - g->mean_deg * g->mean_deg);
-    g->cv_deg = g->mean_deg > 0 ? std::sqrt(var) / g->mean_deg : 0.0;
-  }
+  set_degree_stats(g, h_tmp);
+  g->nbr_cap = m;
   *out = g;
   return done(BYO_OK);
 }
@@ -411,6 +432,9 @@ void byo_graph_destroy(byo_graph *g) {
   }
   if (g->deg) (void)hipFree(g->deg);
   if (g->zero_bits) (void)hipFree(g->zero_bits);
+  if (g->spare_off) (void)hipFree(g->spare_off);
+  if (g->spare_nbr) (void)hipFree(g->spare_nbr);
+  upd_free(g->upd);
   delete g;
 }
 
@@ -450,6 +474,14 @@ byo_status byo_graph_arrays(const byo_graph *g, const int64_t **d_off, const int
   if (d_off) *d_off = g->off;
   if (d_nbr) *d_nbr = g->nbr;
   if (d_deg) *d_deg = g->deg;
+  return BYO_OK;
+}
+
+byo_status byo_graph_copy(const byo_graph *g, int64_t *h_off, int32_t *h_nbr) {
+  BYO_CHECK(g && h_off && (g->m == 0 || h_nbr), BYO_EINVAL, "null argument");
+  BYO_HIP(hipDeviceSynchronize());
+  BYO_HIP(hipMemcpy(h_off, g->off, sizeof(int64_t) * (size_t)(g->n + 1), hipMemcpyDeviceToHost));
+  if (g->m > 0) BYO_HIP(hipMemcpy(h_nbr, g->nbr, sizeof(int32_t) * (size_t)g->m, hipMemcpyDeviceToHost));
   return BYO_OK;
 }
 
