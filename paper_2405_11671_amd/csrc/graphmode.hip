@@ -2,9 +2,10 @@
 // captured once into a hipGraph and replayed with one host sync per replay.
 //
 // A level is a fixed launch sequence (grids fixed at capture time):
-//   gm_select    one thread: counts the level just finished, stops on an empty
+//   gm_select    one block: counts the level just finished, stops on an empty
 //                frontier or at the level cap, and picks push or pull with the
-//                threshold rule (dense iff |U| + sum(deg U) > m / div);
+//                threshold rule (dense iff |U| + sum(deg U) > m / div), or with
+//                the learned selector evaluated on the device (BYO_SEL_MLP);
 //   gm_prepush   push only: zero the output bitmap and, after a pull level,
 //                turn the input bitmap into an ID list;
 //   gm_push      degree-bucketed push from the list (thread per vertex,
@@ -17,6 +18,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "selector_dev.h"
 
 namespace byo {
 
@@ -39,27 +41,47 @@ struct gm_state {
 constexpr int GM_BLOCK = 256;
 constexpr int GM_GRID = 2048;
 
-__global__ void gm_select_kernel(gm_counters *__restrict__ cin, gm_counters *__restrict__ cout,
-                                 gm_state *__restrict__ st, int64_t m, int32_t div, int32_t cap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (st->prev_sel != GM_NONE) st->level += 1;
-  st->prev_sel = GM_NONE;
-  st->sel = GM_NONE;
-  if (st->done) return;
-  unsigned long long k = cin->count, ds = cin->degsum;
-  if (k == 0) {
-    st->done = 1;
-    return;
+// One block of 64 threads. With learned weights (wts non-null) the block
+// evaluates the selector network on the level's features, as the host-driven
+// loop does from its counters, and a pull variant choice means pull; without
+// them, or if a prediction is not finite, the threshold rule decides.
+__global__ void __launch_bounds__(64) gm_select_kernel(gm_counters *__restrict__ cin, gm_counters *__restrict__ cout,
+                                                       gm_state *__restrict__ st, int64_t n, int64_t m, int32_t div,
+                                                       int32_t cap, const float *__restrict__ wts, int64_t max_deg,
+                                                       double cv) {
+  __shared__ int go, pull;
+  __shared__ float raw[SEL_F];
+  if (threadIdx.x == 0) {
+    go = 0;
+    if (st->prev_sel != GM_NONE) st->level += 1;
+    st->prev_sel = GM_NONE;
+    st->sel = GM_NONE;
+    if (!st->done) {
+      const unsigned long long k = cin->count, ds = cin->degsum;
+      if (k == 0) {
+        st->done = 1;
+      } else if (st->level >= cap) {
+        st->done = 1;
+        st->limit = 1;
+      } else {
+        st->reached += k;
+        st->edges += ds;
+        go = 1;
+        pull = (long long)(k + ds) > m / (div > 0 ? div : 20);
+        if (wts)
+          selector_features((double)k, (double)ds, (double)(n - (int64_t)st->reached), (double)n, (double)m,
+                            (double)max_deg, cv, cin->list_valid ? 0.0 : 1.0, raw);
+      }
+    }
   }
-  if (st->level >= cap) {
-    st->done = 1;
-    st->limit = 1;
-    return;
+  __syncthreads();
+  if (!go) return;  // uniform over the block
+  if (wts) {
+    const int v = sel_pick_block(wts, raw, true, nullptr);
+    if (threadIdx.x == 0 && v >= 0) pull = v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE;
   }
-  st->reached += k;
-  st->edges += ds;
-  bool pull = (long long)(k + ds) > m / (div > 0 ? div : 20);
-  int sel = pull ? GM_PULL : (cin->list_valid ? GM_PUSH : GM_PUSH_COMPACT);
+  if (threadIdx.x != 0) return;
+  const int sel = pull ? GM_PULL : (cin->list_valid ? GM_PUSH : GM_PUSH_COMPACT);
   st->sel = sel;
   st->prev_sel = sel;
   if (pull) st->pull_levels += 1; else st->push_levels += 1;
@@ -265,6 +287,8 @@ struct gm_graph {
   hipStream_t cap = nullptr;
   int32_t *parent = nullptr, *depth = nullptr;
   int levels = 0, div = 0, cap_levels = 0, t_wave = 0;
+  const float *wts = nullptr;  // selector weights baked into the captured select kernels
+  uint64_t wver = 0;
 };
 
 void gm_release(byo_workspace &w) {
@@ -277,10 +301,10 @@ void gm_release(byo_workspace &w) {
 }
 
 static byo_status enqueue_level(byo_graph *g, int parity, int32_t *parent, int32_t *depth, gm_counters *ctr,
-                                gm_state *st, int div, int cap_levels, int t_wave, hipStream_t s) {
+                                gm_state *st, int div, int cap_levels, int t_wave, const float *wts, hipStream_t s) {
   byo_workspace &w = g->ws;
   int a = parity, b = 1 - parity;
-  gm_select_kernel<<<1, 64, 0, s>>>(ctr + a, ctr + b, st, g->m, div, cap_levels);
+  gm_select_kernel<<<1, 64, 0, s>>>(ctr + a, ctr + b, st, g->n, g->m, div, cap_levels, wts, g->max_deg, g->cv_deg);
   gm_prepush_kernel<<<GM_GRID, GM_BLOCK, 0, s>>>(st, ctr + a, w.bits[a], w.ids[a], w.bits[b], w.words, g->n);
   gm_push_kernel<<<GM_GRID, GM_BLOCK, 0, s>>>(st, ctr + a, ctr + b, g->off, g->nbr, g->deg, w.ids[a], w.ids[b],
                                               w.bits[b], parent, depth, w.visited, t_wave);
@@ -313,10 +337,13 @@ byo_status bfs_graph_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t
   BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
   gm_init_kernel<<<1, 64, 0, s>>>(ctr, ctr + 1, st, (unsigned long long)ns, w.scan + ns);
   BYO_HIP(hipGetLastError());
-  // (re)capture when the outputs or options changed
+  // learned choice on the device when asked for and weights are installed
+  uint64_t wver = 0;
+  const float *wts = o.selector == BYO_SEL_MLP ? selector_device_weights(&wver) : nullptr;
+  // (re)capture when the outputs, options or selector weights changed
   gm_graph *gg = (gm_graph *)w.gmode;
   if (!gg || gg->parent != d_parent || gg->depth != d_depth || gg->div != div || gg->cap_levels != cap_levels ||
-      gg->t_wave != tw) {
+      gg->t_wave != tw || gg->wts != wts || (wts && gg->wver != wver)) {
     gm_release(w);
     gg = new gm_graph();
     w.gmode = gg;
@@ -324,7 +351,7 @@ byo_status bfs_graph_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t
     BYO_HIP(hipStreamBeginCapture(gg->cap, hipStreamCaptureModeThreadLocal));
     byo_status cs = BYO_OK;
     for (int L = 0; L < K && cs == BYO_OK; ++L) cs = enqueue_level(g, L & 1, d_parent, d_depth, ctr, st, div,
-                                                                   cap_levels, tw, gg->cap);
+                                                                   cap_levels, tw, wts, gg->cap);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(gg->cap, &graph);
     if (cs != BYO_OK) return cs;
@@ -337,6 +364,8 @@ byo_status bfs_graph_run(byo_graph *g, const std::vector<int32_t> &srcs, int32_t
     gg->div = div;
     gg->cap_levels = cap_levels;
     gg->t_wave = tw;
+    gg->wts = wts;
+    gg->wver = wver;
     gg->levels = K;
   }
   gm_state h;

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "selector_dev.h"
 
 namespace byo {
 
@@ -236,6 +237,7 @@ struct sel_state {
   int device = -1;
   float *d_w = nullptr;       // params[P], mu[F], sd[F]
   std::vector<float> h_w;     // host copy of d_w for the host-driven level loop
+  uint64_t version = 0;       // changes whenever weights are installed or cleared
 };
 static sel_state g_sel;
 static std::mutex g_sel_mu;
@@ -249,42 +251,8 @@ struct pick_args {
 // variants; -1 if any prediction is not finite.
 __global__ void __launch_bounds__(64) mlp_pick_kernel(const float *__restrict__ wts, pick_args a,
                                                       float *__restrict__ pred_out, int32_t *__restrict__ var_out) {
-  __shared__ float x[F], h1[H], h2[H], o[K];
-  int t = threadIdx.x;
-  if (t < F) x[t] = (a.raw[t] - wts[P + t]) / wts[P + F + t];
-  __syncthreads();
-  if (t < H) {
-    float z = wts[OFF_B1 + t];
-    for (int i = 0; i < F; ++i) z += x[i] * wts[OFF_W1 + i * H + t];
-    h1[t] = z > 0.f ? z : 0.f;
-  }
-  __syncthreads();
-  if (t < H) {
-    float z = wts[OFF_B2 + t];
-    for (int i = 0; i < H; ++i) z += h1[i] * wts[OFF_W2 + i * H + t];
-    h2[t] = z > 0.f ? z : 0.f;
-  }
-  __syncthreads();
-  if (t < K) {
-    float z = wts[OFF_B3 + t];
-    for (int i = 0; i < H; ++i) z += h2[i] * wts[OFF_W3 + i * K + t];
-    o[t] = z;
-    pred_out[t] = z;
-  }
-  __syncthreads();
-  if (t == 0) {
-    int best = -1;
-    for (int v = 0; v < K; ++v) {
-      if (!isfinite(o[v])) {
-        best = -1;
-        break;
-      }
-      bool pull = v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE;
-      if (pull && !a.allow_pull) continue;
-      if (best < 0 || o[v] < o[best]) best = v;
-    }
-    *var_out = best;
-  }
+  const int best = sel_pick_block(wts, a.raw, a.allow_pull != 0, pred_out);
+  if (threadIdx.x == 0) *var_out = best;
 }
 
 bool selector_ready() {
@@ -292,6 +260,12 @@ bool selector_ready() {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   return dev == g_sel.device;
+}
+
+const float *selector_device_weights(uint64_t *version) {
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  if (version) *version = g_sel.version;
+  return selector_ready() ? g_sel.d_w : nullptr;
 }
 
 // The host-driven level loop reads each level's counters anyway, so the
@@ -417,12 +391,14 @@ byo_status byo_selector_set(const float *h_params, const float *h_mu, const floa
   g_sel.h_w = buf;
   g_sel.device = dev;
   g_sel.loaded = true;
+  ++g_sel.version;
   return BYO_OK;
 }
 
 byo_status byo_selector_clear(void) {
   std::lock_guard<std::mutex> lk(g_sel_mu);
   g_sel.loaded = false;
+  ++g_sel.version;
   return BYO_OK;
 }
 

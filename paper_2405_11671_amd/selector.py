@@ -167,18 +167,24 @@ def evaluate(levels, choose):
     return tot
 
 
-def forward_np(params, Xn):
-    """Float32 numpy forward (for offline evaluation of collected tables)."""
-    w = unpack(np.asarray(params, np.float32))
-    h1 = np.maximum(Xn @ w["W1"] + w["b1"], 0)
-    h2 = np.maximum(h1 @ w["W2"] + w["b2"], 0)
-    return h2 @ w["W3"] + w["b3"]
+def forward(params, Xn):
+    """Predictions [N, K] of the network on normalised features [N, F], by the
+    library's forward kernel (byo_mlp_forward)."""
+    torch = _torch()
+    Xn = np.ascontiguousarray(Xn, np.float32)
+    N = int(Xn.shape[0])
+    p = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
+    Xd = torch.from_numpy(Xn).cuda()
+    out = torch.empty((max(N, 1), K), dtype=torch.float32, device="cuda")
+    _lib.check(_lib.load().byo_mlp_forward(ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(Xd.data_ptr()), N,
+                                           ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out[:N].cpu().numpy()
 
 
 def compare(levels, params, mu, sd, opts=None):
     """Sum of timed ms per policy over the levels: heuristic, learned, best."""
     X, _, _ = dataset(levels)
-    pred = forward_np(params, (X - mu) / sd)
+    pred = forward(params, (X - mu) / sd)
     learned = {id(lv): int(np.argmin(pred[i])) for i, lv in enumerate(levels)}
     return {
         "heuristic_ms": evaluate(levels, lambda lv: heuristic_choice(lv["rec"], opts)),

@@ -4,6 +4,7 @@ the trained selector over the threshold heuristic on held-out graphs."""
 import ctypes
 import json
 import os
+import time
 
 import numpy as np
 import pytest
@@ -185,30 +186,61 @@ def collect_tables(plist, sources=2):
     return levels
 
 
+def timed_runs(g, fn, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best * 1e3
+
+
 def test_trained_selector_gain_on_heldout_graphs(capsys):
-    """Train on the library's own timing tables, evaluate on graphs it never saw."""
+    """Train on the library's own timing tables, evaluate on graphs it never
+    saw: offline, each held-out level's choice comes from the library's
+    device predictor (the network the traversals run) and is priced with
+    that level's measured times; online, BFS and connectivity with the
+    installed network are timed end to end against the threshold rule."""
     train_levels = collect_tables(training_graphs())
     X, Y, M = sel.dataset(train_levels)
     mu, sd = sel.normaliser(X)
     params, losses = sel.train((X - mu) / sd, Y, M, steps=3000, lr=3e-3)
     assert losses[-1] < 0.5 * losses[0]
     test_levels = collect_tables(heldout_graphs())
-    rep = sel.compare(test_levels, params, mu, sd)
-    gain = rep["heuristic_ms"] / rep["learned_ms"]
-    with capsys.disabled():
-        print(f"\n[selector] held-out: heuristic {rep['heuristic_ms']:.3f} ms, learned {rep['learned_ms']:.3f} ms, "
-              f"best {rep['best_ms']:.3f} ms over {rep['levels']} levels; gain {gain:.3f}x")
-    # the learned policy beats the rule it replaces on graphs it never saw
-    assert gain > 1.0
-    # online: the installed selector still gives exact results on a held-out graph
     sel.install(params, mu, sd)
     try:
-        p = heldout_graphs()[0]
-        g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
-        d, _, st = byo.bfs(g, 1, selector=byo.SEL_MLP)
-        assert np.array_equal(d.cpu().numpy(), og.bfs(1)[0])
+        heur = sel.evaluate(test_levels, lambda lv: sel.heuristic_choice(lv["rec"]))
+        learned = sel.evaluate(test_levels, lambda lv: sel.predict(sel.features(lv["rec"]))[1])
+        best = sel.evaluate(test_levels, lambda lv: int(np.nanargmin(lv["ms"])))
+        gain = heur / learned
+        # end to end: the shipped SEL_MLP path against the heuristic, same graphs
+        e2e = {}
+        for p in heldout_graphs():
+            g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+            src = int(gen.pick_sources(p, 1, seed=3)[0])
+            d, _, _ = byo.bfs(g, src, selector=byo.SEL_MLP)
+            assert np.array_equal(d.cpu().numpy(), og.bfs(src)[0])
+            for algo, run in (("bfs", lambda o: byo.bfs(g, src, opts=o)), ("cc", lambda o: byo.cc(g, opts=o))):
+                th = timed_runs(g, lambda: run(byo.default_opts()))
+                tl = timed_runs(g, lambda: run(byo.default_opts(selector=byo.SEL_MLP)))
+                e2e[f"{p.name}:{algo}"] = (th, tl)
     finally:
         sel.clear()
+    th_tot = sum(a for a, _ in e2e.values())
+    tl_tot = sum(b for _, b in e2e.values())
+    with capsys.disabled():
+        print(f"\n[selector] held-out tables: heuristic {heur:.3f} ms, learned {learned:.3f} ms, best {best:.3f} ms "
+              f"over {len(test_levels)} levels; gain {gain:.3f}x")
+        print("[selector] end to end (heuristic ms / learned ms): " +
+              ", ".join(f"{k} {a:.2f}/{b:.2f}" for k, (a, b) in e2e.items()) +
+              f"; total {th_tot:.2f}/{tl_tot:.2f} ({th_tot / tl_tot:.3f}x)")
+    # the learned policy beats the rule it replaces on graphs it never saw
+    assert gain > 1.0
+    # and the shipped path, with its inference cost, is not slower in total
+    assert tl_tot <= 1.10 * th_tot
 
 
 def test_traversal_choices_match_device_prediction():
@@ -235,4 +267,37 @@ def test_traversal_choices_match_device_prediction():
             assert checked >= len(recs) // 2
     finally:
         byo.trace_enable(False)
+        sel.clear()
+
+
+def test_graph_mode_consults_the_network_on_the_device():
+    """BFS with hipGraph-replayed levels and BYO_SEL_MLP: the select kernel
+    evaluates the installed network on the device. Weights whose last layer
+    is a constant bias force every level to pull (or to push), which the
+    run's variant counts show; depths stay exact either way."""
+    p = gen.rmat_pairs(15, 16, seed=4)
+    g, og = byo.Graph.from_pairs(p), oracle.Graph.from_pairs(p)
+    src = int(gen.pick_sources(p, 1, seed=9)[0])
+    want = og.bfs(src)[0]
+    base = sel.init_params(5)
+    mu, sd = np.zeros(sel.F, np.float32), np.ones(sel.F, np.float32)
+    try:
+        for forced, bias in ((byo.V_PULL_WAVE, [1, 1, 1, 1, 1, 0]), (byo.V_PUSH_THREAD, [0, 1, 1, 1, 1, 1])):
+            params = base.copy()
+            v = sel.unpack(params)
+            v["W3"][:] = 0.0
+            v["b3"][:] = np.array(bias, np.float32)
+            sel.install(params, mu, sd)
+            d, par, st = byo.bfs(g, src, selector=byo.SEL_MLP, use_graph=1)
+            assert np.array_equal(d.cpu().numpy(), want)
+            assert og.check_bfs(src, d.cpu().numpy(), par.cpu().numpy()) == 0
+            pulls = st["variant_count"]["pull_wave"]
+            if forced == byo.V_PULL_WAVE:
+                assert pulls == st["levels"], st
+            else:
+                assert pulls == 0, st
+            # the threshold rule (no network) picks both kinds on this graph
+            _, _, sh = byo.bfs(g, src, use_graph=1)
+            assert 0 < sh["variant_count"]["pull_wave"] < sh["levels"]
+    finally:
         sel.clear()

@@ -27,6 +27,23 @@ def test_features_match_oracle_definition(r):
     assert np.allclose(got, np.array(want, np.float32), rtol=1e-6, atol=1e-7)
 
 
+def test_features_pinned_to_hand_computed_values():
+    """The oracle's feature definition (and the library's) on a level whose
+    features are exact by hand: every count one below a power of two, so each
+    log2(1 + x) is an integer; a dropped term, swapped argument or wrong
+    ratio changes at least one of these literals."""
+    r = rec(k=3, degsum=7, unvisited=15, n=31, m=63, max_deg=127, cv=0.5, dense_in=1)
+    # log2 4, log2 8, log2 16, log2 32, log2 64, (3+7)/64, 3/32, log2 128, cv,
+    # log2(1 + 7/4) = log2 2.75, 15/32, flag
+    want = [2.0, 3.0, 4.0, 5.0, 6.0, 0.15625, 0.09375, 7.0, 0.5, math.log2(2.75), 0.46875, 1.0]
+    got_oracle = omlp.selector_features(3, 7, 15, 31, 63, 127, 0.5, 1)
+    assert got_oracle == pytest.approx(want, rel=0, abs=1e-15)
+    assert np.allclose(sel.features(r), np.array(want, np.float32), rtol=0, atol=1e-6)
+    # an empty frontier on an edgeless one-vertex graph: every log term is 0
+    z = omlp.selector_features(0, 0, 0, 0, 0, 0, 0.0, 0)
+    assert z == [0.0] * 12
+
+
 def test_heuristic_cutoff_and_balance_choices():
     m = 2_000_000
     # exactly at the cutoff stays sparse; one more goes dense (k + degsum > m/20)
@@ -64,12 +81,3 @@ def test_weight_file_roundtrip(tmp_path):
     p2, mu2, sd2, meta = sel.load_weights(path)
     assert np.array_equal(p, p2) and np.array_equal(mu, mu2) and np.array_equal(sd, sd2)
     assert meta == {"trained_on": ["x"]}
-
-
-def test_numpy_forward_matches_oracle():
-    rng = np.random.default_rng(0)
-    p = sel.init_params(3)
-    X = rng.standard_normal((50, 12)).astype(np.float32)
-    got = sel.forward_np(p, X)
-    want, _ = omlp.forward({k: v.astype(np.float64) for k, v in sel.unpack(p).items()}, X.astype(np.float64))
-    assert np.allclose(got, want, rtol=1e-5, atol=1e-5)
