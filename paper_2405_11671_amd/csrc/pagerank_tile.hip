@@ -22,7 +22,7 @@
 namespace byo {
 
 constexpr int PT_THREADS = 1024;
-constexpr int PT_ILP = 16;
+constexpr int PT_ILP = 12;
 constexpr int PT_APPLY = 256;
 constexpr int PT_AV = 4;
 int pr_tile_shift(const byo_graph *g, int32_t opt) { return (opt >= 12 && opt <= 14) ? opt : tiles_auto_shift(g); }
