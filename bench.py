@@ -334,7 +334,8 @@ def container_study(byo, gen, args, configs, base_name, title, unit, extra_algos
                             "cz_bytes_per_edge": round((8 * (n + 1) + nbytes.value) / m, 3),
                             "cz_list_bytes_per_edge": round(nbytes.value / m, 3)}
         for cname, kw in configs:
-            o = byo.default_opts(**kw)
+            # the CSR container throughout (the tile layout is a second container)
+            o = byo.default_opts(pr_blocked=0, tiled=0, **kw)
             for aname, fn in algos.items():
                 fn(o)
                 ts = []
@@ -524,6 +525,7 @@ def main():
     params, mu, sd, _ = sel.load_weights(wpath)
     sel.install(params, mu, sd)
     mlp_opts = byo.default_opts(selector=byo.SEL_MLP)
+    mlp_csr_opts = byo.default_opts(selector=byo.SEL_MLP, tiled=0, pr_blocked=0)
 
     ms_srcs = gen.pick_sources(pairs, args.ms_sources, seed=2)
     ms_depth = torch.empty(n * len(ms_srcs), dtype=torch.uint8, device="cuda")
@@ -535,7 +537,7 @@ def main():
         ev[1].record()
         byo.pagerank(g, 0.85, args.pr_iters, opts=tiled, rank=rank)
         ev[2].record()
-        _, cst = byo.cc(g, opts=tiled if not args.no_tiles else mlp_opts, label=label)
+        _, cst = byo.cc(g, opts=tiled if not args.no_tiles else mlp_csr_opts, label=label)
         ev[3].record()
         ms_edges = mst["edges"] // 2
         if record is not None:

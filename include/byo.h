@@ -86,7 +86,7 @@ typedef struct byo_opts {
                              max(16 x this, 2^16) edges, capped at 2^17) run in the
                              device-resident loop: one cooperative kernel of 64
                              workgroups, grid barriers between levels (0 = off; default 0) */
-  int32_t pr_blocked;     /* PageRank layout: 0 = pull over the CSR (default); 1 = entries
+  int32_t pr_blocked;     /* PageRank layout: 0 = pull over the CSR; 1 (default) = entries
                              regrouped by destination tile of degree-ordered vertices, exact
                              fixed-point sums in LDS, tiles of 2^12 vertices up to n = 2^22,
                              2^13 up to 2^23, 2^14 beyond; 12..14 = tiles of 2^value. The
@@ -98,11 +98,11 @@ typedef struct byo_opts {
                              hipGraph (push or pull chosen on the device: the threshold
                              rule, or with selector = BYO_SEL_MLP the learned network
                              evaluated there), 0 = host loop (default) */
-  int32_t tiled;          /* multi-source BFS and connectivity: 1 = dense levels / rounds over
-                             the degree-ordered tile layout (the kind PageRank's pr_blocked
-                             uses; multi-source BFS always with tiles of 2^12 vertices) when
-                             n >= 2^16 and m >= 4n; 0 = over the CSR with the selected
-                             variants (default) */
+  int32_t tiled;          /* multi-source BFS and connectivity: 1 (default) = dense levels /
+                             rounds over the degree-ordered tile layout (the kind PageRank's
+                             pr_blocked uses; multi-source BFS always with tiles of 2^12
+                             vertices) when n >= 2^16 and m >= 4n, else over the CSR; 0 = over
+                             the CSR with the selected variants */
   int32_t tile_shift;     /* connectivity with tiled = 1: tiles of 2^value vertices (12..14);
                              0 = chosen from n as for pr_blocked = 1 (default) */
   int32_t api_omit;       /* container-API ablation: BYO_API_NO_* bits of container functions

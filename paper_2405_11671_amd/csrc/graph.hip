@@ -257,9 +257,9 @@ void byo_opts_default(byo_opts *o) {
   o->max_levels = 0;
   o->cc_shortcut = 1;
   o->small_frontier = 0;
-  o->pr_blocked = 0;
+  o->pr_blocked = 1;   // the tile layout wherever the graph qualifies (n >= 2^16, m >= 4n)
   o->use_graph = 0;
-  o->tiled = 0;
+  o->tiled = 1;
 }
 
 byo_status byo_csr_from_pairs(const int32_t *src, const int32_t *dst, int64_t npairs, int64_t n, int64_t *off,

@@ -34,13 +34,15 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_binding_covers_every_declared_symbol():
-    bound = set(_lib.SIGNATURES) | set(_lib.extra_signatures())
+    bound = set(_lib.SIGNATURES)
     assert declared_functions() == bound
 
 
 def test_opts_defaults_and_version():
     o = _lib.default_opts()
     assert (o.selector, o.dense_divisor, o.t_wave, o.t_block, o.cc_shortcut) == (0, 20, 32, 4096, 1)
+    # the tile layout is the default wherever a graph qualifies
+    assert (o.pr_blocked, o.tiled, o.use_graph, o.small_frontier) == (1, 1, 0, 0)
     assert b"gfx950" in _lib.load().byo_version()
 
 
@@ -83,7 +85,6 @@ def test_every_entry_point_rejects_null_arguments_before_device_work():
     The calls that switch process-wide state are left uncalled."""
     lib = _lib.load()
     sigs = dict(_lib.SIGNATURES)
-    sigs.update(_lib.extra_signatures())
     h = ctypes.c_void_p()
     off = np.array([0, 0], np.int64)
     for name in sorted(declared_functions() - STATEFUL):

@@ -29,11 +29,12 @@ def test_msbfs_matches_single_source_oracle(p, k):
     rng = np.random.default_rng(k)
     srcs = rng.integers(0, og.n, k)
     srcs[0] = srcs[-1]          # a repeated source is allowed
-    D, st = byo.msbfs(g, srcs)
     want = og.msbfs(srcs)
-    assert np.array_equal(D.cpu().numpy(), want), (p.name, k)
     reached = int((want != 255).sum())
-    assert st["reached"] == reached
+    for tiled in (1, 0):        # the default (tiles where the graph qualifies) and the CSR levels
+        D, st = byo.msbfs(g, srcs, tiled=tiled)
+        assert np.array_equal(D.cpu().numpy(), want), (p.name, k, tiled)
+        assert st["reached"] == reached
 
 
 @pytest.mark.parametrize("variant", [byo.V_PUSH_THREAD, byo.V_PUSH_WAVE, byo.V_PUSH_BUCKET, byo.V_PUSH_EDGE,
@@ -64,7 +65,7 @@ def test_msbfs_tiled_matches_oracle(pi, k):
     want = og.msbfs(srcs)
     assert np.array_equal(D.cpu().numpy(), want), (pi, k)
     assert st["reached"] == int((want != 255).sum())
-    D2, st2 = byo.msbfs(g, srcs)
+    D2, st2 = byo.msbfs(g, srcs, tiled=0)
     assert np.array_equal(D2.cpu().numpy(), want)
     assert st2["edges"] == st["edges"] and st2["reached"] == st["reached"]
 
