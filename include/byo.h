@@ -119,7 +119,11 @@ typedef struct byo_opts {
                              the grid (PUSH_EDGE), pull by thread or wavefront, PageRank's pull over
                              the lists.
                              With api_omit != 0: BYO_EINVAL. 0 = the CSR (default) */
-  int32_t reserved[1];
+  int32_t persistent;     /* byo_batch_bfs: 1 (default) = every level in one persistent
+                             cooperative launch with grid barriers between levels (direction
+                             by the threshold rule on the device; falls back to the host loop
+                             where cooperative launches are not supported); 0 = the
+                             host-driven level loop, or hipGraph levels with use_graph = 1 */
 } byo_opts;
 
 /* Container functions a traversal can be denied (Section 4.2 defines the

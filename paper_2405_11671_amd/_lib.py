@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
                 ("pr_blocked", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("tiled", ctypes.c_int32), ("tile_shift", ctypes.c_int32), ("api_omit", ctypes.c_int32),
                 ("ms_history", ctypes.c_int32), ("compressed", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("persistent", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):

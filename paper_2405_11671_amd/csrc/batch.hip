@@ -1,7 +1,8 @@
 // Batched execution over many graphs: the graphs are laid out back to back as
 // one CSR (a disjoint union, vertex IDs shifted by each graph's offset), so a
 // BFS from one source per graph, or one connectivity run, traverses every
-// graph in the same launches. Per-graph results are exactly those of separate
+// graph in the same launches (for BFS, by default, in one persistent launch
+// that runs every level: persistent.hip). Per-graph results are exactly those of separate
 // runs because no edge crosses between graphs; uneven sizes are balanced by
 // the edgeMap schedules themselves (edge-balanced push, word-per-wave pull).
 #include <algorithm>
@@ -127,8 +128,11 @@ byo_status byo_batch_bfs(byo_batch *b, const int64_t *h_srcs, int32_t *d_depth, 
     srcs[i] = (int32_t)(h_srcs[i] + b->voff[i]);
   }
   hipStream_t s = (hipStream_t)stream;
-  if (o.use_graph && o.api_omit == 0 && !o.compressed)
+  const bool plain = o.api_omit == 0 && !o.compressed;
+  if (o.use_graph && plain)
     BYO_TRY(bfs_graph_run(b->g, srcs, d_depth, d_parent, o, s, stats));
+  else if (o.persistent && plain && bfs_persistent_usable(b->g))
+    BYO_TRY(bfs_persistent_run(b->g, srcs.data(), (int64_t)srcs.size(), d_depth, d_parent, o, s, stats));
   else
     BYO_TRY(bfs_run(b->g, srcs.data(), (int64_t)srcs.size(), d_depth, d_parent, o, s, stats));
   return localize(b, d_parent, s);

@@ -27,6 +27,29 @@ struct LevelArgs {
   int32_t no_early_exit;                // pulls scan whole lists (container without early-exit maps)
 };
 
+// Serial early-exit scans issue PULL_ILP independent neighbour loads (and
+// bitmap probes) per step instead of one dependent chain per neighbour.
+constexpr int PULL_ILP = 8;
+
+// First u in nbr[beg, lim) (ascending) whose bit is set in `bits`, else -1.
+__device__ __forceinline__ int32_t first_member(const int32_t *__restrict__ nbr, const uint64_t *__restrict__ bits,
+                                                int64_t beg, int64_t lim, bool scan_all = false) {
+  int32_t first = -1;
+  for (int64_t e = beg; e < lim; e += PULL_ILP) {
+    int32_t u[PULL_ILP];
+    uint64_t w[PULL_ILP];
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) u[j] = (e + j < lim) ? nbr[e + j] : -1;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j) w[j] = u[j] >= 0 ? bits[u[j] >> 6] : 0ull;
+#pragma unroll
+    for (int j = 0; j < PULL_ILP; ++j)
+      if (first < 0 && ((w[j] >> (u[j] & 63)) & 1ull)) first = u[j];
+    if (first >= 0 && !scan_all) return first;  // early exit
+  }
+  return first;
+}
+
 // ---------------------------------------------------------------- functors
 
 // BFS: a vertex is claimed by the first successful CAS of its parent from -1.

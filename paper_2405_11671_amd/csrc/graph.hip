@@ -180,6 +180,7 @@ void ws_free(byo_workspace &w) {
   cz_free(w.cz);
   gm_release(w);
   dl_release(w);
+  pb_release(w.pbfs);
   w = byo_workspace();
 }
 
@@ -260,6 +261,7 @@ void byo_opts_default(byo_opts *o) {
   o->pr_blocked = 1;   // the tile layout wherever the graph qualifies (n >= 2^16, m >= 4n)
   o->use_graph = 0;
   o->tiled = 1;
+  o->persistent = 1;
 }
 
 byo_status byo_csr_from_pairs(const int32_t *src, const int32_t *dst, int64_t npairs, int64_t n, int64_t *off,

@@ -190,6 +190,7 @@ struct byo_workspace {
   uint8_t *ds_alive = nullptr;         // [n] densest subgraph: membership of S
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
+  void *pbfs = nullptr;              // persistent-launch BFS buffers (persistent.hip)
 };
 
 struct byo_graph {
@@ -483,6 +484,13 @@ void gm_release(byo_workspace &w);
 // parent/depth/visited set up for BFS from d_srcs (distinct), traverse.hip
 byo_status bfs_sources_init(byo_graph *g, const int32_t *d_srcs, int64_t ns, int32_t *parent, int32_t *depth,
                             hipStream_t s);
+
+// BFS from distinct sources in one persistent cooperative launch
+// (persistent.hip); usable when the device supports cooperative launches
+bool bfs_persistent_usable(byo_graph *g);
+byo_status bfs_persistent_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,
+                              const byo_opts &o, hipStream_t s, byo_run_stats *stats);
+void pb_release(void *p);
 
 // BFS from distinct sources (traverse.hip)
 byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,

@@ -1,0 +1,359 @@
+// BFS in one persistent launch: a cooperative kernel runs every level of a
+// BFS from a set of sources, with a grid barrier between levels, and returns
+// when the frontier is empty. The batch of many graphs (batch.hip, one source
+// per graph of the disjoint union) runs it by default: its union frontier
+// grows over a few heavy levels and then trails off over many small ones,
+// where a host-driven level loop pays a launch and a counter read-back per
+// level.
+//
+// A level, identical in every workgroup:
+//  - reads the frontier's size and degree sum (written by the level before),
+//    and picks the direction with the threshold rule: dense pull iff
+//    |U| + sum(deg U) > m / dense_divisor;
+//  - push: the frontier's ID list, a lane per vertex with four neighbours
+//    in flight, lists longer than t_wave shared by the wavefront; a CAS on
+//    parent[v] claims v;
+//  - pull: a wavefront per 64-vertex word of the visited bitmap, words
+//    already all visited skipped; each unvisited vertex scans its list until
+//    a neighbour in the frontier bitmap (the lane the first t_wave entries,
+//    eight loads in flight, the wavefront the rest of a longer list), the
+//    first one found being its parent;
+//  - either way the new vertices go to the next bitmap (three rotate, so the
+//    one two levels back is cleared during this level); a push level also
+//    writes them to the next ID list, staged in LDS and reserved with one
+//    atomic per workgroup, while a push level after a pull reads its
+//    frontier from the bitmap, so pull levels write no list;
+//  - the size and degree sum of the next frontier are summed per workgroup
+//    and added with one atomic each; counter slots rotate like the bitmaps.
+// The depths, the reached set and its size are those of any BFS; parents are
+// a valid BFS tree.
+#include <algorithm>
+#include <cstring>
+
+#include "edgemap_dev.h"
+#include "gridsync.h"
+#include "internal.h"
+
+namespace byo {
+
+constexpr int PB_THREADS = 512;
+constexpr int PB_STAGE = 4096;          // LDS staging of one workgroup's new vertices per level
+constexpr int PB_PER_CU = 3;            // workgroups per compute unit in the launch
+constexpr unsigned PB_SPIN_LIMIT = 1u << 22;
+constexpr int PB_SLOT = 16;             // counter slots 128 bytes apart
+
+struct pb_ctl {
+  grid_sync sync;
+  unsigned long long cnt[3 * PB_SLOT];   // frontier size per level mod 3 (also the next list's append cursor)
+  unsigned long long dsum[3 * PB_SLOT];  // its degree sum
+};
+
+struct pb_result {
+  int32_t levels, limit, fail, pad;
+  unsigned long long reached, edges, push_levels, pull_levels;
+};
+
+struct pb_ws {
+  uint64_t *bits2 = nullptr;  // third frontier bitmap (the workspace holds two)
+  pb_ctl *ctl = nullptr;
+  pb_result *res = nullptr;
+  int nblocks = 0;
+  bool checked = false, usable = false;
+};
+
+// frontier of the first level: the sources' count and degree sum
+__global__ void pb_init_kernel(pb_ctl *c, unsigned long long k0, const long long *__restrict__ degsum0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->cnt[0] = k0;
+    c->dsum[0] = (unsigned long long)*degsum0;
+  }
+}
+
+__global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
+    const int64_t *__restrict__ off, const int32_t *__restrict__ nbr, const int32_t *__restrict__ deg, int64_t n,
+    int64_t m, int32_t div, int32_t t_wave, int32_t *__restrict__ parent, int32_t *__restrict__ depth,
+    uint64_t *__restrict__ visited, int64_t words, uint64_t *__restrict__ b0, uint64_t *__restrict__ b1,
+    uint64_t *__restrict__ b2, int32_t *__restrict__ q0, int32_t *__restrict__ q1, pb_ctl *__restrict__ c,
+    int32_t max_levels, pb_result *__restrict__ res) {
+  __shared__ int32_t stage[PB_STAGE];
+  __shared__ unsigned s_cnt;
+  __shared__ unsigned long long s_base;
+  const unsigned nblocks = gridDim.x;
+  const int t = threadIdx.x;
+  const int64_t cutoff = m / (div > 0 ? div : 20);
+  const int64_t tw = t_wave > 0 ? t_wave : 32;
+  unsigned long long push_levels = 0, pull_levels = 0, reached = 0, edges = 0;
+  int L = 0, limit = 0;
+  bool prev_pull = false;  // level 0 pushes from the sources' list (its bitmap is set too)
+  for (;; ++L) {
+    const unsigned long long k = ld_rlx64(&c->cnt[(L % 3) * PB_SLOT]);
+    const unsigned long long ds = ld_rlx64(&c->dsum[(L % 3) * PB_SLOT]);
+    reached += k;
+    edges += ds;
+    if (k == 0) break;
+    if (L >= max_levels) {
+      limit = 1;
+      break;
+    }
+    uint64_t *bin = L % 3 == 0 ? b0 : (L % 3 == 1 ? b1 : b2);
+    uint64_t *bout = L % 3 == 0 ? b1 : (L % 3 == 1 ? b2 : b0);
+    uint64_t *bclr = L % 3 == 0 ? b2 : (L % 3 == 1 ? b0 : b1);
+    const int32_t *qin = (L & 1) ? q1 : q0;
+    int32_t *qout = (L & 1) ? q0 : q1;
+    const int nx = (L + 1) % 3, cl = (L + 2) % 3;
+    // the slot and bitmap of two levels back were last read before the
+    // previous barrier: clear them for the level after this one
+    if (blockIdx.x == 0 && t == 0) {
+      __hip_atomic_store(&c->cnt[cl * PB_SLOT], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&c->dsum[cl * PB_SLOT], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int64_t w = (int64_t)blockIdx.x * PB_THREADS + t; w < words; w += (int64_t)nblocks * PB_THREADS) bclr[w] = 0ull;
+    if (t == 0) s_cnt = 0;
+    __syncthreads();
+    const int32_t nd = L + 1;
+    unsigned long long mydeg = 0, mycount = 0;
+    auto emit = [&](int32_t v) {
+      const unsigned pos = atomicAdd(&s_cnt, 1u);
+      if (pos < (unsigned)PB_STAGE) {
+        stage[pos] = v;
+      } else {
+        const unsigned long long gp = atomicAdd(&c->cnt[nx * PB_SLOT], 1ull);
+        qout[gp] = v;
+      }
+      mydeg += (unsigned long long)deg[v];
+    };
+    const bool pull = (int64_t)(k + ds) > cutoff;
+    if (pull) {
+      ++pull_levels;
+      const int64_t nwaves = (int64_t)nblocks * (PB_THREADS / BYO_WAVE);
+      for (int64_t w = (int64_t)blockIdx.x * (PB_THREADS / BYO_WAVE) + t / BYO_WAVE; w < words; w += nwaves) {
+        const uint64_t vis = visited[w];
+        if (vis == ~0ull) continue;  // every vertex of the word visited (bits past n are set)
+        const int64_t v = w * 64 + lane_id();
+        const bool cand = !((vis >> lane_id()) & 1ull);
+        int32_t par = -1;
+        int64_t b = 0, e = 0;
+        if (cand) {
+          b = off[v];
+          e = off[v + 1];
+          // the first t_wave entries by the lane (PULL_ILP loads in flight),
+          // the rest of a long list by the whole wavefront
+          par = first_member(nbr, bin, b, e - b > tw ? b + tw : e);
+        }
+        uint64_t pm = __ballot(cand && par < 0 && e - b > tw);
+        while (pm) {
+          const int l = __ffsll((long long)pm) - 1;
+          pm &= pm - 1;
+          const int64_t lb = (int64_t)read_lane_u64((uint64_t)(b + tw), l);
+          const int64_t le = (int64_t)read_lane_u64((uint64_t)e, l);
+          for (int64_t x0 = lb; x0 < le; x0 += 4 * BYO_WAVE) {
+            int32_t u[4];
+            bool hit[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int64_t x = x0 + j * BYO_WAVE + lane_id();
+              u[j] = x < le ? nbr[x] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int64_t x = x0 + j * BYO_WAVE + lane_id();
+              hit[j] = x < le && ((bin[u[j] >> 6] >> (u[j] & 63)) & 1ull);
+            }
+            int32_t pu = -1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint64_t hm = __ballot(hit[j]);
+              if (hm && pu < 0) pu = read_lane_i32(u[j], __ffsll((long long)hm) - 1);
+            }
+            if (pu >= 0) {
+              if (lane_id() == l) par = pu;
+              break;
+            }
+          }
+        }
+        const bool found = par >= 0;
+        const uint64_t mask = __ballot(found);
+        if (mask == 0) continue;
+        if (lane_id() == 0) {
+          visited[w] = vis | mask;  // one wavefront owns word w in a pull level
+          bout[w] = mask;
+          mycount += (unsigned long long)__popcll(mask);
+        }
+        if (found) {
+          parent[v] = par;
+          depth[v] = nd;
+          mydeg += (unsigned long long)deg[v];
+        }
+      }
+    } else {
+      ++push_levels;
+      // a lane claims v: CAS on parent[v], then the visited and output bits
+      auto claim = [&](int32_t src, int32_t v) {
+        if (atomicCAS(&parent[v], -1, src) != -1) return;
+        const unsigned long long bit = 1ull << (v & 63);
+        depth[v] = nd;
+        atomicOr((unsigned long long *)&visited[v >> 6], bit);
+        atomicOr((unsigned long long *)&bout[v >> 6], bit);
+        emit(v);
+      };
+      // the frontier: the ID list a push level wrote, or after a pull level
+      // (which writes only the bitmap) the set bits of the frontier bitmap,
+      // a wavefront per 64-vertex word
+      const unsigned long long items = prev_pull ? (unsigned long long)words * BYO_WAVE : k;
+      const unsigned long long stride = (unsigned long long)nblocks * PB_THREADS;
+      for (unsigned long long base = (unsigned long long)blockIdx.x * PB_THREADS; base < items; base += stride) {
+        const unsigned long long i = base + t;
+        int32_t u = -1;
+        int64_t b = 0, e = 0;
+        if (prev_pull) {
+          if (i < items && ((bin[i >> 6] >> (i & 63)) & 1ull)) u = (int32_t)i;
+        } else if (i < k) {
+          u = qin[i];
+        }
+        if (u >= 0) {
+          b = off[u];
+          e = off[u + 1];
+        }
+        const bool wide = u >= 0 && e - b > tw;
+        if (u >= 0 && !wide) {
+          // four neighbours and their visited words in flight per step
+          for (int64_t x0 = b; x0 < e; x0 += 8) {
+            int32_t v[8];
+            uint64_t vw[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = x0 + j < e ? nbr[x0 + j] : -1;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) vw[j] = v[j] >= 0 ? visited[v[j] >> 6] : ~0ull;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (!((vw[j] >> (v[j] & 63)) & 1ull)) claim(u, v[j]);
+          }
+        }
+        uint64_t wm = __ballot(wide);
+        while (wm) {
+          const int l = __ffsll((long long)wm) - 1;
+          wm &= wm - 1;
+          const int32_t wu = read_lane_i32(u, l);
+          const int64_t wb = (int64_t)read_lane_u64((uint64_t)b, l), we = (int64_t)read_lane_u64((uint64_t)e, l);
+          for (int64_t x = wb + lane_id(); x < we; x += BYO_WAVE) {
+            const int32_t v = nbr[x];
+            if (!((visited[v >> 6] >> (v & 63)) & 1ull)) claim(wu, v);
+          }
+        }
+      }
+    }
+    // flush the stage with one reservation; add this workgroup's degree sum
+    const unsigned long long bdeg = block_sum<unsigned long long, PB_THREADS>(mydeg);
+    const unsigned long long bcount = block_sum<unsigned long long, PB_THREADS>(mycount);
+    __syncthreads();
+    const unsigned staged = s_cnt < (unsigned)PB_STAGE ? s_cnt : (unsigned)PB_STAGE;
+    if (t == 0) {
+      // a push level's count is its list's append cursor; a pull level adds its count
+      s_base = staged ? atomicAdd(&c->cnt[nx * PB_SLOT], (unsigned long long)staged) : 0ull;
+      if (bcount) atomicAdd(&c->cnt[nx * PB_SLOT], bcount);
+      if (bdeg) atomicAdd(&c->dsum[nx * PB_SLOT], bdeg);
+    }
+    __syncthreads();
+    for (unsigned j = t; j < staged; j += PB_THREADS) qout[s_base + j] = stage[j];
+    prev_pull = pull;
+    if (!grid_barrier(&c->sync, nblocks, PB_SPIN_LIMIT)) break;
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    res->levels = L;
+    res->limit = limit;
+    res->fail = ld_rlx(&c->sync.fail[0]) ? 1 : 0;
+    res->reached = reached;
+    res->edges = edges;
+    res->push_levels = push_levels;
+    res->pull_levels = pull_levels;
+  }
+}
+
+void pb_release(void *p) {
+  pb_ws *d = (pb_ws *)p;
+  if (!d) return;
+  void *x[] = {d->bits2, d->ctl, d->res};
+  for (void *y : x)
+    if (y) (void)hipFree(y);
+  delete d;
+}
+
+static byo_status pb_ensure(byo_graph *g, pb_ws **out) {
+  byo_workspace &w = g->ws;
+  if (!w.pbfs) w.pbfs = new pb_ws();
+  pb_ws *d = (pb_ws *)w.pbfs;
+  *out = d;
+  if (d->checked) return BYO_OK;
+  d->checked = true;
+  int dev = 0, coop = 0, cus = 0, per_cu = 0;
+  BYO_HIP(hipGetDevice(&dev));
+  BYO_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  BYO_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  BYO_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel, PB_THREADS, 0));
+  if (!coop || cus <= 0 || per_cu <= 0) return BYO_OK;  // not usable: the host-driven loop runs instead
+  d->nblocks = cus * std::min(per_cu, PB_PER_CU);
+  BYO_HIP(hipMalloc(&d->bits2, sizeof(uint64_t) * (size_t)std::max<int64_t>(g->ws.words, 1)));
+  BYO_HIP(hipMalloc(&d->ctl, sizeof(pb_ctl)));
+  BYO_HIP(hipMalloc(&d->res, sizeof(pb_result)));
+  d->usable = true;
+  return BYO_OK;
+}
+
+bool bfs_persistent_usable(byo_graph *g) {
+  if (ws_ensure_traversal(g) != BYO_OK) return false;
+  pb_ws *d = nullptr;
+  if (pb_ensure(g, &d) != BYO_OK) return false;
+  return d->usable;
+}
+
+byo_status bfs_persistent_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,
+                              const byo_opts &o, hipStream_t s, byo_run_stats *stats) {
+  BYO_TRY(ws_ensure_traversal(g));
+  pb_ws *d = nullptr;
+  BYO_TRY(pb_ensure(g, &d));
+  BYO_CHECK(d->usable, BYO_ESTATE, "cooperative launch not available for the persistent BFS");
+  byo_workspace &w = g->ws;
+  const int64_t n = g->n;
+  BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
+  BYO_TRY(fill_i32(d_parent, n, -1, s));
+  BYO_TRY(fill_i32(d_depth, n, -1, s));
+  // sources: staged through ids[1], then visited, parent/depth and the first
+  // list (ids[0]) and bitmap (bits[0]); the other bitmaps start clear
+  BYO_HIP(hipMemcpyAsync(w.ids[1], srcs, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
+  BYO_TRY(bfs_sources_init(g, w.ids[1], ns, d_parent, d_depth, s));
+  BYO_TRY(ids_to_bitmap(w.ids[0], ns, w.bits[0], w.words, s));
+  BYO_TRY(bitmap_clear(w.bits[1], w.words, s));
+  BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
+  BYO_HIP(hipMemsetAsync(d->ctl, 0, sizeof(pb_ctl), s));
+  pb_init_kernel<<<1, 64, 0, s>>>(d->ctl, (unsigned long long)ns, w.scan + ns);
+  BYO_HIP(hipGetLastError());
+  const int64_t m = g->m, words = w.words;
+  const int32_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
+  const int32_t tw = o.t_wave > 0 ? o.t_wave : 32;
+  const int32_t cap = (int32_t)std::min<int64_t>(o.max_levels > 0 ? o.max_levels : n + 1, 2147483647LL);
+  void *args[] = {(void *)&g->off, (void *)&g->nbr, (void *)&g->deg, (void *)&n, (void *)&m, (void *)&div,
+                  (void *)&tw, (void *)&d_parent, (void *)&d_depth, (void *)&w.visited, (void *)&words,
+                  (void *)&w.bits[0], (void *)&w.bits[1], (void *)&d->bits2, (void *)&w.ids[0], (void *)&w.ids[1],
+                  (void *)&d->ctl, (void *)&cap, (void *)&d->res};
+  {
+    ktimer_scope kt(BYO_K_SMALL_LOOP, s);
+    BYO_HIP(hipLaunchCooperativeKernel((const void *)bfs_persistent_kernel, dim3((unsigned)d->nblocks),
+                                       dim3(PB_THREADS), args, 0, s));
+  }
+  pb_result r;
+  BYO_TRY(sync_read(s, d->res, &r, sizeof(r)));
+  BYO_CHECK(!r.fail, BYO_EHIP, "persistent BFS: a grid barrier wait timed out");
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->levels = r.levels;
+    stats->device_levels = stats->levels;
+    stats->variant_count[BYO_V_PUSH_BUCKET] = (int64_t)r.push_levels;
+    stats->variant_count[BYO_V_PULL_THREAD] = (int64_t)r.pull_levels;
+    stats->reached = (int64_t)r.reached;
+    stats->edges = (int64_t)r.edges;
+  }
+  if (r.limit) return fail(BYO_ELIMIT, "BFS level cap reached");
+  return BYO_OK;
+}
+
+}  // namespace byo

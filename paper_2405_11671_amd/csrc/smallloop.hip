@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "gridsync.h"
 #include "internal.h"
 
 namespace byo {
@@ -45,10 +46,7 @@ struct small_loop_result {
 };
 
 struct dl_ctl {
-  unsigned arrive[DL_GROUPS * DL_PAD];
-  unsigned top[DL_PAD];
-  unsigned gen[DL_PAD];
-  unsigned fail[DL_PAD];
+  grid_sync sync;
   unsigned qcount[3][DL_GROUPS * DL_PAD];              // per level mod 3, per group
   unsigned long long qdeg[3][DL_GROUPS * DL_PAD / 2];  // degree sums, same layout (8 bytes each)
 };
@@ -60,58 +58,6 @@ struct dl_ws {
   int nblocks = 0;
   bool checked = false, usable = false;
 };
-
-// Relaxed agent-scope loads read the coherent copy without cache
-// maintenance; the barrier's fences order them (an acquire load in the spin
-// loop would invalidate the L2 on every poll).
-__device__ __forceinline__ unsigned ld_rlx(unsigned *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long ld_rlx64(unsigned long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid barrier; false if this workgroup gave up waiting or saw the failure
-// flag. Stores before the barrier are visible to every workgroup after it:
-// one release fence before arriving, one acquire fence after the wait.
-__device__ bool dl_barrier(dl_ctl *c, unsigned nblocks) {
-  __shared__ int ok;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    ok = 1;
-    const unsigned grp = blockIdx.x % DL_GROUPS;
-    const unsigned gsize = (nblocks - grp + DL_GROUPS - 1) / DL_GROUPS;
-    const unsigned ngroups = nblocks < (unsigned)DL_GROUPS ? nblocks : (unsigned)DL_GROUPS;
-    const unsigned g = ld_rlx(&c->gen[0]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    bool released = false;
-    unsigned a = __hip_atomic_fetch_add(&c->arrive[grp * DL_PAD], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a == gsize - 1) {
-      __hip_atomic_store(&c->arrive[grp * DL_PAD], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      unsigned t = __hip_atomic_fetch_add(&c->top[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (t == ngroups - 1) {
-        __hip_atomic_store(&c->top[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(&c->gen[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        released = true;
-      }
-    }
-    if (!released) {
-      unsigned spins = 0;
-      while (ld_rlx(&c->gen[0]) == g) {
-        if (++spins > DL_SPIN_LIMIT || ld_rlx(&c->fail[0])) {
-          __hip_atomic_store(&c->fail[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (ld_rlx(&c->fail[0])) ok = 0;
-  }
-  __syncthreads();
-  return ok != 0;
-}
 
 __global__ void __launch_bounds__(DL_THREADS) bfs_device_loop_kernel(
     const int64_t *__restrict__ off, const int32_t *__restrict__ nbr, const int32_t *__restrict__ deg,
@@ -223,7 +169,7 @@ __global__ void __launch_bounds__(DL_THREADS) bfs_device_loop_kernel(
     }
     __syncthreads();
     for (unsigned j = t; j < staged; j += DL_THREADS) qout[(int64_t)grp * DL_QCAP + s_base + j] = stage[j];
-    if (!dl_barrier(c, nblocks)) break;
+    if (!grid_barrier(&c->sync, nblocks, DL_SPIN_LIMIT)) break;
     // every workgroup reads the same totals and takes the same decision
     unsigned long long kn = 0, dn = 0;
     for (int gq = 0; gq < DL_GROUPS; ++gq) {
@@ -243,7 +189,7 @@ __global__ void __launch_bounds__(DL_THREADS) bfs_device_loop_kernel(
   }
   // hand the last frontier back as one list (levels run >= 1 here unless a barrier failed)
   const int Lf = levels;
-  if (!empty && Lf > 0 && !ld_rlx(&c->fail[0])) {
+  if (!empty && Lf > 0 && !ld_rlx(&c->sync.fail[0])) {
     const int p = Lf % 3;
     int32_t *qin = (Lf & 1) ? q1 : q0;
     unsigned pre[DL_GROUPS + 1];
@@ -259,7 +205,7 @@ __global__ void __launch_bounds__(DL_THREADS) bfs_device_loop_kernel(
     res->levels = levels;
     res->side = 0;
     res->empty = empty;
-    res->fail = ld_rlx(&c->fail[0]) ? 1 : 0;
+    res->fail = ld_rlx(&c->sync.fail[0]) ? 1 : 0;
     res->count = empty ? 0ull : kcur;
     res->degsum = empty ? 0ull : last_deg;
     res->reached = reached;

@@ -36,15 +36,53 @@ def check_batch(plist, **kw):
 
 
 def test_batch_config_64_er_graphs():
-    """The full batch: 64 ER graphs, n log-uniform in [2^10, 2^18], degree in [4, 32]."""
+    """The full batch: 64 ER graphs, n log-uniform in [2^10, 2^18], degree in
+    [4, 32]; one persistent launch (the default) and the host level loop."""
     st = check_batch(gen.batch_pairs(64, seed=3))
-    assert st["levels"] >= 2
+    assert st["levels"] >= 2 and st["device_levels"] == st["levels"]
+    st_host = check_batch(gen.batch_pairs(64, seed=3), persistent=0)
+    assert st_host["levels"] == st["levels"] and st_host["reached"] == st["reached"]
 
 
 @pytest.mark.parametrize("variant", list(range(6)))
 def test_batch_fixed_variants(variant):
     plist = gen.batch_pairs(12, seed=7, log2_hi=13.0)
-    check_batch(plist, selector=byo.SEL_FIXED, fixed_variant=variant)
+    check_batch(plist, selector=byo.SEL_FIXED, fixed_variant=variant, persistent=0)
+
+
+SHAPES = [
+    ("rmat16", lambda: [gen.rmat_pairs(16, 16, seed=12)]),
+    ("star", lambda: [graphs.star(70000)]),
+    ("path", lambda: [graphs.path(3000)]),
+    ("grid", lambda: [gen.grid_pairs(200, 150, 0.1, seed=3)]),
+    ("mixed", lambda: [graphs.star(5000), graphs.path(300), graphs.pairs(1, [], [], "single"),
+                       gen.grid_pairs(30, 40, 0.1, seed=2), gen.rmat_pairs(12, 8, seed=9), graphs.empty(70)]),
+]
+
+
+@pytest.mark.parametrize("divisor", [20, 1, 1 << 30])
+@pytest.mark.parametrize("name,mk", SHAPES, ids=[x[0] for x in SHAPES])
+def test_batch_persistent_launch(name, mk, divisor):
+    """Every level in one persistent launch, on skewed, long-path and mixed
+    graphs; divisor 1 keeps every level a push, 2^30 makes every level a
+    pull. Depths exact, parents valid, and the same counts as the host loop."""
+    plist = mk()
+    st = check_batch(plist, dense_divisor=divisor)
+    st_host = check_batch(plist, dense_divisor=divisor, persistent=0)
+    assert st["reached"] == st_host["reached"] and st["edges"] == st_host["edges"]
+    assert st["levels"] == st_host["levels"], (st, st_host)
+    pushes, pulls = st["variant_count"]["push_bucket"], st["variant_count"]["pull_thread"]
+    assert pushes + pulls == st["levels"]
+    if divisor == 1:
+        assert pulls == 0
+    if divisor == 1 << 30:
+        assert pushes == 0
+
+
+def test_batch_persistent_level_cap():
+    B = byo.Batch.from_pairs([graphs.path(100)])
+    with pytest.raises(byo.ByoError, match="ELIMIT"):
+        B.bfs([0], max_levels=10)
 
 
 def test_batch_mixed_shapes():
@@ -83,7 +121,7 @@ def test_batch_device_resident_loop(cap):
     B = byo.Batch.from_pairs(plist)
     ogs = [oracle.Graph.from_pairs(p) for p in plist]
     srcs = [first_non_isolated(og) for og in ogs]
-    depth, parent, st = B.bfs(srcs, small_frontier=cap)
+    depth, parent, st = B.bfs(srcs, small_frontier=cap, persistent=0)
     D, P = B.split(depth.cpu().numpy()), B.split(parent.cpu().numpy())
     for i, og in enumerate(ogs):
         want, _ = og.bfs(srcs[i])
