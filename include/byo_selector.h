@@ -42,9 +42,14 @@ extern "C" {
  * The device inference computes the same values from its level counters. */
 byo_status byo_selector_features(const byo_level_record *rec, float *out);
 
-/* The threshold rule the selector falls back to (pure host function). */
+/* The threshold rule the selector falls back to (pure host function).
+ * Dense (pull) when |U| + sum deg(U) > m / dense_divisor (the sparse/dense
+ * cutoff that Section 6.3 takes from Ligra and GBBS); otherwise a push whose
+ * load-balancing scheme is set by the frontier's degrees: max_deg_u, the
+ * largest degree in U, or -1 when it is not known (then max_deg, the graph's
+ * largest degree, stands in for it). The pull scheme uses max_deg and cv. */
 int32_t byo_heuristic_choice(int64_t k, int64_t degsum, int64_t m, int64_t max_deg, double cv, const byo_opts *opts,
-                             int32_t allow_pull);
+                             int32_t allow_pull, int64_t max_deg_u);
 
 /* out[N][K] = MLP(X[N][F]) (no normalisation applied; X is already normalised). */
 byo_status byo_mlp_forward(const float *d_params, const float *d_X, int32_t N, float *d_out, void *stream);

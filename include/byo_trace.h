@@ -41,7 +41,7 @@ typedef struct byo_level_record {
   int64_t max_deg;    /* graph maximum degree */
   double cv;          /* graph degree coefficient of variation */
   float ms;           /* device time of the level, conversions included */
-  float reserved;
+  int32_t max_deg_u;  /* largest degree in U (-1 when the level loop does not know it) */
 } byo_level_record;
 
 byo_status byo_trace_enable(int32_t on);

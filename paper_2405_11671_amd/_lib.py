@@ -72,10 +72,10 @@ class LevelRecord(ctypes.Structure):
                 ("dense_in", ctypes.c_int32), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
                 ("k", ctypes.c_int64), ("degsum", ctypes.c_int64), ("unvisited", ctypes.c_int64),
                 ("out_count", ctypes.c_int64), ("out_degsum", ctypes.c_int64), ("max_deg", ctypes.c_int64),
-                ("cv", ctypes.c_double), ("ms", ctypes.c_float), ("reserved", ctypes.c_float)]
+                ("cv", ctypes.c_double), ("ms", ctypes.c_float), ("max_deg_u", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 K_FAMILIES = ("bfs_push", "bfs_pull", "cc_push", "cc_pull", "pr_pull", "pr_chunk", "msbfs_push", "msbfs_pull",
@@ -151,7 +151,7 @@ SIGNATURES = {
     # batched execution, multi-source BFS, tracing and kernel timers (byo_trace.h), the learned
     # selector (byo_selector.h)
     "byo_selector_features": (st, [ctypes.POINTER(LevelRecord), fp]),
-    "byo_heuristic_choice": (i32, [i64, i64, i64, i64, dbl, ctypes.POINTER(Opts), i32]),
+    "byo_heuristic_choice": (i32, [i64, i64, i64, i64, dbl, ctypes.POINTER(Opts), i32, i64]),
     "byo_mlp_forward": (st, [vp, vp, i32, vp, vp]),
     "byo_mlp_loss_grad": (st, [vp, vp, vp, vp, i32, vp, vp, vp]),
     "byo_mlp_adam": (st, [vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),

@@ -253,7 +253,7 @@ template <bool WAVE, typename F>
 __global__ void __launch_bounds__(EM_BLOCK) cz_push_kernel(LevelArgs a, CzArgs z, F f) {
   __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
   int32_t *row = lds[threadIdx.x / BYO_WAVE];
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   // uniform trip count per workgroup: every lane reaches the wavefront part
   for (int64_t base = (int64_t)blockIdx.x * EM_BLOCK; base < a.k; base += (int64_t)gridDim.x * EM_BLOCK) {
     const int64_t i = base + threadIdx.x;
@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_kernel(LevelArgs a, CzArgs z
     const int32_t own = WAVE ? (nb < 1 ? nb : 1) : nb;
     for (int32_t j = 0; j < own; ++j)
       cz_block_for<false>(z.bytes, r, u, d, nb, j, [&](int32_t v) {
-        emit<F>(a, f.update(u, su, v, a.out_bits), v, degsum, count);
+        emit<F>(a, f.update(u, su, v, a.out_bits), v, degsum, count, maxdeg);
         return false;
       });
     if (WAVE) {
@@ -284,12 +284,12 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_kernel(LevelArgs a, CzArgs z
         const int32_t nbl = cz_nblocks(dl);
         for (int32_t j = 1; j < nbl; ++j) {
           const int32_t v = cz_wave_block(z.bytes, rl, el, ul, dl, nbl, j, row);
-          emit<F>(a, v >= 0 && f.update(ul, sul, v, a.out_bits), v, degsum, count);
+          emit<F>(a, v >= 0 && f.update(ul, sul, v, a.out_bits), v, degsum, count, maxdeg);
         }
       }
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // BFS pull: one wavefront per 64-vertex bitmap word; an unvisited lane
@@ -300,7 +300,7 @@ template <bool WAVE>
 __global__ void __launch_bounds__(EM_BLOCK) cz_bfs_pull_kernel(LevelArgs a, CzArgs z, BfsF f) {
   __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
   int32_t *row = lds[threadIdx.x / BYO_WAVE];
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < a.words; w += nwaves_total) {
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_bfs_pull_kernel(LevelArgs a, CzAr
     if (found) {
       f.parent[v] = par;
       f.depth[v] = f.newdepth;
-      degsum += (unsigned long long)a.deg[v];
+      tally_degree((unsigned long long)a.deg[v], degsum, maxdeg);
     }
     const uint64_t m = __ballot(found);
     if (lane_id() == 0) {
@@ -378,13 +378,13 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_bfs_pull_kernel(LevelArgs a, CzAr
       if (found) a.out_ids[b + __popcll(m & lanemask_lt())] = v;
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // Min-label pull: every vertex takes the least label over its neighbours in U.
 template <bool WAVE>
 __global__ void __launch_bounds__(EM_BLOCK) cz_cc_pull_kernel(LevelArgs a, CzArgs z, CcF f) {
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < a.words; w += nwaves_total) {
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_cc_pull_kernel(LevelArgs a, CzArg
     const bool changed = valid && best < lv;
     if (changed) {
       atomicMin(&f.label[v], best);
-      degsum += (unsigned long long)a.deg[v];
+      tally_degree((unsigned long long)a.deg[v], degsum, maxdeg);
     }
     const uint64_t m = __ballot(changed);
     if (lane_id() == 0) {
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_cc_pull_kernel(LevelArgs a, CzArg
       count += (unsigned long long)__popcll(m);
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // fnb[i] = blocks of frontier vertex ids[i]; fnb[k] = 0
@@ -464,7 +464,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_blocks_kernel(LevelArgs a, C
                                                                   const int64_t *__restrict__ fpre, F f) {
   __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
   int32_t *row = lds[threadIdx.x / BYO_WAVE];
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const int64_t total = fpre[a.k];
   // Lane l of wavefront gw takes blocks gw + nw * (l + 64 t): consecutive
   // blocks (one long list) land in different wavefronts. A block of more than
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_blocks_kernel(LevelArgs a, C
     const bool wide = c > CZ_WAVE_MIN;
     if (c > 0 && !wide)
       cz_block_for<false>(z.bytes, r, u, d, cz_nblocks(d), j, [&](int32_t v) {
-        emit<F>(a, f.update(u, su, v, a.out_bits), v, degsum, count);
+        emit<F>(a, f.update(u, su, v, a.out_bits), v, degsum, count, maxdeg);
         return false;
       });
     uint64_t pm = __ballot(wide);
@@ -503,10 +503,10 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_push_blocks_kernel(LevelArgs a, C
       const int32_t jl = read_lane_i32(j, l);
       const int64_t rl = (int64_t)read_lane_u64((uint64_t)r, l);
       const int32_t v = cz_wave_block(z.bytes, rl, z.coff[ul + 1], ul, dl, cz_nblocks(dl), jl, row);
-      emit<F>(a, v >= 0 && f.update(ul, sul, v, a.out_bits), v, degsum, count);
+      emit<F>(a, v >= 0 && f.update(ul, sul, v, a.out_bits), v, degsum, count, maxdeg);
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 unsigned cz_pull_grid(int64_t words) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 3) / 4, 4096)); }

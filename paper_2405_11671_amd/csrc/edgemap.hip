@@ -49,7 +49,7 @@ __device__ __forceinline__ void wave_count(bool pred, unsigned long long *count)
 
 template <typename F>
 __global__ void __launch_bounds__(EM_BLOCK) push_thread_kernel(LevelArgs a, F f) {
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   for (int64_t i = (int64_t)blockIdx.x * EM_BLOCK + threadIdx.x; i - threadIdx.x < a.k;
        i += (int64_t)gridDim.x * EM_BLOCK) {
     if (i < a.k) {
@@ -59,16 +59,16 @@ __global__ void __launch_bounds__(EM_BLOCK) push_thread_kernel(LevelArgs a, F f)
       for (int64_t e = a.off[u]; e < end; ++e) {
         int32_t v = a.nbr[e];
         bool ok = f.update(u, su, v, a.out_bits);
-        emit<F>(a, ok, v, degsum, count);
+        emit<F>(a, ok, v, degsum, count, maxdeg);
       }
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 template <typename F>
 __global__ void __launch_bounds__(EM_BLOCK) push_wave_kernel(LevelArgs a, F f) {
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   int64_t wave = ((int64_t)blockIdx.x * EM_BLOCK + threadIdx.x) / BYO_WAVE;
   int64_t nwaves = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   for (int64_t i = wave; i < a.k; i += nwaves) {
@@ -82,10 +82,10 @@ __global__ void __launch_bounds__(EM_BLOCK) push_wave_kernel(LevelArgs a, F f) {
         v = a.nbr[e];
         ok = f.update(u, su, v, a.out_bits);
       }
-      emit<F>(a, ok, v, degsum, count);
+      emit<F>(a, ok, v, degsum, count, maxdeg);
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // Degree-bucketed push: in each chunk of EM_BLOCK frontier vertices, those
@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
   __shared__ int32_t s_u[EM_BLOCK];
   __shared__ int32_t s_su[EM_BLOCK];
   __shared__ int s_nbig;
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   for (int64_t c0 = (int64_t)blockIdx.x * EM_BLOCK; c0 < a.k; c0 += (int64_t)gridDim.x * EM_BLOCK) {
     int64_t i = c0 + threadIdx.x;
     int32_t u = -1, su = 0, d = 0;
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
           v = a.nbr[e];
           ok = f.update(bu, bsu, v, a.out_bits);
         }
-        emit<F>(a, ok, v, degsum, count);
+        emit<F>(a, ok, v, degsum, count, maxdeg);
       }
     }
     uint64_t wm = __ballot(d >= a.t_wave && d < a.t_block);
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
           v = a.nbr[e];
           ok = f.update(wu, wsu, v, a.out_bits);
         }
-        emit<F>(a, ok, v, degsum, count);
+        emit<F>(a, ok, v, degsum, count, maxdeg);
       }
     }
     if (u >= 0 && d < a.t_wave) {
@@ -148,12 +148,12 @@ __global__ void __launch_bounds__(EM_BLOCK) push_bucket_kernel(LevelArgs a, F f)
       for (int64_t e = beg; e < end; ++e) {
         int32_t v = a.nbr[e];
         bool ok = f.update(u, su, v, a.out_bits);
-        emit<F>(a, ok, v, degsum, count);
+        emit<F>(a, ok, v, degsum, count, maxdeg);
       }
     }
     __syncthreads();
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // Edge-balanced push: workgroup b owns edges [b*TILE, (b+1)*TILE) of the
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
   __shared__ int64_t s_lo, s_hi;
   __shared__ unsigned s_cnt;
   __shared__ unsigned long long s_dst;
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const long long total = a.scan[a.k] < a.total ? a.scan[a.k] : a.total;  // never past the real edge count
   const long long ntiles = (total + PE_TILE - 1) / PE_TILE;
   if (threadIdx.x == 0) s_cnt = 0;
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
         else ++count;
         if (!F::kDenseFromUpdate && a.out_bits)
           atomicOr((unsigned long long *)&a.out_bits[v >> 6], 1ull << (v & 63));
-        degsum += (unsigned long long)a.deg[v];
+        tally_degree((unsigned long long)a.deg[v], degsum, maxdeg);
       }
     }
     if (a.out_ids) {
@@ -257,7 +257,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
     }
   }
   if (a.out_ids) flush();
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // ---------------------------------------------------------------- pull kernels (BFS)
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(EM_BLOCK) push_edge_kernel(LevelArgs a, F f) {
 // wavefront owns its word of `visited` and the output bitmap, so no atomics.
 template <bool WAVE_ASSIST>
 __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f) {
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < a.words; w += nwaves_total) {
@@ -332,7 +332,7 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
     if (found) {
       f.parent[v] = par;
       f.depth[v] = f.newdepth;
-      degsum += (unsigned long long)a.deg[v];
+      tally_degree((unsigned long long)a.deg[v], degsum, maxdeg);
     }
     uint64_t m = __ballot(found);
     if (lane_id() == 0) {
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
       }
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // ---------------------------------------------------------------- pull kernel (min-label)
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(EM_BLOCK) bfs_pull_kernel(LevelArgs a, BfsF f)
 // wavefront when WAVE_ASSIST.
 template <bool WAVE_ASSIST>
 __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < a.words; w += nwaves_total) {
@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
     bool changed = valid && best < lv;
     if (changed) {
       atomicMin(&f.label[v], best);
-      degsum += (unsigned long long)a.deg[v];
+      tally_degree((unsigned long long)a.deg[v], degsum, maxdeg);
     }
     uint64_t m = __ballot(changed);
     if (lane_id() == 0) {
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
       count += (unsigned long long)__popcll(m);
     }
   }
-  finish_level<EM_BLOCK>(a, degsum, count);
+  finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
 // Pointer jumping: label[v] <- label[label[v]] until it stops decreasing.
@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_pull_kernel(LevelArgs a, CcF f) {
 __global__ void __launch_bounds__(EM_BLOCK) cc_shortcut_kernel(int32_t *label, const int32_t *__restrict__ deg,
                                                                int64_t n, int64_t words, uint64_t *out_bits,
                                                                byo_counters *ctr) {
-  unsigned long long degsum = 0, count = 0;
+  unsigned long long degsum = 0, count = 0, maxdeg = 0;
   const int64_t nwaves_total = (int64_t)gridDim.x * (EM_BLOCK / BYO_WAVE);
   int64_t w = (int64_t)xcd_block(blockIdx.x, gridDim.x) * (EM_BLOCK / BYO_WAVE) + threadIdx.x / BYO_WAVE;
   for (; w < words; w += nwaves_total) {
@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_shortcut_kernel(int32_t *label, c
     if (m) {
       uint64_t old = out_bits[w];
       uint64_t fresh = m & ~old;
-      if (changed && ((fresh >> lane_id()) & 1ull)) degsum += (unsigned long long)deg[v64];
+      if (changed && ((fresh >> lane_id()) & 1ull)) tally_degree((unsigned long long)deg[v64], degsum, maxdeg);
       if (lane_id() == 0) {
         out_bits[w] = old | m;
         count += (unsigned long long)__popcll(fresh);
@@ -453,9 +453,11 @@ __global__ void __launch_bounds__(EM_BLOCK) cc_shortcut_kernel(int32_t *label, c
   }
   unsigned long long t = block_sum<unsigned long long, EM_BLOCK>(degsum);
   unsigned long long c = block_sum<unsigned long long, EM_BLOCK>(count);
+  unsigned long long mx = block_max_u64<EM_BLOCK>(maxdeg);
   if (threadIdx.x == 0) {
     if (t) atomicAdd(&ctr->degsum, t);
     if (c) atomicAdd(&ctr->count, c);
+    if (mx) atomicMax(&ctr->maxdeg, mx);
   }
 }
 

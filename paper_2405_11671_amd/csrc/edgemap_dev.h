@@ -92,9 +92,17 @@ struct CcF {
 // atomic; otherwise the count stays in a register (`count`) and is added once
 // per workgroup in finish_level: same-address atomics from every wavefront of
 // a large grid serialise and would dominate the level.
+// The degree of an emitted vertex goes into the level's degree sum and its
+// largest degree (the frontier statistics of the next level).
+__device__ __forceinline__ void tally_degree(unsigned long long d, unsigned long long &degsum,
+                                             unsigned long long &maxdeg) {
+  degsum += d;
+  maxdeg = d > maxdeg ? d : maxdeg;
+}
+
 template <typename F>
 __device__ __forceinline__ void emit(const LevelArgs &a, bool pred, int32_t v, unsigned long long &degsum,
-                                     unsigned long long &count) {
+                                     unsigned long long &count, unsigned long long &maxdeg) {
   if (a.out_ids)
     wave_append(pred, v, a.out_ids, &a.ctr->count);
   else
@@ -102,23 +110,40 @@ __device__ __forceinline__ void emit(const LevelArgs &a, bool pred, int32_t v, u
   if (pred) {
     if (!F::kDenseFromUpdate && a.out_bits)
       atomicOr((unsigned long long *)&a.out_bits[v >> 6], 1ull << (v & 63));
-    degsum += (unsigned long long)a.deg[v];
+    tally_degree((unsigned long long)a.deg[v], degsum, maxdeg);
   }
 }
 
+// Block maximum; result valid in every thread. All threads must call it.
 template <int BLOCK>
-__device__ __forceinline__ void finish_level(const LevelArgs &a, unsigned long long degsum,
-                                             unsigned long long count) {
+__device__ __forceinline__ unsigned long long block_max_u64(unsigned long long v) {
+  __shared__ unsigned long long part[BLOCK / BYO_WAVE];
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) part[threadIdx.x / BYO_WAVE] = v;
+  __syncthreads();
+  unsigned long long r = 0;
+#pragma unroll
+  for (int i = 0; i < BLOCK / BYO_WAVE; ++i) r = part[i] > r ? part[i] : r;
+  return r;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void finish_level(const LevelArgs &a, unsigned long long degsum, unsigned long long count,
+                                             unsigned long long maxdeg) {
   unsigned long long t = block_sum<unsigned long long, BLOCK>(degsum);
   unsigned long long c = block_sum<unsigned long long, BLOCK>(count);
+  unsigned long long mx = block_max_u64<BLOCK>(maxdeg);
   if (threadIdx.x == 0) {
     if (t) atomicAdd(&a.ctr->degsum, t);
     if (c) atomicAdd(&a.ctr->count, c);
+    if (mx) atomicMax(&a.ctr->maxdeg, mx);
     if (blockIdx.x == 0 && a.ctr_clear) {
       a.ctr_clear->count = 0;
       a.ctr_clear->degsum = 0;
       a.ctr_clear->aux0 = 0;
       a.ctr_clear->aux1 = 0;
+      a.ctr_clear->maxdeg = 0;
     }
   }
 }

@@ -130,6 +130,7 @@ struct byo_counters {
   unsigned long long degsum;  // sum of their degrees
   unsigned long long aux0;    // variant-specific (e.g. edges inspected)
   unsigned long long aux1;
+  unsigned long long maxdeg;  // largest degree among them (edgeMap levels)
 };
 #define BYO_COUNTER_SLOTS 4
 
@@ -426,15 +427,20 @@ struct ktimer_scope {
 // (the sparse/dense cutoff of Section 6.3); sparse pushes are edge-balanced on
 // skewed graphs or heavy frontiers, wavefront-per-vertex for high average
 // degree, thread-per-vertex otherwise.
+// max_deg is the graph's largest degree (pulls scan the lists of unvisited
+// vertices); frontier_max_deg, when known (>= 0), the largest degree in U,
+// which sets how unequal a push's lists are.
 __host__ __device__ inline int heuristic_rule(int64_t k, int64_t degsum, int64_t m, int64_t max_deg, double cv,
-                                              int div, int t_wave, int t_block, bool allow_pull) {
+                                              int div, int t_wave, int t_block, bool allow_pull,
+                                              int64_t frontier_max_deg = -1) {
   if (div <= 0) div = 20;
   if (t_wave <= 0) t_wave = 32;
   if (t_block <= 0) t_block = 4096;
   if (allow_pull && k + degsum > m / div)
     return (cv > 1.0 || max_deg > 4 * (int64_t)t_wave) ? BYO_V_PULL_WAVE : BYO_V_PULL_THREAD;
   double avg = k > 0 ? (double)degsum / (double)k : 0.0;
-  if (max_deg >= t_block || degsum >= 65536) return BYO_V_PUSH_EDGE;
+  const int64_t push_max = frontier_max_deg >= 0 ? frontier_max_deg : max_deg;
+  if (push_max >= t_block || degsum >= 65536) return BYO_V_PUSH_EDGE;
   if (avg >= t_wave) return BYO_V_PUSH_WAVE;
   return BYO_V_PUSH_THREAD;
 }
@@ -461,6 +467,7 @@ struct level_features {
   int64_t n, m, k, degsum, unvisited, max_deg, level;
   double cv;
   bool dense_in;
+  int64_t frontier_max_deg = -1;  // largest degree in U (-1: not known)
 };
 int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull);
 

@@ -319,11 +319,12 @@ byo_status byo_selector_features(const byo_level_record *r, float *out) {
 }
 
 int32_t byo_heuristic_choice(int64_t k, int64_t degsum, int64_t m, int64_t max_deg, double cv, const byo_opts *opts,
-                             int32_t allow_pull) {
+                             int32_t allow_pull, int64_t max_deg_u) {
   byo_opts o;
   byo_opts_default(&o);
   if (opts) o = *opts;
-  return heuristic_rule(k, degsum, m, max_deg, cv, o.dense_divisor, o.t_wave, o.t_block, allow_pull != 0);
+  return heuristic_rule(k, degsum, m, max_deg, cv, o.dense_divisor, o.t_wave, o.t_block, allow_pull != 0,
+                        max_deg_u);
 }
 
 byo_status byo_mlp_forward(const float *d_params, const float *d_X, int32_t N, float *d_out, void *stream) {

@@ -18,7 +18,8 @@ namespace byo {
 static bool is_pull(int v) { return v == BYO_V_PULL_THREAD || v == BYO_V_PULL_WAVE; }
 
 int heuristic_variant(const byo_opts &o, const level_features &f, bool allow_pull) {
-  return heuristic_rule(f.k, f.degsum, f.m, f.max_deg, f.cv, o.dense_divisor, o.t_wave, o.t_block, allow_pull);
+  return heuristic_rule(f.k, f.degsum, f.m, f.max_deg, f.cv, o.dense_divisor, o.t_wave, o.t_block, allow_pull,
+                        f.frontier_max_deg);
 }
 
 int choose_variant(const byo_opts &o, const level_features &f, bool allow_pull) {
@@ -50,6 +51,7 @@ __global__ void bfs_init_kernel(int32_t *parent, int32_t *depth, const int32_t *
     ctr[threadIdx.x].degsum = 0;
     ctr[threadIdx.x].aux0 = 0;
     ctr[threadIdx.x].aux1 = 0;
+    ctr[threadIdx.x].maxdeg = 0;
   }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nsrc) {
@@ -94,7 +96,29 @@ __global__ void zero_counters_kernel(byo_counters *ctr) {
     ctr[threadIdx.x].degsum = 0;
     ctr[threadIdx.x].aux0 = 0;
     ctr[threadIdx.x].aux1 = 0;
+    ctr[threadIdx.x].maxdeg = 0;
   }
+}
+
+// The first frontier's statistics into one counter slot (read back once):
+// the degree sum from the frontier scan, the largest degree by a max over the
+// sources.
+__global__ void src_stats_kernel(const int32_t *__restrict__ ids, int64_t k, const int32_t *__restrict__ deg,
+                                 const long long *__restrict__ scan_total, byo_counters *slot) {
+  unsigned long long mx = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long d = (unsigned long long)deg[ids[i]];
+    mx = d > mx ? d : mx;
+  }
+  mx = wave_max(mx);
+  if (lane_id() == 0 && mx) atomicMax(&slot->maxdeg, mx);
+  if (blockIdx.x == 0 && threadIdx.x == 0) slot->degsum = (unsigned long long)*scan_total;
+}
+
+// The largest degree in a frontier as its level reported it; a level whose
+// kernels do not track it leaves 0 beside a nonzero degree sum: not known.
+static int64_t frontier_max(const byo_counters &c) {
+  return (c.maxdeg == 0 && c.degsum > 0) ? -1 : (int64_t)c.maxdeg;
 }
 
 static byo_status read_slot(byo_graph *g, int slot, hipStream_t s, byo_counters *out) {
@@ -152,6 +176,7 @@ struct level_timer {
     r.out_count = out_count;
     r.out_degsum = out_degsum;
     r.max_deg = g->max_deg;
+    r.max_deg_u = (int32_t)f.frontier_max_deg;
     r.cv = g->cv_deg;
     r.ms = ms;
     trace_push(r);
@@ -167,6 +192,7 @@ struct frontier {
   int cur = 0;
   bool sparse = false, dense = false;
   int64_t k = 0, degsum = 0;
+  int64_t maxdeg = -1;  // largest degree in the frontier (-1: not known)
 };
 
 static byo_status make_sparse(byo_graph *g, frontier &fr, hipStream_t s) {
@@ -267,7 +293,13 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
   long long dsum = 0;
   BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
   bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
-  BYO_TRY(sync_read(s, w.scan + ns, &dsum, sizeof(dsum)));
+  // slot BYO_COUNTER_SLOTS - 1 is next written by level 3 and cleared by level 1
+  src_stats_kernel<<<(unsigned)std::min<int64_t>((ns + 255) / 256, 1024), 256, 0, s>>>(
+      w.ids[0], ns, g->deg, w.scan + ns, w.ctr + (BYO_COUNTER_SLOTS - 1));
+  BYO_HIP(hipGetLastError());
+  byo_counters c0;
+  BYO_TRY(read_slot(g, BYO_COUNTER_SLOTS - 1, s, &c0));
+  dsum = (long long)c0.degsum;
 
   byo_run_stats st;
   std::memset(&st, 0, sizeof(st));
@@ -276,6 +308,7 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
   fr.sparse = true;
   fr.k = ns;
   fr.degsum = dsum;
+  fr.maxdeg = frontier_max(c0);
   // without degree() each frontier's degree sum is mapped at its level
   const bool mapped_deg = (o.api_omit & BYO_API_NO_DEGREE) != 0;
   int64_t reached = ns, edges = mapped_deg ? 0 : dsum;
@@ -309,6 +342,7 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
       fr.dense = false;
       fr.k = r.count;
       fr.degsum = r.degsum;
+      fr.maxdeg = -1;  // the device loop does not report it
       zero_counters_kernel<<<1, 64, 0, s>>>(w.ctr);  // ring slots were not advanced on the device
       BYO_HIP(hipGetLastError());
       if (level >= cap) {
@@ -324,6 +358,7 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
     }
     level_features f = features(g, fr.k, fr.degsum, n - reached, level, fr.dense && !fr.sparse);
     f.m = m_seen;
+    f.frontier_max_deg = mapped_deg ? -1 : fr.maxdeg;
     int v = pick(o, f, use_mlp);
     if (o.api_omit) v = api_variant((uint32_t)o.api_omit, v, true);
     if (o.compressed) v = cz_variant(v);
@@ -362,6 +397,7 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
     fr.dense = is_pull(v);
     fr.k = (int64_t)c.count;
     fr.degsum = (int64_t)c.degsum;
+    fr.maxdeg = frontier_max(c);
   }
   st.levels = level;
   st.reached = reached;
@@ -422,6 +458,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
   fr.dense = true;
   fr.k = n;
   fr.degsum = g->m;
+  fr.maxdeg = g->max_deg;
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   int32_t round = 0;
   bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
@@ -438,6 +475,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     }
     level_features f = features(g, fr.k, fr.degsum, n, round, fr.dense && !fr.sparse);
     f.m = m_seen;
+    f.frontier_max_deg = (o.api_omit & BYO_API_NO_DEGREE) ? -1 : fr.maxdeg;
     int v = pick(o, f, use_mlp);
     if (o.api_omit) v = api_variant((uint32_t)o.api_omit, v, false);
     if (o.compressed) v = cz_variant(v);
@@ -475,6 +513,7 @@ byo_status byo_cc(byo_graph *g, int32_t *d_label, const byo_opts *opts, void *st
     fr.sparse = !is_pull(v) && !shortcut;
     fr.k = (int64_t)c.count;
     fr.degsum = (int64_t)c.degsum;
+    fr.maxdeg = frontier_max(c);
   }
   st.levels = round;
   if (stats) *stats = st;

@@ -42,7 +42,7 @@ def heuristic_choice(rec, opts=None, allow_pull=True) -> int:
     o = opts if opts is not None else _lib.default_opts()
     return int(_lib.load().byo_heuristic_choice(int(rec["k"]), int(rec["degsum"]), int(rec["m"]),
                                                 int(rec["max_deg"]), float(rec["cv"]), ctypes.byref(o),
-                                                1 if allow_pull else 0))
+                                                1 if allow_pull else 0, int(rec.get("max_deg_u", -1))))
 
 
 def collect(g, algo: int = ALGO_BFS, src: int = 0, repeats: int = 2, opts=None, tag: str = ""):
