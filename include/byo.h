@@ -119,11 +119,14 @@ typedef struct byo_opts {
                              the grid (PUSH_EDGE), pull by thread or wavefront, PageRank's pull over
                              the lists.
                              With api_omit != 0: BYO_EINVAL. 0 = the CSR (default) */
-  int32_t persistent;     /* byo_batch_bfs: 1 (default) = every level in one persistent
-                             cooperative launch with grid barriers between levels (direction
-                             by the threshold rule on the device; falls back to the host loop
-                             where cooperative launches are not supported); 0 = the
-                             host-driven level loop, or hipGraph levels with use_graph = 1 */
+  int32_t persistent;     /* byo_batch_bfs and byo_kcore: 1 (default) = the whole traversal in
+                             one persistent cooperative launch with grid barriers between its
+                             phases (the batch's levels take their direction by the threshold
+                             rule on the device; k-core's sub-rounds their removal scheme by
+                             the same frontier tests as the host loop); where cooperative
+                             launches are not supported, and for k-core with api_omit != 0,
+                             the host loop runs instead. 0 = the host-driven loop (for the
+                             batch also hipGraph levels with use_graph = 1) */
 } byo_opts;
 
 /* Container functions a traversal can be denied (Section 4.2 defines the
@@ -394,9 +397,11 @@ byo_status byo_bc(byo_graph *g, int64_t src, double *d_delta, double *d_sigma, i
  * frontier's degree sum is at least 2^15 or a list is longer than 16, else
  * one vertex per lane) until
  * none is left, k then jumping to the least remaining degree. d_core: device int32
- * [n]. Returns when done (it reads each sub-round's size back). BYO_ELIMIT
- * if max_levels sub-rounds do not finish. stats: levels = sub-rounds,
- * edges = sum of the removed vertices' degrees. */
+ * [n]. Returns when done: with opts->persistent (default) every phase runs in
+ * one cooperative launch, else the host loop reads each sub-round's size
+ * back. BYO_ELIMIT if max_levels sub-rounds do not finish; BYO_EHIP if a
+ * grid barrier wait of the persistent launch times out. stats: levels =
+ * sub-rounds, edges = sum of the removed vertices' degrees. */
 byo_status byo_kcore(byo_graph *g, int32_t *d_core, const byo_opts *opts, void *stream, byo_run_stats *stats);
 
 /* Maximal independent set (Table algs-list, covering problems): the greedy

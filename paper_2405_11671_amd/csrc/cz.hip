@@ -213,11 +213,9 @@ byo_status cz_build(const byo_graph *g, byo_cz *z, hipStream_t s) {
                                                        z->bytes);
   BYO_HIP(hipGetLastError());
   // buffers of the block-parallel push
-  BYO_HIP(hipMalloc(&z->fnb, sizeof(int64_t) * (size_t)(n + 1)));
-  BYO_HIP(hipMalloc(&z->fpre, sizeof(int64_t) * (size_t)(n + 1)));
-  BYO_HIP(rocprim::exclusive_scan(nullptr, z->scan_bytes, z->fnb, z->fpre, (int64_t)0, (size_t)n + 1,
-                                  rocprim::plus<int64_t>(), s));
-  BYO_HIP(hipMalloc(&z->scan_tmp, std::max<size_t>(z->scan_bytes, 1)));
+  BYO_HIP(hipMalloc(&z->fpre, sizeof(long long) * (size_t)(n + 1)));
+  z->fpart_cap = scan_partials_needed(n);
+  BYO_HIP(hipMalloc(&z->fpart, sizeof(long long) * (size_t)z->fpart_cap));
   BYO_HIP(hipStreamSynchronize(s));
   return BYO_OK;
 }
@@ -448,20 +446,13 @@ __global__ void __launch_bounds__(EM_BLOCK) cz_cc_pull_kernel(LevelArgs a, CzArg
   finish_level<EM_BLOCK>(a, degsum, count, maxdeg);
 }
 
-// fnb[i] = blocks of frontier vertex ids[i]; fnb[k] = 0
-__global__ void cz_frontier_blocks_kernel(const int32_t *__restrict__ ids, const int32_t *__restrict__ deg, int64_t k,
-                                          int64_t *__restrict__ fnb) {
-  for (int64_t i = (int64_t)blockIdx.x * CZ_THREADS + threadIdx.x; i <= k; i += (int64_t)gridDim.x * CZ_THREADS)
-    fnb[i] = i < k ? (int64_t)cz_nblocks(deg[ids[i]]) : 0;
-}
-
 // Block-parallel push (the edge-balanced push of the byte-coded lists): the
 // frontier's blocks are numbered through fpre (exclusive scan of blocks per
 // frontier vertex, fpre[k] = all) and every lane of the grid decodes whole
 // blocks, so one long list spreads over as many lanes as it has blocks.
 template <typename F>
 __global__ void __launch_bounds__(EM_BLOCK) cz_push_blocks_kernel(LevelArgs a, CzArgs z,
-                                                                  const int64_t *__restrict__ fpre, F f) {
+                                                                  const long long *__restrict__ fpre, F f) {
   __shared__ int32_t lds[EM_BLOCK / BYO_WAVE][BYO_WAVE];
   int32_t *row = lds[threadIdx.x / BYO_WAVE];
   unsigned long long degsum = 0, count = 0, maxdeg = 0;
@@ -517,14 +508,7 @@ template <typename F>
 byo_status cz_launch_push(int variant, const byo_cz *cz, const LevelArgs &a, const CzArgs &z, const F &f,
                           long long known_total, hipStream_t s) {
   if (variant == BYO_V_PUSH_EDGE && a.k > 0) {
-    cz_frontier_blocks_kernel<<<cz_grid(a.k + 1), CZ_THREADS, 0, s>>>(a.in_ids, a.deg, a.k, cz->fnb);
-    BYO_HIP(hipGetLastError());
-    size_t q = 0;
-    BYO_HIP(rocprim::exclusive_scan(nullptr, q, cz->fnb, cz->fpre, (int64_t)0, (size_t)a.k + 1,
-                                    rocprim::plus<int64_t>(), s));
-    BYO_CHECK(q <= cz->scan_bytes, BYO_ESTATE, "frontier scan needs more workspace than sized at build");
-    BYO_HIP(rocprim::exclusive_scan(cz->scan_tmp, q, cz->fnb, cz->fpre, (int64_t)0, (size_t)a.k + 1,
-                                    rocprim::plus<int64_t>(), s));
+    BYO_TRY(scan_degree_units(a.deg, a.in_ids, a.k, CZ_BLOCK, cz->fpre, cz->fpart, cz->fpart_cap, s));
     // at most k + degsum / 64 blocks; about 16 per wavefront
     const int64_t bound = a.k + std::max<long long>(known_total, 0) / CZ_BLOCK;
     const int64_t per = 16 * (EM_BLOCK / BYO_WAVE);
@@ -569,9 +553,8 @@ void cz_free(byo_cz *z) {
   if (!z) return;
   if (z->coff) (void)hipFree(z->coff);
   if (z->bytes) (void)hipFree(z->bytes);
-  if (z->fnb) (void)hipFree(z->fnb);
   if (z->fpre) (void)hipFree(z->fpre);
-  if (z->scan_tmp) (void)hipFree(z->scan_tmp);
+  if (z->fpart) (void)hipFree(z->fpart);
   delete z;
 }
 

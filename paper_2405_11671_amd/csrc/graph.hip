@@ -181,6 +181,7 @@ void ws_free(byo_workspace &w) {
   gm_release(w);
   dl_release(w);
   pb_release(w.pbfs);
+  kp_release(w.kcp);
   w = byo_workspace();
 }
 

@@ -144,10 +144,9 @@ struct byo_cz {
   int64_t *coff = nullptr;   // [n + 1]
   uint8_t *bytes = nullptr;  // [coff[n]], padded
   int64_t nbytes = 0;
-  int64_t *fnb = nullptr;    // [n + 1] blocks per frontier vertex (block-parallel push)
-  int64_t *fpre = nullptr;   // [n + 1] their exclusive scan
-  void *scan_tmp = nullptr;  // scan workspace for n + 1 entries
-  size_t scan_bytes = 0;
+  long long *fpre = nullptr;   // [n + 1] exclusive scan of the frontier's blocks (block-parallel push)
+  long long *fpart = nullptr;  // [scan_partials_needed(n)] that scan's block partials
+  int64_t fpart_cap = 0;
 };
 }  // namespace byo
 
@@ -192,6 +191,7 @@ struct byo_workspace {
   void *gmode = nullptr;             // captured level graph (graphmode.hip)
   void *dloop = nullptr;             // device-resident level loop buffers (smallloop.hip)
   void *pbfs = nullptr;              // persistent-launch BFS buffers (persistent.hip)
+  void *kcp = nullptr;               // persistent-launch k-core buffers (kcore.hip)
 };
 
 struct byo_graph {
@@ -352,6 +352,11 @@ struct no_alloc_scope {
 };
 bool noalloc_active();
 
+// exclusive scan of ceil(deg(ids[i]) / per) (per = 1: the degrees themselves);
+// partial needs scan_partials_needed(k) entries
+byo_status scan_degree_units(const int32_t *deg, const int32_t *ids, int64_t k, int32_t per, long long *scan,
+                             long long *partial, int64_t partial_cap, hipStream_t s);
+int64_t scan_partials_needed(int64_t k);
 // the same over an explicit degree array
 byo_status scan_degrees(const int32_t *deg, const int32_t *ids, int64_t k, long long *scan, long long *partial,
                         int64_t partial_cap, hipStream_t s);
@@ -498,6 +503,7 @@ bool bfs_persistent_usable(byo_graph *g);
 byo_status bfs_persistent_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,
                               const byo_opts &o, hipStream_t s, byo_run_stats *stats);
 void pb_release(void *p);
+void kp_release(void *p);
 
 // BFS from distinct sources (traverse.hip)
 byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_depth, int32_t *d_parent,

@@ -134,22 +134,27 @@ byo_status ids_to_bitmap(const int32_t *ids, int64_t k, uint64_t *bits, int64_t 
 constexpr int DS_ITEMS = 8;
 constexpr int DS_TILE = CB_THREADS * DS_ITEMS;  // 2048 frontier entries per block
 
+// units of a list of d entries: d itself (per = 1), or its blocks of `per`
+__device__ __forceinline__ long long deg_units(int32_t d, int32_t per) {
+  return per == 1 ? (long long)d : (long long)((d + per - 1) / per);
+}
+
 __global__ void __launch_bounds__(CB_THREADS) deg_scan_reduce_kernel(const int32_t *__restrict__ ids, int64_t k,
-                                                                     const int32_t *__restrict__ deg,
+                                                                     const int32_t *__restrict__ deg, int32_t per,
                                                                      long long *__restrict__ partial) {
   int64_t i0 = (int64_t)blockIdx.x * DS_TILE;
   long long c = 0;
 #pragma unroll
   for (int j = 0; j < DS_ITEMS; ++j) {
     int64_t i = i0 + j * CB_THREADS + threadIdx.x;
-    if (i < k) c += deg[ids[i]];
+    if (i < k) c += deg_units(deg[ids[i]], per);
   }
   long long t = block_sum<long long, CB_THREADS>(c);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 __global__ void __launch_bounds__(CB_THREADS) deg_scan_write_kernel(const int32_t *__restrict__ ids, int64_t k,
-                                                                    const int32_t *__restrict__ deg,
+                                                                    const int32_t *__restrict__ deg, int32_t per,
                                                                     const long long *__restrict__ partial,
                                                                     int64_t nb, long long *__restrict__ scan) {
   // each thread owns DS_ITEMS consecutive entries
@@ -158,7 +163,7 @@ __global__ void __launch_bounds__(CB_THREADS) deg_scan_write_kernel(const int32_
   long long c = 0;
 #pragma unroll
   for (int j = 0; j < DS_ITEMS; ++j) {
-    d[j] = (i0 + j < k) ? (long long)deg[ids[i0 + j]] : 0;
+    d[j] = (i0 + j < k) ? deg_units(deg[ids[i0 + j]], per) : 0;
     c += d[j];
   }
   long long tot;
@@ -171,15 +176,23 @@ __global__ void __launch_bounds__(CB_THREADS) deg_scan_write_kernel(const int32_
   if (blockIdx.x == 0 && threadIdx.x == 0) scan[k] = partial[nb];
 }
 
-byo_status scan_degrees(const int32_t *deg, const int32_t *ids, int64_t k, long long *scan, long long *partial,
-                        int64_t partial_cap, hipStream_t s) {
+int64_t scan_partials_needed(int64_t k) { return std::max<int64_t>(1, (k + DS_TILE - 1) / DS_TILE) + 1; }
+
+byo_status scan_degree_units(const int32_t *deg, const int32_t *ids, int64_t k, int32_t per, long long *scan,
+                             long long *partial, int64_t partial_cap, hipStream_t s) {
+  BYO_CHECK(per >= 1, BYO_EINVAL, "bad unit size");
   int64_t nb = std::max<int64_t>(1, (k + DS_TILE - 1) / DS_TILE);
   BYO_CHECK(nb + 1 <= partial_cap, BYO_EINVAL, "scan scratch too small");
-  deg_scan_reduce_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, partial);
+  deg_scan_reduce_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, per, partial);
   scan_partials_kernel<<<1, CB_THREADS, 0, s>>>(partial, nb, nullptr);
-  deg_scan_write_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, partial, nb, scan);
+  deg_scan_write_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, per, partial, nb, scan);
   BYO_HIP(hipGetLastError());
   return BYO_OK;
+}
+
+byo_status scan_degrees(const int32_t *deg, const int32_t *ids, int64_t k, long long *scan, long long *partial,
+                        int64_t partial_cap, hipStream_t s) {
+  return scan_degree_units(deg, ids, k, 1, scan, partial, partial_cap, s);
 }
 
 byo_status frontier_degree_scan(const byo_graph *g, const int32_t *ids, int64_t k, long long *scan,

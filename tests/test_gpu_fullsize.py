@@ -56,6 +56,20 @@ def test_bfs_cc_rmat22_full(rmat22):
         assert np.array_equal(lab.cpu().numpy(), want), tiled
 
 
+def test_kcore_rmat22_full(rmat22):
+    """Coreness at the benchmark's size (244 distinct values, 768 sub-rounds),
+    in one persistent launch and through the host-driven loop."""
+    p, g, og = rmat22
+    want = og.kcore()
+    subs = []
+    for persistent in (1, 0):
+        core, st = byo.kcore(g, persistent=persistent)
+        got = core.cpu().numpy()
+        assert np.array_equal(got, want), (persistent, int(np.sum(got != want)))
+        subs.append(st["levels"])
+    assert subs[0] == subs[1]
+
+
 # eight columns in each of the four 64-source words of the benchmark's
 # 256-source batch (first and last lane of every word included)
 MS_COLUMNS = [64 * w + j for w in range(4) for j in (0, 9, 18, 27, 36, 45, 54, 63)]
