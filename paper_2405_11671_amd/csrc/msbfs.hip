@@ -405,6 +405,115 @@ __device__ __forceinline__ void load_mask(const uint64_t *__restrict__ m, int64_
   }
 }
 
+// Where the level's results land: seen and the next frontier masks, the next
+// active and the "full" bitmaps, the depths (null while they come from the
+// level history), the counters.
+struct ms_fin_args {
+  uint64_t *seen, *front_next, *abits_next, *fbits;
+  const int32_t *rdeg, *orig;
+  uint8_t *depth;
+  int32_t k;
+  uint8_t newdepth;
+  int64_t n;
+};
+
+// per-workgroup level tallies: next frontier size and degree sum, (vertex,
+// source) pairs reached and edges over them
+struct ms_tallies {
+  unsigned long long degsum = 0, count = 0, pairs = 0, edges = 0;
+};
+
+// One level's end for 64 consecutive vertices, one per lane of the wavefront
+// (v of lane 0 a multiple of 64): a = the sources that reached v this level
+// (already ORed over the chunks), now_full = v had seen every source before
+// (lanes past n pass true). Keeps the bits not seen before, writes seen, the
+// next frontier, the depths, and the words of the next active and the full
+// bitmaps (when `owned`: the wavefront's word belongs to the caller).
+template <int W>
+__device__ __forceinline__ void ms_finish_word(const ms_fin_args &f, int64_t v, bool now_full, const uint64_t *a,
+                                               const uint64_t *full, bool vec_depth,
+                                               bool owned, ms_tallies &tl) {
+  bool any = false;
+  uint64_t nb[W], sv[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) nb[w] = sv[w] = 0ull;
+  int64_t row = 0;
+  if (v < f.n && !now_full) {
+    bool got = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) got |= a[w] != 0;
+    if (got) {  // else nothing reached v and its full bit stays clear
+      now_full = true;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        sv[w] = f.seen[v * W + w];
+        nb[w] = a[w] & ~sv[w];
+        any |= nb[w] != 0;
+        now_full &= (sv[w] | nb[w]) == full[w];
+      }
+    }
+    if (any) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        f.seen[v * W + w] = sv[w] | nb[w];
+        f.front_next[v * W + w] = nb[w];
+      }
+      row = f.orig[v];
+      tl.degsum += (unsigned long long)f.rdeg[v];
+      unsigned long long pc = 0;
+#pragma unroll
+      for (int w = 0; w < W; ++w) pc += (unsigned long long)__popcll(nb[w]);
+      tl.pairs += pc;
+      tl.edges += pc * (unsigned long long)f.rdeg[v];
+    } else {
+#pragma unroll
+      for (int w = 0; w < W; ++w) nb[w] = 0ull;
+    }
+  }
+  if (!f.depth) {
+    // depths of this level come from the level history later
+  } else if (vec_depth) {
+    write_depths_wave<W>(f.depth, f.k, row, nb, sv, f.newdepth);  // every lane of the wavefront
+  } else if (any) {
+    write_depths<W>(f.depth, row, f.k, nb, sv, f.newdepth);
+  }
+  const uint64_t am = __ballot(any);
+  const uint64_t fm = __ballot(now_full);  // vertices past n count as full
+  if (lane_id() == 0 && v < f.n && owned) {
+    f.abits_next[v >> 6] = am;
+    f.fbits[v >> 6] = fm;
+    tl.count += (unsigned long long)__popcll(am);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void ms_full_words(int32_t k, uint64_t *full) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int bits = k - 64 * w;
+    full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
+  }
+}
+
+// the workgroup's tallies into the level counters (one atomic each)
+template <int BLOCK>
+__device__ __forceinline__ void ms_add_tallies(const ms_tallies &tl, byo_counters *ctr,
+                                               unsigned long long *tally) {
+  const unsigned long long ts = block_sum<unsigned long long, BLOCK>(tl.degsum);
+  const unsigned long long tc = block_sum<unsigned long long, BLOCK>(tl.count);
+  const unsigned long long tp = block_sum<unsigned long long, BLOCK>(tl.pairs);
+  const unsigned long long te = block_sum<unsigned long long, BLOCK>(tl.edges);
+  if (threadIdx.x == 0) {
+    if (ts) atomicAdd(&ctr->degsum, ts);
+    if (tc) atomicAdd(&ctr->count, tc);
+    if (tp) atomicAdd(&tally[0], tp);
+    if (te) atomicAdd(&tally[1], te);
+  }
+}
+
+// A tile cut into one chunk is finished by that chunk's workgroup (its
+// accumulators are the tile's whole result); the chunk results of a tile cut
+// into several go to `partial` for the apply pass.
 template <int W>
 __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__restrict__ ent,
                                                              const int32_t *__restrict__ anchor,
@@ -412,16 +521,20 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
                                                              const int32_t *__restrict__ cblk,
                                                              const uint64_t *__restrict__ front,
                                                              const uint64_t *__restrict__ abits,
-                                                             const uint64_t *__restrict__ fbits, int64_t words,
+                                                             int64_t words, const int32_t *__restrict__ bfirst,
+                                                             ms_fin_args f, byo_counters *__restrict__ ctr,
+                                                             unsigned long long *__restrict__ tally,
                                                              uint64_t *__restrict__ partial,
                                                              uint32_t *__restrict__ cflag) {
   constexpr int B = 1 << MT_SHIFT;
   __shared__ uint64_t acc[B * W];
   __shared__ uint64_t need[B / 64 + 1];  // word B / 64 (padding entries) stays 0
   __shared__ int s_any, s_need;
+  const uint64_t *__restrict__ fbits = f.fbits;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
   const int64_t tile = cblk[c];
+  const bool single = bfirst[tile + 1] - bfirst[tile] == 1;
   if (t == 0) {
     s_any = 0;
     s_need = 0;
@@ -437,7 +550,12 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
   // a tile whose vertices have all seen every source has nothing to gain:
   // the workgroup leaves without streaming its entries
   if (!s_need) {
-    if (t == 0) cflag[c] = 0u;
+    if (!single) {
+      if (t == 0) cflag[c] = 0u;
+    } else if (t < B / 64) {
+      const int64_t wd = (tile << (MT_SHIFT - 6)) + t;
+      if (wd < words) f.abits_next[wd] = 0ull;
+    }
     return;
   }
   for (int i = t; i < B * W; i += MT_THREADS) acc[i] = 0ull;
@@ -499,55 +617,83 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
   if (mine) s_any = 1;  // every writer stores the same value
   __syncthreads();
   const int any = s_any;
-  if (any) {
-    uint64_t *out = partial + ((c * B) * W);
-    for (int i = t; i < B * W; i += MT_THREADS) out[i] = acc[i];
+  if (!single) {
+    if (any) {
+      uint64_t *out = partial + ((c * B) * W);
+      for (int i = t; i < B * W; i += MT_THREADS) out[i] = acc[i];
+    }
+    if (t == 0) cflag[c] = any ? 1u : 0u;
+    return;
   }
-  if (t == 0) cflag[c] = any ? 1u : 0u;
+  if (!any) {  // nothing reached the tile: no next-frontier vertex, the full bits stand
+    if (t < B / 64) {
+      const int64_t wd = (tile << (MT_SHIFT - 6)) + t;
+      if (wd < words) f.abits_next[wd] = 0ull;
+    }
+    return;
+  }
+  uint64_t full[W];
+  ms_full_words<W>(f.k, full);
+  const bool vec_depth = (f.k & 15) == 0 && ((uintptr_t)f.depth & 15) == 0;
+  ms_tallies tl;
+  for (int l = t; l < B; l += MT_THREADS) {
+    const int64_t v = (tile << MT_SHIFT) + l;
+    const bool now_full = v >= f.n || !((need[l >> 6] >> (l & 63)) & 1ull);
+    uint64_t a[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) a[w] = acc[l * W + w];
+    ms_finish_word<W>(f, v, now_full, a, full, vec_depth, true, tl);
+  }
+  ms_add_tallies<MT_THREADS>(tl, ctr, tally);
 }
 
+// The apply pass: the vertices of the tiles cut into several chunks, in
+// pieces of the tile layout's apply plan (a word: first vertex, bit 0 set for
+// a 64-vertex piece of a many-chunk tile, else 1024 vertices), ORing each
+// vertex's chunk results; then, in the workgroups past the plan, the
+// next-active words of the trailing tiles without entries (cleared: nothing
+// reaches a vertex without neighbours).
 template <int W>
 __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
     const uint64_t *__restrict__ partial, const uint32_t *__restrict__ cflag, const int32_t *__restrict__ bfirst,
-    uint64_t *__restrict__ seen, uint64_t *__restrict__ front_next, uint64_t *__restrict__ abits_next,
-    uint64_t *__restrict__ fbits, const int32_t *__restrict__ rdeg, const int32_t *__restrict__ orig,
-    uint8_t *__restrict__ depth, int32_t k, uint8_t newdepth, int64_t n, byo_counters *__restrict__ ctr,
+    const int32_t *__restrict__ plan, int64_t nplan, int64_t wtail, ms_fin_args f, byo_counters *__restrict__ ctr,
     unsigned long long *__restrict__ tally) {
   constexpr int B = 1 << MT_SHIFT;
-  uint64_t full[W];
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    int bits = k - 64 * w;
-    full[w] = bits >= 64 ? ~0ull : (bits <= 0 ? 0ull : (~0ull >> (64 - bits)));
+  if ((int64_t)blockIdx.x >= nplan) {
+    const int64_t words = (f.n + 63) / 64;
+    for (int64_t wd = (wtail >> 6) + ((int64_t)blockIdx.x - nplan) * MS_BLOCK + threadIdx.x; wd < words;
+         wd += ((int64_t)gridDim.x - nplan) * MS_BLOCK)
+      f.abits_next[wd] = 0ull;
+    return;
   }
-  unsigned long long degsum = 0, count = 0, pairs = 0, edges = 0;
-  const bool vec_depth = (k & 15) == 0 && ((uintptr_t)depth & 15) == 0;
-  // capped grid: a few thousand counter atomics per level, not one per 256 vertices
-  for (int64_t base = (int64_t)blockIdx.x * MS_BLOCK; base < n; base += (int64_t)gridDim.x * MS_BLOCK) {
+  uint64_t full[W];
+  ms_full_words<W>(f.k, full);
+  const bool vec_depth = (f.k & 15) == 0 && ((uintptr_t)f.depth & 15) == 0;
+  const int32_t piece = plan[blockIdx.x];
+  const int64_t v0 = piece & ~1;
+  const int64_t v1 = v0 + ((piece & 1) ? 64 : 1024);
+  ms_tallies tl;
+  for (int64_t base = v0; base < v1; base += MS_BLOCK) {
     const int64_t v = base + threadIdx.x;
-    const bool valid = v < n;
-    bool any = false, now_full = true;
-    uint64_t nb[W], sv[W];
+    const bool valid = v < v1 && v < f.n;
+    bool now_full = true;
+    uint64_t a[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) nb[w] = sv[w] = 0ull;
-    int64_t row = 0;
+    for (int w = 0; w < W; ++w) a[w] = 0ull;
     if (valid) {
-      now_full = (fbits[v >> 6] >> (v & 63)) & 1ull;
+      now_full = (f.fbits[v >> 6] >> (v & 63)) & 1ull;
       if (!now_full) {
         const int64_t b = v >> MT_SHIFT, l = v & (B - 1);
-        uint64_t a[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) a[w] = 0ull;
         // hub tiles have many chunks: eight chunk results in flight; results of
         // chunks that produced nothing this level are stale and masked out
         const int32_t c1 = bfirst[b + 1];
         const uint64_t *pl = partial + (int64_t)l * W;
         int32_t c = bfirst[b];
         for (; c + 8 <= c1; c += 8) {
-          uint32_t f[8];
+          uint32_t fl[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) f[j] = cflag[c + j];
-          if (!(f[0] | f[1] | f[2] | f[3] | f[4] | f[5] | f[6] | f[7])) continue;
+          for (int j = 0; j < 8; ++j) fl[j] = cflag[c + j];
+          if (!(fl[0] | fl[1] | fl[2] | fl[3] | fl[4] | fl[5] | fl[6] | fl[7])) continue;
           uint64_t x[8][W];
 #pragma unroll
           for (int j = 0; j < 8; ++j)
@@ -556,70 +702,19 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_apply_kernel(
 #pragma unroll
           for (int j = 0; j < 8; ++j)
 #pragma unroll
-            for (int w = 0; w < W; ++w) a[w] |= f[j] ? x[j][w] : 0ull;
+            for (int w = 0; w < W; ++w) a[w] |= fl[j] ? x[j][w] : 0ull;
         }
         for (; c < c1; ++c) {
           if (!cflag[c]) continue;
 #pragma unroll
           for (int w = 0; w < W; ++w) a[w] |= pl[((int64_t)c * B) * W + w];
         }
-        bool got = false;
-#pragma unroll
-        for (int w = 0; w < W; ++w) got |= a[w] != 0;
-        if (got) {  // else nothing reached v and its full bit stays clear
-          now_full = true;
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            sv[w] = seen[v * W + w];
-            nb[w] = a[w] & ~sv[w];
-            any |= nb[w] != 0;
-            now_full &= (sv[w] | nb[w]) == full[w];
-          }
-        }
-        if (any) {
-#pragma unroll
-          for (int w = 0; w < W; ++w) {
-            seen[v * W + w] = sv[w] | nb[w];
-            front_next[v * W + w] = nb[w];
-          }
-          row = orig[v];
-          degsum += (unsigned long long)rdeg[v];
-          unsigned long long pc = 0;
-#pragma unroll
-          for (int w = 0; w < W; ++w) pc += (unsigned long long)__popcll(nb[w]);
-          pairs += pc;
-          edges += pc * (unsigned long long)rdeg[v];
-        } else {
-#pragma unroll
-          for (int w = 0; w < W; ++w) nb[w] = 0ull;
-        }
       }
     }
-    if (!depth) {
-      // depths of this level come from the level history later
-    } else if (vec_depth) {
-      write_depths_wave<W>(depth, k, row, nb, sv, newdepth);  // every lane of the wavefront
-    } else if (any) {
-      write_depths<W>(depth, row, k, nb, sv, newdepth);
-    }
-    uint64_t am = __ballot(any);
-    uint64_t fm = __ballot(now_full);  // vertices past n count as full
-    if (lane_id() == 0 && v < n) {
-      abits_next[v >> 6] = am;
-      fbits[v >> 6] = fm;
-      count += (unsigned long long)__popcll(am);
-    }
+    // every lane calls it; a wavefront past a 64-vertex piece owns no word
+    ms_finish_word<W>(f, v, now_full, a, full, vec_depth, v - (int64_t)lane_id() < v1, tl);
   }
-  unsigned long long ts = block_sum<unsigned long long, MS_BLOCK>(degsum);
-  unsigned long long tc = block_sum<unsigned long long, MS_BLOCK>(count);
-  unsigned long long tp = block_sum<unsigned long long, MS_BLOCK>(pairs);
-  unsigned long long te = block_sum<unsigned long long, MS_BLOCK>(edges);
-  if (threadIdx.x == 0) {
-    if (ts) atomicAdd(&ctr->degsum, ts);
-    if (tc) atomicAdd(&ctr->count, tc);
-    if (tp) atomicAdd(&tally[0], tp);
-    if (te) atomicAdd(&tally[1], te);
-  }
+  ms_add_tallies<MS_BLOCK>(tl, ctr, tally);
 }
 
 // Sources, in one workgroup (k <= 256 threads): the source vertices' frontier
@@ -882,16 +977,22 @@ template <int W>
 static void launch_tile_level(const byo_tiles *t, ms_ws &mw, const ms_level_bufs &lb, int32_t k, uint8_t nd,
                               int64_t n, byo_counters *ctr, hipStream_t s) {
   int64_t words = (n + 63) / 64;
+  const ms_fin_args f{mw.seen, lb.front_next, lb.abits_next, mw.fbits, t->rdeg, t->orig, lb.depth, k, nd, n};
   {
     ktimer_scope kt(BYO_K_MSBFS_PULL, s);
     ms_tile_kernel<W><<<(unsigned)t->nchunks, MT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, t->cblk, lb.front_cur,
-                                                                 lb.abits_cur, mw.fbits, words,
+                                                                 lb.abits_cur, words, t->bfirst, f, ctr, mw.tally,
                                                                  (uint64_t *)t->partial, t->cflag);
   }
+  // the plan's pieces, then enough workgroups for the words of the trailing
+  // tiles without entries (wtail is then a tile boundary; wtail == n: none)
+  const int64_t tail_words = t->wtail < n ? words - (t->wtail >> 6) : 0;
+  const int64_t tail_blocks = std::min<int64_t>((tail_words + MS_BLOCK - 1) / MS_BLOCK, 256);
+  const int64_t grid = t->napply + tail_blocks;
+  if (grid == 0) return;
   ktimer_scope kt(BYO_K_MSBFS_FINISH, s);
-  ms_tile_apply_kernel<W><<<(unsigned)std::min<int64_t>((n + MS_BLOCK - 1) / MS_BLOCK, 2048), MS_BLOCK, 0, s>>>(
-      (const uint64_t *)t->partial, t->cflag, t->bfirst, mw.seen, lb.front_next, lb.abits_next, mw.fbits, t->rdeg,
-      t->orig, lb.depth, k, nd, n, ctr, mw.tally);
+  ms_tile_apply_kernel<W><<<(unsigned)grid, MS_BLOCK, 0, s>>>((const uint64_t *)t->partial, t->cflag, t->bfirst,
+                                                              t->aplan, t->napply, t->wtail, f, ctr, mw.tally);
 }
 
 // History slots for the tiled levels: as many as fit in a quarter of the free
