@@ -766,15 +766,21 @@ __global__ void __launch_bounds__(256) ms_depth_flush_kernel(ms_hist_args h, int
                                                              const int32_t *__restrict__ orig, int64_t n, int32_t k,
                                                              uint8_t *__restrict__ depth) {
   const bool vec = (k & 15) == 0 && ((uintptr_t)depth & 15) == 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * W; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t w = i / W;
+  // full 256-byte rows: a wavefront's 16 rows go through LDS so that each
+  // store instruction writes four whole rows
+  __shared__ uint4 tr[256 / BYO_WAVE][16 * 16];
+  const bool rows = W == 4 && k == 256 && vec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane_id() < n * W;
+       i += (int64_t)gridDim.x * blockDim.x) {  // uniform per wavefront
+    const bool live = i < n * W;
+    const int64_t w = live ? i / W : 0;
     const int word = (int)(i - w * W);
     const uint64_t bit = 1ull << (w & 63);
     uint64_t act[MS_HIST], fm[MS_HIST];
 #pragma unroll
     for (int l = 0; l < MS_HIST; ++l) act[l] = l < L ? h.a[l][w >> 6] : 0ull;
 #pragma unroll
-    for (int l = 0; l < MS_HIST; ++l) fm[l] = (act[l] & bit) ? h.f[l][i] : 0ull;
+    for (int l = 0; l < MS_HIST; ++l) fm[l] = (live && (act[l] & bit)) ? h.f[l][i] : 0ull;
     uint32_t c[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) c[q] = 0xFFFFFFFFu;
@@ -790,6 +796,29 @@ __global__ void __launch_bounds__(256) ms_depth_flush_kernel(ms_hist_args h, int
         c[q] = (c[q] & ~bm) | (ls & bm);
       }
     }
+    if (rows) {
+      uint4 *t = tr[threadIdx.x / BYO_WAVE];
+      const int lane = lane_id();
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4)
+        t[lane * 4 + s4] = make_uint4(c[4 * s4], c[4 * s4 + 1], c[4 * s4 + 2], c[4 * s4 + 3]);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int64_t w0 = (i - lane) / W;  // the wavefront's first vertex
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int vr = 4 * st + (lane >> 4);  // vertex of the wavefront this lane stores
+        const int64_t wv = w0 + vr;
+        if (wv < n) {
+          // row vr's 16-byte group (lane & 15) is piece s4 = (lane & 3) of lane 4 vr + (lane & 15) / 4
+          const uint4 x = t[(4 * vr + ((lane & 15) >> 2)) * 4 + (lane & 3)];
+          *(uint4 *)(depth + (int64_t)orig[wv] * 256 + 16 * (lane & 15)) = x;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      continue;
+    }
+    if (!live) continue;
     uint8_t *row = depth + (int64_t)orig[w] * k + 64 * word;
     if (vec && 64 * word + 64 <= k) {
 #pragma unroll
