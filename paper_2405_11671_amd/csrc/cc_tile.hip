@@ -10,8 +10,9 @@
 // The round runs in the layout's vertex order, but label values are original
 // IDs, so the minimum taken is the minimum original ID. A workgroup takes a
 // chunk of a destination tile, keeps the tile's minima in LDS (atomic min is
-// order-free) and skips entries whose source is not active; the apply pass
-// takes the minimum over the tile's chunks.
+// order-free) and skips entries whose source is not active. A tile cut into
+// one chunk is finished by that chunk's workgroup; for the others the apply
+// pass takes the minimum over the tile's chunks.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -24,12 +25,51 @@ constexpr int CT_THREADS = 1024;
 constexpr int CT_ILP = 16;
 constexpr int CT_APPLY = 256;
 
+// Lower lab[w] to m, the smallest label offered to w this round, and hook
+// the vertex w's old label named; true if lab[w] changed. Every lane of the
+// wavefront calls it (w >= n: nothing); the caller ORs the changed lanes into
+// the next active bitmap.
+__device__ __forceinline__ bool cc_lower(int64_t w, int64_t n, int32_t m, const int32_t *__restrict__ rlabel,
+                                         int32_t *__restrict__ lab, uint64_t *__restrict__ abits_next) {
+  if (w >= n) return false;
+  const int32_t old = lab[w];
+  if (m >= old) return false;
+  atomicMin(&lab[w], m);
+  // Hooking: the vertex whose ID w carried as its label is in w's component
+  // too, so it may take m as well; it becomes active when it drops. Labels
+  // only decrease and stay IDs of the component, so the result (the smallest
+  // ID of each component) is unchanged; fewer rounds reach it.
+  const int32_t h = rlabel[old];
+  // (read first: most labels name a few roots, and once a root holds m its
+  // hooks would only queue on the same address)
+  if (h != w && m < lab[h] && m < atomicMin(&lab[h], m))
+    atomicOr((unsigned long long *)&abits_next[h >> 6], 1ull << (h & 63));
+  return true;
+}
+
+// the changed lanes of a wavefront (first vertex w0, a multiple of 64) into
+// the next active bitmap; returns how many
+__device__ __forceinline__ unsigned long long cc_mark(bool changed, int64_t w0, int64_t n,
+                                                      uint64_t *__restrict__ abits_next) {
+  const uint64_t am = __ballot(changed);
+  if (lane_id() == 0 && w0 < n && am) {
+    atomicOr((unsigned long long *)&abits_next[w0 >> 6], (unsigned long long)am);
+    return (unsigned long long)__popcll(am);
+  }
+  return 0ull;
+}
+
 template <int SHIFT>
 __global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const uint32_t *__restrict__ ent,
                                                              const int32_t *__restrict__ anchor,
                                                              const int64_t *__restrict__ cbeg,
-                                                             const int32_t *__restrict__ lab,
+                                                             const int32_t *__restrict__ cblk,
+                                                             const int32_t *__restrict__ bfirst,
+                                                             const int32_t *__restrict__ rlabel,
+                                                             int32_t *__restrict__ lab,
                                                              const uint64_t *__restrict__ abits,
+                                                             uint64_t *__restrict__ abits_next, int64_t n,
+                                                             byo_counters *__restrict__ ctr,
                                                              int32_t *__restrict__ partial,
                                                              uint32_t *__restrict__ cflag) {
   constexpr int B = 1 << SHIFT;
@@ -37,6 +77,8 @@ __global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const uint32_t *__r
   __shared__ int s_any;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;
+  const int64_t tile = cblk[c];
+  const bool single = bfirst[tile + 1] - bfirst[tile] == 1;
   for (int i = t; i <= B; i += CT_THREADS) acc[i] = INT_MAX;
   if (t == 0) s_any = 0;
   __syncthreads();
@@ -94,35 +136,50 @@ __global__ void __launch_bounds__(CT_THREADS) cc_tile_kernel(const uint32_t *__r
   if (mine) s_any = 1;  // every writer stores the same value
   __syncthreads();
   const int any = s_any;
-  if (any) {
-    int32_t *out = partial + (c << SHIFT);
-    for (int i = t; i < B; i += CT_THREADS) out[i] = acc[i];
+  if (!single) {
+    if (any) {
+      int32_t *out = partial + (c << SHIFT);
+      for (int i = t; i < B; i += CT_THREADS) out[i] = acc[i];
+    }
+    if (t == 0) cflag[c] = any ? 1u : 0u;
+    return;
   }
-  if (t == 0) cflag[c] = any ? 1u : 0u;
+  if (!any) return;  // nothing offered to the tile
+  unsigned long long count = 0;
+  for (int l = t; l < B; l += CT_THREADS) {
+    const int64_t w = (tile << SHIFT) + l;
+    const bool changed = cc_lower(w, n, acc[l], rlabel, lab, abits_next);
+    count += cc_mark(changed, w - lane_id(), n, abits_next);
+  }
+  const unsigned long long tc = block_sum<unsigned long long, CT_THREADS>(count);
+  if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
 }
 
-// Smallest label offered to w over its tile's chunks; lower lab[w] to it and
-// mark w active (a wavefront ORs in its word of the next active bitmap, which
-// the caller cleared), and hook the vertex w's old label named.
+// The tiles cut into several chunks, in pieces of the layout's apply plan (a
+// word: first vertex, bit 0 set for a 64-vertex piece of a many-chunk tile,
+// else 1024 vertices): the smallest label offered to w over its tile's
+// chunks lowers lab[w] (cc_lower).
 template <int SHIFT>
 __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *__restrict__ partial,
                                                                  const uint32_t *__restrict__ cflag,
                                                                  const int32_t *__restrict__ bfirst,
+                                                                 const int32_t *__restrict__ plan,
                                                                  const int32_t *__restrict__ rlabel,
                                                                  int32_t *__restrict__ lab,
                                                                  uint64_t *__restrict__ abits_next, int64_t n,
                                                                  byo_counters *__restrict__ ctr) {
   constexpr int B = 1 << SHIFT;
+  const int32_t piece = plan[blockIdx.x];
+  const int64_t v0 = piece & ~1;
+  const int64_t v1 = std::min<int64_t>(v0 + ((piece & 1) ? 64 : 1024), n);
   unsigned long long count = 0;
-  // capped grid: a few thousand counter atomics per round
-  for (int64_t base = (int64_t)blockIdx.x * CT_APPLY; base < n; base += (int64_t)gridDim.x * CT_APPLY) {
+  for (int64_t base = v0; base < v1; base += CT_APPLY) {  // uniform per workgroup
     const int64_t w = base + threadIdx.x;
-    bool changed = false;
-    if (w < n) {
+    int32_t m = INT_MAX;
+    if (w < v1) {
       const int64_t b = w >> SHIFT, l = w & (B - 1);
       const int32_t *pl = partial + l;
       const int32_t c1 = bfirst[b + 1];
-      int32_t m = INT_MAX;
       int32_t c = bfirst[b];
       for (; c + 8 <= c1; c += 8) {
         uint32_t f[8];
@@ -137,27 +194,10 @@ __global__ void __launch_bounds__(CT_APPLY) cc_tile_apply_kernel(const int32_t *
       }
       for (; c < c1; ++c)
         if (cflag[c]) m = min(m, pl[(int64_t)c << SHIFT]);
-      const int32_t old = lab[w];
-      if (m < old) {
-        atomicMin(&lab[w], m);
-        changed = true;
-        // Hooking: the vertex whose ID w carried as its label is in w's
-        // component too, so it may take m as well; it becomes active when it
-        // drops. Labels only decrease and stay IDs of the component, so the
-        // result (the smallest ID of each component) is unchanged; fewer
-        // rounds reach it.
-        const int32_t h = rlabel[old];
-        // (read first: most labels name a few roots, and once a root holds m
-        // its hooks would only queue on the same address)
-        if (h != w && m < lab[h] && m < atomicMin(&lab[h], m))
-          atomicOr((unsigned long long *)&abits_next[h >> 6], 1ull << (h & 63));
-      }
     }
-    uint64_t am = __ballot(changed);
-    if (lane_id() == 0 && w < n && am) {
-      atomicOr((unsigned long long *)&abits_next[w >> 6], (unsigned long long)am);
-      count += (unsigned long long)__popcll(am);
-    }
+    const bool changed = cc_lower(w < v1 ? w : n, n, m, rlabel, lab, abits_next);
+    // a wavefront past a 64-vertex piece marks nothing (no lane changed)
+    count += cc_mark(changed, w - lane_id(), n, abits_next);
   }
   unsigned long long tc = block_sum<unsigned long long, CT_APPLY>(count);
   if (threadIdx.x == 0 && tc) atomicAdd(&ctr->count, tc);
@@ -219,12 +259,14 @@ template <int SHIFT>
 static void cc_tile_pass(const byo_tiles *t, int32_t *lab, const uint64_t *abits, uint64_t *abits_next,
                          byo_counters *ctr, int64_t n, hipStream_t s) {
   ktimer_scope kt(BYO_K_CC_PULL, s);
-  cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, lab, abits,
-                                                                   (int32_t *)t->partial, t->cflag);
-  // the apply ORs its bits in (a hooked vertex may sit in another wavefront's word)
+  // the passes OR their bits in (a hooked vertex may sit in another wavefront's word)
   (void)fill_u64(abits_next, (n + 63) / 64, 0ull, s);
-  cc_tile_apply_kernel<SHIFT><<<apply_grid(n), CT_APPLY, 0, s>>>((const int32_t *)t->partial, t->cflag, t->bfirst,
-                                                                 t->rlabel, lab, abits_next, n, ctr);
+  cc_tile_kernel<SHIFT><<<(unsigned)t->nchunks, CT_THREADS, 0, s>>>(t->ent, t->anchor, t->cbeg, t->cblk, t->bfirst,
+                                                                   t->rlabel, lab, abits, abits_next, n, ctr,
+                                                                   (int32_t *)t->partial, t->cflag);
+  if (t->napply > 0)
+    cc_tile_apply_kernel<SHIFT><<<(unsigned)t->napply, CT_APPLY, 0, s>>>(
+        (const int32_t *)t->partial, t->cflag, t->bfirst, t->aplan, t->rlabel, lab, abits_next, n, ctr);
 }
 
 // Rounds in the layout's order, direction-optimising: a push over the
