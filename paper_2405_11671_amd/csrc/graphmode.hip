@@ -24,11 +24,19 @@ namespace byo {
 
 enum { GM_NONE = 0, GM_PUSH = 1, GM_PUSH_COMPACT = 2, GM_PULL = 3 };
 
+// each field on its own 128-byte line (every workgroup adds into count and
+// degsum; device-scope atomics on one line serialise)
 struct gm_counters {
-  unsigned long long count, degsum;
+  unsigned long long count;
+  unsigned long long pad0_[BYO_LINE_U64 - 1];
+  unsigned long long degsum;
+  unsigned long long pad1_[BYO_LINE_U64 - 1];
   unsigned long long list_valid;  // the frontier exists as an ID list
+  unsigned long long pad2_[BYO_LINE_U64 - 1];
   unsigned long long cursor;      // append cursor used when compacting this frontier
+  unsigned long long pad3_[BYO_LINE_U64 - 1];
 };
+static_assert(2 * sizeof(gm_counters) <= 1024, "two counter sets fit between misc + 1024 and the state at + 2048");
 
 struct gm_state {
   int32_t sel, prev_sel;

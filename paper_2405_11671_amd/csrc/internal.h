@@ -125,12 +125,22 @@ __device__ __forceinline__ bool test_bit(const uint64_t *bits, int64_t v) {
 // ---------------------------------------------------------------- objects
 
 // Per-level counters written by edgeMap kernels (ring of slots, see edgemap).
+// Every workgroup of a level adds into them, and device-scope atomics on one
+// 128-byte line serialise with each other, so each counter has a line of its
+// own (together on one line they cost single-source BFS a quarter of its
+// rate at RMAT-22).
+constexpr int BYO_LINE_U64 = 16;  // 64-bit words per 128-byte line
 struct byo_counters {
   unsigned long long count;   // vertices emitted
+  unsigned long long pad0_[BYO_LINE_U64 - 1];
   unsigned long long degsum;  // sum of their degrees
+  unsigned long long pad1_[BYO_LINE_U64 - 1];
   unsigned long long aux0;    // variant-specific (e.g. edges inspected)
+  unsigned long long pad2_[BYO_LINE_U64 - 1];
   unsigned long long aux1;
+  unsigned long long pad3_[BYO_LINE_U64 - 1];
   unsigned long long maxdeg;  // largest degree among them (edgeMap levels)
+  unsigned long long pad4_[BYO_LINE_U64 - 1];
 };
 #define BYO_COUNTER_SLOTS 4
 

@@ -18,6 +18,10 @@ namespace byo {
 
 constexpr int MS_BLOCK = 256;
 constexpr int MS_ILP = 4;
+// the run's tallies, (vertex, source) pairs reached at word 0 and edges over
+// them at MS_TALLY_EDGES, on separate lines (every workgroup adds into both)
+constexpr int MS_TALLY_EDGES = BYO_LINE_U64;
+constexpr int MS_TALLY_WORDS = 2 * BYO_LINE_U64;
 
 // Depth bytes of the sources newly seen by v (bits of nb; sv = the sources
 // seen before). When rows are 16-byte aligned (k a multiple of 16) each group
@@ -351,7 +355,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tally_kernel(const uint64_t *__re
   unsigned long long te = block_sum<unsigned long long, MS_BLOCK>(e);
   if (threadIdx.x == 0) {
     atomicAdd(&out[0], tr);
-    atomicAdd(&out[1], te);
+    atomicAdd(&out[MS_TALLY_EDGES], te);
   }
 }
 
@@ -507,7 +511,7 @@ __device__ __forceinline__ void ms_add_tallies(const ms_tallies &tl, byo_counter
     if (ts) atomicAdd(&ctr->degsum, ts);
     if (tc) atomicAdd(&ctr->count, tc);
     if (tp) atomicAdd(&tally[0], tp);
-    if (te) atomicAdd(&tally[1], te);
+    if (te) atomicAdd(&tally[MS_TALLY_EDGES], te);
   }
 }
 
@@ -734,7 +738,7 @@ __global__ void __launch_bounds__(256) ms_tile_init_kernel(const int32_t *__rest
   const unsigned long long e = block_sum<unsigned long long, 256>(j < k ? (unsigned long long)rdeg[r] : 0ull);
   if (j == 0) {
     atomicAdd(&tally[0], (unsigned long long)k);
-    atomicAdd(&tally[1], e);
+    atomicAdd(&tally[MS_TALLY_EDGES], e);
   }
   if (j < k)
     for (int w = 0; w < W; ++w) front[r * W + w] = 0ull;
@@ -958,7 +962,7 @@ __global__ void __launch_bounds__(MS_BLOCK) ms_tile_finish_kernel(
     if (ts) atomicAdd(&ctr->degsum, ts);
     if (tc) atomicAdd(&ctr->count, tc);
     if (tp) atomicAdd(&tally[0], tp);
-    if (te) atomicAdd(&tally[1], te);
+    if (te) atomicAdd(&tally[MS_TALLY_EDGES], te);
   }
 }
 
@@ -1149,11 +1153,11 @@ static byo_status ms_tiled_run(byo_graph *g, ms_ws &mw, int32_t k, int W,
   }
   // levels 0 .. level are in slots 0 .. level (the last one empty)
   if (!flushed) launch_depth_flush(mw, level + 1, t, n, k, W, d_depth, s);
-  unsigned long long tl[2] = {0, 0};
+  unsigned long long tl[MS_TALLY_WORDS] = {};
   BYO_TRY(sync_read(s, mw.tally, tl, sizeof(tl)));
   st.levels = level;
   st.reached = (int64_t)tl[0];
-  st.edges = (int64_t)tl[1];
+  st.edges = (int64_t)tl[MS_TALLY_EDGES];
   if (stats) *stats = st;
   mw.tiled_clean = true;
   return BYO_OK;
@@ -1194,7 +1198,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     BYO_HIP(hipMalloc(&mw.active[1], sizeof(int32_t) * (size_t)n));
     BYO_HIP(hipMalloc(&mw.srcs, sizeof(int32_t) * 256));
     BYO_HIP(hipMalloc(&mw.ctr, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1)));
-    BYO_HIP(hipMalloc(&mw.tally, sizeof(unsigned long long) * 2));
+    BYO_HIP(hipMalloc(&mw.tally, sizeof(unsigned long long) * MS_TALLY_WORDS));
     mw.n = n;
     mw.W = W;
   }
@@ -1211,7 +1215,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
     }
     BYO_HIP(hipMemsetAsync(mw.fbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
     BYO_HIP(hipMemsetAsync(mw.ctr, 0, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1), s));
-    BYO_HIP(hipMemsetAsync(mw.tally, 0, sizeof(unsigned long long) * 2, s));
+    BYO_HIP(hipMemsetAsync(mw.tally, 0, sizeof(unsigned long long) * MS_TALLY_WORDS, s));
     mw.tiled_clean = false;
     byo_status r = ms_tiled_run(g, mw, k, W, d_depth, o, s, stats);
     // the copy of hs must stay alive until the stream has read it
@@ -1226,7 +1230,7 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   BYO_HIP(hipMemsetAsync(mw.tbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
   BYO_HIP(hipMemsetAsync(mw.fbits, 0, sizeof(uint64_t) * (size_t)std::max<int64_t>(words, 1), s));
   BYO_HIP(hipMemsetAsync(mw.ctr, 0, sizeof(byo_counters) * 2 * (MS_MAX_LEVELS + 1), s));
-  BYO_HIP(hipMemsetAsync(mw.tally, 0, sizeof(unsigned long long) * 2, s));
+  BYO_HIP(hipMemsetAsync(mw.tally, 0, sizeof(unsigned long long) * MS_TALLY_WORDS, s));
   {
     int64_t total = n * (int64_t)k;
     unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(1, (total / 16 + 255) / 256), 65536);
@@ -1327,11 +1331,11 @@ extern "C" byo_status byo_msbfs(byo_graph *g, const int64_t *h_srcs, int32_t k, 
   }
   ms_tally_kernel<<<(unsigned)std::min<int64_t>(std::max<int64_t>(1, (n + 255) / 256), 4096), MS_BLOCK, 0, s>>>(
       mw.seen, W, g->deg, n, mw.tally);
-  unsigned long long tl[2] = {0, 0};
+  unsigned long long tl[MS_TALLY_WORDS] = {};
   BYO_TRY(sync_read(s, mw.tally, tl, sizeof(tl)));
   st.levels = level;
   st.reached = (int64_t)tl[0];
-  st.edges = (int64_t)tl[1];
+  st.edges = (int64_t)tl[MS_TALLY_EDGES];
   if (stats) *stats = st;
   return BYO_OK;
 }
