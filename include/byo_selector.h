@@ -45,9 +45,12 @@ byo_status byo_selector_features(const byo_level_record *rec, float *out);
 /* The threshold rule the selector falls back to (pure host function).
  * Dense (pull) when |U| + sum deg(U) > m / dense_divisor (the sparse/dense
  * cutoff that Section 6.3 takes from Ligra and GBBS); otherwise a push whose
- * load-balancing scheme is set by the frontier's degrees: max_deg_u, the
- * largest degree in U, or -1 when it is not known (then max_deg, the graph's
- * largest degree, stands in for it). The pull scheme uses max_deg and cv. */
+ * load-balancing scheme is set by the frontier's lists: with max_deg_u, the
+ * largest degree in U, known (>= 0), edge-balanced when a list is longer than
+ * 512 or sum deg(U) >= 65536, one lane per list when every list is at most 8
+ * long, else a wavefront per list; with max_deg_u = -1, edge-balanced when the
+ * graph's largest degree max_deg >= t_block or sum deg(U) >= 65536, else by
+ * the average list length against t_wave. The pull scheme uses max_deg and cv. */
 int32_t byo_heuristic_choice(int64_t k, int64_t degsum, int64_t m, int64_t max_deg, double cv, const byo_opts *opts,
                              int32_t allow_pull, int64_t max_deg_u);
 

@@ -444,7 +444,7 @@ struct ktimer_scope {
 // degree, thread-per-vertex otherwise.
 // max_deg is the graph's largest degree (pulls scan the lists of unvisited
 // vertices); frontier_max_deg, when known (>= 0), the largest degree in U,
-// which sets how unequal a push's lists are.
+// which sets how long a push's longest list is.
 __host__ __device__ inline int heuristic_rule(int64_t k, int64_t degsum, int64_t m, int64_t max_deg, double cv,
                                               int div, int t_wave, int t_block, bool allow_pull,
                                               int64_t frontier_max_deg = -1) {
@@ -454,8 +454,16 @@ __host__ __device__ inline int heuristic_rule(int64_t k, int64_t degsum, int64_t
   if (allow_pull && k + degsum > m / div)
     return (cv > 1.0 || max_deg > 4 * (int64_t)t_wave) ? BYO_V_PULL_WAVE : BYO_V_PULL_THREAD;
   double avg = k > 0 ? (double)degsum / (double)k : 0.0;
-  const int64_t push_max = frontier_max_deg >= 0 ? frontier_max_deg : max_deg;
-  if (push_max >= t_block || degsum >= 65536) return BYO_V_PUSH_EDGE;
+  if (frontier_max_deg >= 0) {
+    // The lists' own lengths: a wavefront takes 64 entries per round and a
+    // thread one, each round waiting on its claims, so a list longer than 8
+    // wavefront rounds goes to the edge-balanced push, and one lane per list
+    // only when every list is at most 8 long.
+    if (frontier_max_deg > 8 * BYO_WAVE || degsum >= 65536) return BYO_V_PUSH_EDGE;
+    return frontier_max_deg <= 8 ? BYO_V_PUSH_THREAD : BYO_V_PUSH_WAVE;
+  }
+  // only the graph's largest degree known: it bounds the lists from above
+  if (max_deg >= t_block || degsum >= 65536) return BYO_V_PUSH_EDGE;
   if (avg >= t_wave) return BYO_V_PUSH_WAVE;
   return BYO_V_PUSH_THREAD;
 }

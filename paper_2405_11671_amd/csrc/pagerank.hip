@@ -366,8 +366,11 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
   int32_t *mdeg = nullptr;
   if (omit & BYO_API_NO_DEGREE) BYO_TRY(api_map_degrees(g, omit, s, &mdeg));
   if (!par_map) tw = INT32_MAX;
-  pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(mdeg ? mdeg : g->deg, n, w.words, w.contrib[0], w.dpart);
-  BYO_HIP(hipGetLastError());
+  const bool tiled = o.pr_blocked != 0 && omit == 0 && !o.compressed && tiles_wanted(g);
+  if (!tiled) {  // the tiled path starts from the layout's own degrees below
+    pr_init_kernel<<<(unsigned)nb, PR_BLOCK, 0, s>>>(mdeg ? mdeg : g->deg, n, w.words, w.contrib[0], w.dpart);
+    BYO_HIP(hipGetLastError());
+  }
   if (iters == 0) {
     // a zero-step run returns the initial vector p = 1/n
     fill_f32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_rank, n, 1.0f / (float)n);
@@ -394,7 +397,7 @@ extern "C" byo_status byo_pagerank(byo_graph *g, double damping, int32_t iters, 
     }
     return BYO_OK;
   }
-  if (o.pr_blocked != 0 && omit == 0 && tiles_wanted(g)) {
+  if (tiled) {
     byo_tiles *tl = nullptr;
     BYO_TRY(tiles_ensure(g, pr_tile_shift(g, o.pr_blocked), s, &tl));
     // the tiled step runs in the layout's relabelled vertex order

@@ -56,11 +56,14 @@ def test_heuristic_cutoff_and_balance_choices():
     assert sel.heuristic_choice(rec(m=m, k=10, degsum=100, max_deg=10, cv=0.1)) == 0
     assert sel.heuristic_choice(rec(m=m, k=10, degsum=5000, max_deg=900, cv=0.1)) == 1
     assert sel.heuristic_choice(rec(m=m, k=10, degsum=5000, max_deg=5000, cv=0.1)) == 3
-    # a push looks at the frontier's own largest degree when the level knows it
+    # a push looks at the frontier's own longest list when the level knows it
     hub = rec(m=m, k=10, degsum=5000, max_deg=5000, cv=0.1)
-    assert sel.heuristic_choice(dict(hub, max_deg_u=600)) == 1
-    assert sel.heuristic_choice(dict(hub, max_deg_u=4096)) == 3
-    assert sel.heuristic_choice(dict(hub, max_deg_u=-1)) == 3
+    assert sel.heuristic_choice(dict(hub, max_deg_u=512)) == 1      # 8 wavefront rounds
+    assert sel.heuristic_choice(dict(hub, max_deg_u=513)) == 3      # longer: edge-balanced
+    assert sel.heuristic_choice(dict(hub, max_deg_u=-1)) == 3       # unknown: the graph's 5000
+    assert sel.heuristic_choice(rec(m=m, k=400, degsum=3000, max_deg=5000, max_deg_u=8)) == 0
+    assert sel.heuristic_choice(rec(m=m, k=400, degsum=3000, max_deg=5000, max_deg_u=9)) == 1
+    assert sel.heuristic_choice(rec(m=m, k=10, degsum=70000, max_deg=5000, max_deg_u=100)) == 3
     # ... and a pull keeps the graph's (it scans the lists of unvisited vertices)
     assert sel.heuristic_choice(dict(over, max_deg=1000, max_deg_u=5)) == 5
 
