@@ -80,6 +80,47 @@ __global__ void bfs_visited_init_kernel(uint64_t *__restrict__ visited, const ui
   }
 }
 
+// Single-source start in two launches: every parent and depth to -1 and the
+// visited bitmap as bfs_visited_init_kernel sets it (src included) ...
+__global__ void bfs_reset_kernel(int32_t *__restrict__ parent, int32_t *__restrict__ depth,
+                                 uint64_t *__restrict__ visited, const uint64_t *__restrict__ zero_bits, int64_t n,
+                                 int64_t words, int32_t src) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    parent[i] = -1;
+    depth[i] = -1;
+    if (i < words) {
+      uint64_t x = zero_bits[i];
+      if (i == words - 1 && (n & 63)) x |= ~0ull << (n & 63);
+      if (i == (int64_t)(src >> 6)) x |= 1ull << (src & 63);
+      visited[i] = x;
+    }
+  }
+}
+
+// ... then the source's parent and depth, the first frontier list {src}, its
+// degree scan (0, deg) and, in counter slot `stats`, its degree sum and
+// largest degree; the other counter slots cleared.
+__global__ void bfs_single_init_kernel(int32_t *__restrict__ parent, int32_t *__restrict__ depth, int32_t src,
+                                       const int32_t *__restrict__ deg, int32_t *__restrict__ ids,
+                                       long long *__restrict__ scan, byo_counters *ctr, int stats) {
+  const int t = threadIdx.x;
+  if (t < BYO_COUNTER_SLOTS) {
+    const unsigned long long d = t == stats ? (unsigned long long)deg[src] : 0ull;
+    ctr[t].count = 0;
+    ctr[t].degsum = d;
+    ctr[t].aux0 = 0;
+    ctr[t].aux1 = 0;
+    ctr[t].maxdeg = d;
+  }
+  if (t == 0) {
+    parent[src] = src;
+    depth[src] = 0;
+    ids[0] = src;
+    scan[0] = 0;
+    scan[1] = (long long)deg[src];
+  }
+}
+
 __global__ void set_tail_kernel(uint64_t *bits, int64_t n, int64_t words) {
   if (threadIdx.x == 0 && (n & 63)) bits[words - 1] |= (~0ull << (n & 63));
 }
@@ -281,22 +322,31 @@ byo_status bfs_run(byo_graph *g, const int32_t *srcs, int64_t ns, int32_t *d_dep
   BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
   BYO_CHECK(!o.compressed || o.api_omit == 0, BYO_EINVAL, "byte-coded lists run with the full container API");
   if (o.compressed) BYO_TRY(cz_ensure(g, s, nullptr));
-  BYO_TRY(fill_i32(d_parent, n, -1, s));
-  BYO_TRY(fill_i32(d_depth, n, -1, s));
-  // sources staged through the spare frontier list
-  BYO_HIP(hipMemcpyAsync(w.ids[1], srcs, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
-  bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
-      w.visited, g->zero_bits, n, w.words, srcs[0]);
-  bfs_visited_sources_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(w.visited, w.ids[1], ns);
-  bfs_init_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(d_parent, d_depth, w.ids[1], ns, w.ids[0], w.ctr);
-  BYO_HIP(hipGetLastError());
+  // slot BYO_COUNTER_SLOTS - 1 receives the first frontier's statistics: it
+  // is next written by level 3 and cleared by level 1
+  if (ns == 1) {
+    bfs_reset_kernel<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, s>>>(
+        d_parent, d_depth, w.visited, g->zero_bits, n, w.words, srcs[0]);
+    bfs_single_init_kernel<<<1, 64, 0, s>>>(d_parent, d_depth, srcs[0], g->deg, w.ids[0], w.scan, w.ctr,
+                                            BYO_COUNTER_SLOTS - 1);
+    BYO_HIP(hipGetLastError());
+  } else {
+    BYO_TRY(fill_i32(d_parent, n, -1, s));
+    BYO_TRY(fill_i32(d_depth, n, -1, s));
+    // sources staged through the spare frontier list
+    BYO_HIP(hipMemcpyAsync(w.ids[1], srcs, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
+    bfs_visited_init_kernel<<<(unsigned)std::min<int64_t>((w.words + 255) / 256, 4096), 256, 0, s>>>(
+        w.visited, g->zero_bits, n, w.words, srcs[0]);
+    bfs_visited_sources_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(w.visited, w.ids[1], ns);
+    bfs_init_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(d_parent, d_depth, w.ids[1], ns, w.ids[0], w.ctr);
+    BYO_HIP(hipGetLastError());
+    BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
+    src_stats_kernel<<<(unsigned)std::min<int64_t>((ns + 255) / 256, 1024), 256, 0, s>>>(
+        w.ids[0], ns, g->deg, w.scan + ns, w.ctr + (BYO_COUNTER_SLOTS - 1));
+    BYO_HIP(hipGetLastError());
+  }
   long long dsum = 0;
-  BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
   bool use_mlp = o.selector == BYO_SEL_MLP && selector_ready();
-  // slot BYO_COUNTER_SLOTS - 1 is next written by level 3 and cleared by level 1
-  src_stats_kernel<<<(unsigned)std::min<int64_t>((ns + 255) / 256, 1024), 256, 0, s>>>(
-      w.ids[0], ns, g->deg, w.scan + ns, w.ctr + (BYO_COUNTER_SLOTS - 1));
-  BYO_HIP(hipGetLastError());
   byo_counters c0;
   BYO_TRY(read_slot(g, BYO_COUNTER_SLOTS - 1, s, &c0));
   dsum = (long long)c0.degsum;

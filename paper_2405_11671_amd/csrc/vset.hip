@@ -176,11 +176,38 @@ __global__ void __launch_bounds__(CB_THREADS) deg_scan_write_kernel(const int32_
   if (blockIdx.x == 0 && threadIdx.x == 0) scan[k] = partial[nb];
 }
 
+// The same for a frontier of at most DS_TILE entries: one workgroup, one launch.
+__global__ void __launch_bounds__(CB_THREADS) deg_scan_single_kernel(const int32_t *__restrict__ ids, int64_t k,
+                                                                     const int32_t *__restrict__ deg, int32_t per,
+                                                                     long long *__restrict__ scan) {
+  const int64_t i0 = (int64_t)threadIdx.x * DS_ITEMS;
+  long long d[DS_ITEMS];
+  long long c = 0;
+#pragma unroll
+  for (int j = 0; j < DS_ITEMS; ++j) {
+    d[j] = (i0 + j < k) ? deg_units(deg[ids[i0 + j]], per) : 0;
+    c += d[j];
+  }
+  long long tot;
+  long long pos = block_exclusive_scan_256(c, &tot);
+#pragma unroll
+  for (int j = 0; j < DS_ITEMS; ++j) {
+    if (i0 + j < k) scan[i0 + j] = pos;
+    pos += d[j];
+  }
+  if (threadIdx.x == 0) scan[k] = tot;
+}
+
 int64_t scan_partials_needed(int64_t k) { return std::max<int64_t>(1, (k + DS_TILE - 1) / DS_TILE) + 1; }
 
 byo_status scan_degree_units(const int32_t *deg, const int32_t *ids, int64_t k, int32_t per, long long *scan,
                              long long *partial, int64_t partial_cap, hipStream_t s) {
   BYO_CHECK(per >= 1, BYO_EINVAL, "bad unit size");
+  if (k <= DS_TILE) {
+    deg_scan_single_kernel<<<1, CB_THREADS, 0, s>>>(ids, k, deg, per, scan);
+    BYO_HIP(hipGetLastError());
+    return BYO_OK;
+  }
   int64_t nb = std::max<int64_t>(1, (k + DS_TILE - 1) / DS_TILE);
   BYO_CHECK(nb + 1 <= partial_cap, BYO_EINVAL, "scan scratch too small");
   deg_scan_reduce_kernel<<<(unsigned)nb, CB_THREADS, 0, s>>>(ids, k, deg, per, partial);
