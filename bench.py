@@ -372,6 +372,91 @@ def container_study(byo, gen, args, configs, base_name, title, unit, extra_algos
           flush=True)
 
 
+def config_study(byo, gen, args):
+    """The other quoted workloads next to the oracle on this host's cores:
+    ER n=2^14 (average degree 8), RMAT-20 and the 4096^2 lattice with 10% of
+    edges deleted. GPU: BFS from each listed source under the threshold rule
+    and the learned selector, connectivity, PageRank; oracle (one thread): the
+    same calls on a bounded sample. Rates in GTEPS counting each reached edge
+    once for BFS and connectivity and every edge per PageRank step."""
+    import torch
+    import oracle
+    from paper_2405_11671_amd import selector as sel
+    params, mu, sd, _ = sel.load_weights(os.path.join(ROOT, "paper_2405_11671_amd", "selector_weights.json"))
+    sel.install(params, mu, sd)
+    out = {}
+    cases = [
+        ("er14", gen.er_pairs(1 << 14, 8.0, seed=1), "first", 20, 1, 20, 1),
+        ("rmat20", gen.rmat_pairs(20, 16, gen.GRAPH500_ABCD, seed=1, permute=True), 16, 10, 4, 10, 1),
+        ("lattice4096", gen.grid_pairs(4096, 4096, 0.1, seed=1), "corner", 0, 1, 0, 1),
+    ]
+    for name, p, src_spec, pr_iters, cpu_bfs, cpu_pr, cpu_cc in cases:
+        log(f"[configs] {name}: n={p.n}")
+        g = byo.Graph.from_pairs(p)
+        if src_spec == "first" or src_spec == "corner":
+            srcs = [0]
+        else:
+            srcs = [int(x) for x in gen.pick_sources(p, src_spec, seed=2)]
+        depth = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        label = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        rank = torch.empty(g.n, dtype=torch.float32, device="cuda")
+
+        def gpu(o):
+            e, t0 = 0, time.perf_counter()
+            for s_ in srcs:
+                _, _, st = byo.bfs(g, s_, opts=o, depth=depth, parent=parent)
+                e += st["edges"] // 2
+            torch.cuda.synchronize()
+            return e, time.perf_counter() - t0
+
+        def best(fn, reps=3):
+            fn()
+            return min(fn() for _ in range(reps))
+
+        plain = byo.default_opts()
+        learned = byo.default_opts(selector=byo.SEL_MLP)
+        e_bfs, t_plain = best(lambda: gpu(plain))
+        _, t_learned = best(lambda: gpu(learned))
+
+        def cc_pr():
+            t0 = time.perf_counter()
+            byo.cc(g, label=label)
+            if pr_iters:
+                byo.pagerank(g, 0.85, pr_iters, rank=rank)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+        t_ccpr = best(cc_pr)
+        gpu_edges = e_bfs + g.m // 2 + pr_iters * g.m
+        row = {"n": g.n, "m": g.m, "bfs_sources": len(srcs), "pr_iters": pr_iters,
+               "gpu_bfs_gteps": round(e_bfs / t_plain / 1e9, 3),
+               "gpu_bfs_learned_gteps": round(e_bfs / t_learned / 1e9, 3),
+               "gpu_all_gteps": round(gpu_edges / (t_plain + t_ccpr) / 1e9, 3),
+               "gpu_all_ms": round((t_plain + t_ccpr) * 1e3, 3)}
+        og = oracle.Graph.from_pairs(p)
+        deg = og.degrees()
+        t0 = time.perf_counter()
+        e_cpu = 0
+        for s_ in srcs[:cpu_bfs]:
+            d, _ = og.bfs(s_)
+            e_cpu += int(deg[d >= 0].sum()) // 2
+        if cpu_cc:
+            og.cc()
+            e_cpu += og.m // 2
+        if cpu_pr:
+            og.pagerank(0.85, cpu_pr)
+            e_cpu += cpu_pr * og.m
+        el = time.perf_counter() - t0
+        row.update({"cpu_gteps": round(e_cpu / el / 1e9, 4), "cpu_s": round(el, 2),
+                    "cpu_sample": f"BFS from {min(cpu_bfs, len(srcs))} source(s)" + (" + CC" if cpu_cc else "")
+                                  + (f" + {cpu_pr} PageRank steps (FP64)" if cpu_pr else ""),
+                    "gpu_over_cpu": round((gpu_edges / (t_plain + t_ccpr)) / (e_cpu / el), 1)})
+        out[name] = row
+        log(f"[configs] {name}: {row}")
+        del og, g
+    print(json.dumps({"configs": out, "cpu_cores": 1}), flush=True)
+
+
 def insert_study(byo, gen, args):
     """Batch-insert throughput against batch size (Section 6.6, fig
     inserts_with_sort): on the RMAT graph of the benchmark (the stand-in for
@@ -481,6 +566,8 @@ def parse():
                     help="compare the byte-coded CSR with the CSR instead of the benchmark step")
     ap.add_argument("--inserts", action="store_true",
                     help="batch-insert throughput against batch size instead of the benchmark step")
+    ap.add_argument("--configs", action="store_true",
+                    help="ER-14, RMAT-20 and the 4096^2 lattice on the GPU next to the oracle on this host")
     ap.add_argument("--no-grid", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-bc", action="store_true", help="skip the betweenness and k-core detail")
@@ -506,6 +593,10 @@ def main():
 
     if args.inserts:
         insert_study(byo, gen, args)
+        return
+    if args.configs:
+        torch.cuda.init()
+        config_study(byo, gen, args)
         return
     if args.ablation or args.compression:
         torch.cuda.init()
