@@ -163,10 +163,7 @@ static int64_t frontier_max(const byo_counters &c) {
 }
 
 static byo_status read_slot(byo_graph *g, int slot, hipStream_t s, byo_counters *out) {
-  BYO_HIP(hipMemcpyAsync(g->ws.h_ctr + slot, g->ws.ctr + slot, sizeof(byo_counters), hipMemcpyDeviceToHost, s));
-  BYO_HIP(hipStreamSynchronize(s));
-  *out = g->ws.h_ctr[slot];
-  return BYO_OK;
+  return sync_read(s, g->ws.ctr + slot, out, sizeof(byo_counters));
 }
 
 static level_features features(const byo_graph *g, int64_t k, int64_t degsum, int64_t unvisited, int64_t level,
@@ -792,6 +789,7 @@ static byo_status collect(byo_graph *g, int algo, int64_t src, int repeats, int3
         BYO_HIP(hipEventRecord(eb, s));
         BYO_TRY(read_slot(g, 0, s, &c));
         float ms = 0.f;
+        BYO_HIP(hipEventSynchronize(eb));  // the counters can arrive before the event completes
         BYO_HIP(hipEventElapsedTime(&ms, ea, eb));
         if (r == 0 || ms < vbest) vbest = ms;
       }
