@@ -660,6 +660,7 @@ static void push_trial(int algo, const byo_graph *g, const level_features &f, in
   r.out_count = oc;
   r.out_degsum = od;
   r.max_deg = g->max_deg;
+  r.max_deg_u = (int32_t)f.frontier_max_deg;
   r.cv = g->cv_deg;
   r.ms = ms;
   trace_push(r);
@@ -713,6 +714,7 @@ static byo_status collect(byo_graph *g, int algo, int64_t src, int repeats, int3
     fr.sparse = true;
     fr.k = 1;
     fr.degsum = d0;
+    fr.maxdeg = d0;
     reached = 1;
   } else {
     if (n == 0) return BYO_OK;
@@ -727,10 +729,12 @@ static byo_status collect(byo_graph *g, int algo, int64_t src, int repeats, int3
     fr.dense = true;
     fr.k = n;
     fr.degsum = g->m;
+    fr.maxdeg = g->max_deg;
   }
   int64_t cap = o.max_levels > 0 ? o.max_levels : n + 1;
   for (int32_t level = 0; level < cap; ++level) {
     level_features f = features(g, fr.k, fr.degsum, bfs ? n - reached : n, level, fr.dense && !fr.sparse);
+    f.frontier_max_deg = fr.maxdeg;
     // save the state a level modifies
     BYO_HIP(hipMemcpyAsync(save_a, d_out, ib, hipMemcpyDeviceToDevice, s));
     if (bfs) {
@@ -812,6 +816,7 @@ static byo_status collect(byo_graph *g, int algo, int64_t src, int repeats, int3
     }
     fr.k = (int64_t)c.count;
     fr.degsum = (int64_t)c.degsum;
+    fr.maxdeg = frontier_max(c);
   }
   BYO_HIP(hipStreamSynchronize(s));
   return BYO_OK;
