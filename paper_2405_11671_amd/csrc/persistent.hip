@@ -187,22 +187,52 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
       }
     } else {
       ++push_levels;
-      // a lane claims v: CAS on parent[v], then the visited and output bits
-      auto claim = [&](int32_t src, int32_t v) {
-        if (atomicCAS(&parent[v], -1, src) != -1) return;
+      // a lane that won v's CAS on parent[v] sets its depth and its visited
+      // and output bits; the CASes of a batch are all issued before any result
+      // is used, so a lane waits about one round trip per batch, not per edge
+      auto won = [&](int32_t v) {
         const unsigned long long bit = 1ull << (v & 63);
         depth[v] = nd;
         atomicOr((unsigned long long *)&visited[v >> 6], bit);
         atomicOr((unsigned long long *)&bout[v >> 6], bit);
         emit(v);
       };
-      // the frontier: the ID list a push level wrote, or after a pull level
-      // (which writes only the bitmap) the set bits of the frontier bitmap,
-      // a wavefront per 64-vertex word
+      // a wavefront's lanes take list positions lb + lane, lb + lane + 64, ...
+      // of u's list, four rounds in flight per step
+      auto wave_list = [&](int32_t wu, int64_t wb, int64_t we) {
+        for (int64_t x0 = wb + lane_id(); x0 - lane_id() < we; x0 += 4 * BYO_WAVE) {
+          int32_t v[4];
+          bool tried[4];
+          int32_t old[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) v[j] = x0 + j * BYO_WAVE < we ? nbr[x0 + j * BYO_WAVE] : -1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) tried[j] = v[j] >= 0 && !((visited[v[j] >> 6] >> (v[j] & 63)) & 1ull);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) old[j] = tried[j] ? atomicCAS(&parent[v[j]], -1, wu) : 0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (tried[j] && old[j] == -1) won(v[j]);
+        }
+      };
+      // a frontier list is walked by groups of g lanes per vertex, g a power
+      // of two sized from the level's mean degree (about four entries per
+      // lane), raised to a whole wavefront when the list has no more vertices
+      // than the grid has wavefronts; the bitmap left by a pull level is
+      // walked a lane per vertex
+      const unsigned long long nthreads = (unsigned long long)nblocks * PB_THREADS;
+      unsigned g = 1;
+      if (!prev_pull) {
+        if (k * BYO_WAVE <= nthreads) {
+          g = BYO_WAVE;
+        } else {
+          while (g < (unsigned)BYO_WAVE && (unsigned long long)g * 4 * k < ds && (unsigned long long)g * 2 * k <= nthreads) g *= 2;
+        }
+      }
+      const unsigned sub = (unsigned)t & (g - 1);
       const unsigned long long items = prev_pull ? (unsigned long long)words * BYO_WAVE : k;
-      const unsigned long long stride = (unsigned long long)nblocks * PB_THREADS;
-      for (unsigned long long base = (unsigned long long)blockIdx.x * PB_THREADS; base < items; base += stride) {
-        const unsigned long long i = base + t;
+      for (unsigned long long base = (unsigned long long)blockIdx.x * PB_THREADS; base < items * g; base += nthreads) {
+        const unsigned long long i = (base + t) / g;
         int32_t u = -1;
         int64_t b = 0, e = 0;
         if (prev_pull) {
@@ -214,31 +244,39 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
           b = off[u];
           e = off[u + 1];
         }
-        const bool wide = u >= 0 && e - b > tw;
+        const bool wide = u >= 0 && e - b > (int64_t)g * tw;
         if (u >= 0 && !wide) {
-          // four neighbours and their visited words in flight per step
-          for (int64_t x0 = b; x0 < e; x0 += 8) {
+          // lane sub of the group takes entries b + sub, b + sub + g, ...:
+          // eight entries, their visited words and their CASes in flight per step
+          for (int64_t x0 = b + sub; x0 - sub < e; x0 += 8 * (int64_t)g) {
             int32_t v[8];
             uint64_t vw[8];
+            bool tried[8];
+            int32_t old[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = x0 + j < e ? nbr[x0 + j] : -1;
+            for (int j = 0; j < 8; ++j) v[j] = x0 + j * (int64_t)g < e ? nbr[x0 + j * (int64_t)g] : -1;
 #pragma unroll
             for (int j = 0; j < 8; ++j) vw[j] = v[j] >= 0 ? visited[v[j] >> 6] : ~0ull;
 #pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              tried[j] = v[j] >= 0 && !((vw[j] >> (v[j] & 63)) & 1ull);
+              old[j] = tried[j] ? atomicCAS(&parent[v[j]], -1, u) : 0;
+            }
+#pragma unroll
             for (int j = 0; j < 8; ++j)
-              if (!((vw[j] >> (v[j] & 63)) & 1ull)) claim(u, v[j]);
+              if (tried[j] && old[j] == -1) won(v[j]);
           }
         }
-        uint64_t wm = __ballot(wide);
+        // a list longer than g * t_wave is walked by the whole wavefront;
+        // the lanes of one group hold the same vertex, so only its first
+        // lane raises the ballot
+        uint64_t wm = __ballot(wide && sub == 0);
         while (wm) {
           const int l = __ffsll((long long)wm) - 1;
           wm &= wm - 1;
           const int32_t wu = read_lane_i32(u, l);
           const int64_t wb = (int64_t)read_lane_u64((uint64_t)b, l), we = (int64_t)read_lane_u64((uint64_t)e, l);
-          for (int64_t x = wb + lane_id(); x < we; x += BYO_WAVE) {
-            const int32_t v = nbr[x];
-            if (!((visited[v >> 6] >> (v & 63)) & 1ull)) claim(wu, v);
-          }
+          wave_list(wu, wb, we);
         }
       }
     }
