@@ -6,13 +6,21 @@
 // where a host-driven level loop pays a launch and a counter read-back per
 // level.
 //
+// The launch also starts the search: every parent and depth to -1, the
+// visited bitmap to the vertices of degree zero (and the bits past n), the
+// frontier bitmaps clear; then, after a grid barrier, the sources, their
+// bitmap bits and the first level's counters; so a search is one launch and
+// one read-back of its totals.
+//
 // A level, identical in every workgroup:
 //  - reads the frontier's size and degree sum (written by the level before),
 //    and picks the direction with the threshold rule: dense pull iff
 //    |U| + sum(deg U) > m / dense_divisor;
-//  - push: the frontier's ID list, a lane per vertex with four neighbours
-//    in flight, lists longer than t_wave shared by the wavefront; a CAS on
-//    parent[v] claims v;
+//  - push: the frontier's ID list; a list of up to PB_EB vertices edge-
+//    balanced over the whole grid (each workgroup builds its degree prefix
+//    in LDS), a longer one by lane groups sized from the mean degree, lists
+//    longer than the group's share taken by the whole wavefront; eight
+//    neighbours in flight per lane; a CAS on parent[v] claims v;
 //  - pull: a wavefront per 64-vertex word of the visited bitmap, words
 //    already all visited skipped; each unvisited vertex scans its list until
 //    a neighbour in the frontier bitmap (the lane the first t_wave entries,
@@ -38,9 +46,13 @@ namespace byo {
 
 constexpr int PB_THREADS = 512;
 constexpr int PB_STAGE = 4096;          // LDS staging of one workgroup's new vertices per level
-constexpr int PB_PER_CU = 3;            // workgroups per compute unit in the launch
+// workgroups per compute unit in the launch: one (256 on the chip) keeps the
+// grid barrier cheap for the many small levels of a batch; two were 5% slower
+// there and 4% faster on a single RMAT-22 search
+constexpr int PB_PER_CU = 1;
 constexpr unsigned PB_SPIN_LIMIT = 1u << 22;
 constexpr int PB_SLOT = 16;             // counter slots 128 bytes apart
+constexpr int PB_EB = 2048;             // frontier lists up to this long are pushed edge-balanced over the grid
 
 struct pb_ctl {
   grid_sync sync;
@@ -59,33 +71,79 @@ struct pb_ws {
   pb_result *res = nullptr;
   int nblocks = 0;
   bool checked = false, usable = false;
+  bool reset = true;  // the grid barrier's counters need clearing (first use, or after a failed wait)
 };
 
-// frontier of the first level: the sources' count and degree sum
-__global__ void pb_init_kernel(pb_ctl *c, unsigned long long k0, const long long *__restrict__ degsum0) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    c->cnt[0] = k0;
-    c->dsum[0] = (unsigned long long)*degsum0;
-  }
-}
+// up to this many sources travel in the launch's arguments; more are copied
+// to the device first
+constexpr int PB_ARG_SRCS = 64;
+struct pb_srcs {
+  int32_t v[PB_ARG_SRCS];
+};
 
 __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
     const int64_t *__restrict__ off, const int32_t *__restrict__ nbr, const int32_t *__restrict__ deg, int64_t n,
     int64_t m, int32_t div, int32_t t_wave, int32_t *__restrict__ parent, int32_t *__restrict__ depth,
     uint64_t *__restrict__ visited, int64_t words, uint64_t *__restrict__ b0, uint64_t *__restrict__ b1,
     uint64_t *__restrict__ b2, int32_t *__restrict__ q0, int32_t *__restrict__ q1, pb_ctl *__restrict__ c,
-    int32_t max_levels, pb_result *__restrict__ res) {
+    int32_t max_levels, pb_result *__restrict__ res, const uint64_t *__restrict__ zero_bits, pb_srcs sarg,
+    const int32_t *__restrict__ sdev, int64_t ns) {
   __shared__ int32_t stage[PB_STAGE];
   __shared__ unsigned s_cnt;
   __shared__ unsigned long long s_base;
+  // edge-balanced push of a short frontier list: the list's degree prefix,
+  // each entry's offset from list position to neighbour index, and its vertex
+  __shared__ uint32_t s_pre[PB_EB + 1];
+  __shared__ int64_t s_shift[PB_EB];
+  __shared__ int32_t s_u[PB_EB];
+  __shared__ uint32_t s_wsum[PB_THREADS / BYO_WAVE];
   const unsigned nblocks = gridDim.x;
   const int t = threadIdx.x;
   const int64_t cutoff = m / (div > 0 ? div : 20);
   const int64_t tw = t_wave > 0 ? t_wave : 32;
   unsigned long long push_levels = 0, pull_levels = 0, reached = 0, edges = 0;
   int L = 0, limit = 0;
+  {
+    // start: parents and depths -1, visited = vertices of degree zero and
+    // the bits past n, the first two frontier bitmaps clear (the third is
+    // cleared during level 0)
+    const int64_t gt = (int64_t)blockIdx.x * PB_THREADS + t, gs = (int64_t)nblocks * PB_THREADS;
+    for (int64_t i = gt; i < n; i += gs) {
+      parent[i] = -1;
+      depth[i] = -1;
+    }
+    for (int64_t w = gt; w < words; w += gs) {
+      uint64_t x = zero_bits[w];
+      if (w == words - 1 && (n & 63)) x |= ~0ull << (n & 63);
+      visited[w] = x;
+      b0[w] = 0ull;
+      b1[w] = 0ull;
+    }
+    if (!grid_barrier(&c->sync, nblocks, PB_SPIN_LIMIT)) ns = 0;
+    // then the sources (workgroup 0): parent = itself, depth 0, the first
+    // list and bitmap, and the first level's counters (the other two slots
+    // clear)
+    if (blockIdx.x == 0 && ns > 0) {
+      unsigned long long dsum = 0;
+      for (int64_t i = t; i < ns; i += PB_THREADS) {
+        const int32_t sv = ns <= PB_ARG_SRCS ? sarg.v[i] : sdev[i];
+        parent[sv] = sv;
+        depth[sv] = 0;
+        q0[i] = sv;
+        atomicOr((unsigned long long *)&visited[sv >> 6], 1ull << (sv & 63));
+        atomicOr((unsigned long long *)&b0[sv >> 6], 1ull << (sv & 63));
+        dsum += (unsigned long long)deg[sv];
+      }
+      dsum = block_sum<unsigned long long, PB_THREADS>(dsum);
+      if (t < 3) {
+        c->cnt[t * PB_SLOT] = t == 0 ? (unsigned long long)ns : 0ull;
+        c->dsum[t * PB_SLOT] = t == 0 ? dsum : 0ull;
+      }
+    }
+    if (ns == 0 || !grid_barrier(&c->sync, nblocks, PB_SPIN_LIMIT)) L = -1;
+  }
   bool prev_pull = false;  // level 0 pushes from the sources' list (its bitmap is set too)
-  for (;; ++L) {
+  for (; L >= 0; ++L) {
     const unsigned long long k = ld_rlx64(&c->cnt[(L % 3) * PB_SLOT]);
     const unsigned long long ds = ld_rlx64(&c->dsum[(L % 3) * PB_SLOT]);
     reached += k;
@@ -215,68 +273,155 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
             if (tried[j] && old[j] == -1) won(v[j]);
         }
       };
-      // a frontier list is walked by groups of g lanes per vertex, g a power
-      // of two sized from the level's mean degree (about four entries per
-      // lane), raised to a whole wavefront when the list has no more vertices
-      // than the grid has wavefronts; the bitmap left by a pull level is
-      // walked a lane per vertex
+      // a short frontier list with many edges (a hub among a few vertices)
+      // would leave one wavefront walking the hub's list: every workgroup
+      // builds the list's degree prefix in LDS and the grid takes the
+      // level's edges in equal shares, eight in flight per lane
       const unsigned long long nthreads = (unsigned long long)nblocks * PB_THREADS;
-      unsigned g = 1;
-      if (!prev_pull) {
-        if (k * BYO_WAVE <= nthreads) {
-          g = BYO_WAVE;
-        } else {
-          while (g < (unsigned)BYO_WAVE && (unsigned long long)g * 4 * k < ds && (unsigned long long)g * 2 * k <= nthreads) g *= 2;
-        }
-      }
-      const unsigned sub = (unsigned)t & (g - 1);
-      const unsigned long long items = prev_pull ? (unsigned long long)words * BYO_WAVE : k;
-      for (unsigned long long base = (unsigned long long)blockIdx.x * PB_THREADS; base < items * g; base += nthreads) {
-        const unsigned long long i = (base + t) / g;
-        int32_t u = -1;
-        int64_t b = 0, e = 0;
-        if (prev_pull) {
-          if (i < items && ((bin[i >> 6] >> (i & 63)) & 1ull)) u = (int32_t)i;
-        } else if (i < k) {
-          u = qin[i];
-        }
-        if (u >= 0) {
-          b = off[u];
-          e = off[u + 1];
-        }
-        const bool wide = u >= 0 && e - b > (int64_t)g * tw;
-        if (u >= 0 && !wide) {
-          // lane sub of the group takes entries b + sub, b + sub + g, ...:
-          // eight entries, their visited words and their CASes in flight per step
-          for (int64_t x0 = b + sub; x0 - sub < e; x0 += 8 * (int64_t)g) {
-            int32_t v[8];
-            uint64_t vw[8];
-            bool tried[8];
-            int32_t old[8];
+      if (!prev_pull && k <= (unsigned long long)PB_EB && ds < (1ull << 32)) {
+        constexpr int PER = PB_EB / PB_THREADS;
+        int32_t ul[PER];
+        int64_t bl[PER];
+        uint32_t dl[PER], tsum = 0;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = x0 + j * (int64_t)g < e ? nbr[x0 + j * (int64_t)g] : -1;
+        for (int j = 0; j < PER; ++j) {
+          const unsigned long long i = (unsigned long long)t * PER + j;
+          ul[j] = i < k ? qin[i] : -1;
+        }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) vw[j] = v[j] >= 0 ? visited[v[j] >> 6] : ~0ull;
+        for (int j = 0; j < PER; ++j) {
+          bl[j] = ul[j] >= 0 ? off[ul[j]] : 0;
+          dl[j] = ul[j] >= 0 ? (uint32_t)deg[ul[j]] : 0u;
+          tsum += dl[j];
+        }
+        // exclusive scan of the per-thread sums over the workgroup
+        uint32_t x = tsum;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              tried[j] = v[j] >= 0 && !((vw[j] >> (v[j] & 63)) & 1ull);
-              old[j] = tried[j] ? atomicCAS(&parent[v[j]], -1, u) : 0;
+        for (int o = 1; o < BYO_WAVE; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o);
+          if (lane_id() >= o) x += y;
+        }
+        if (lane_id() == BYO_WAVE - 1) s_wsum[t / BYO_WAVE] = x;
+        __syncthreads();
+        uint32_t run = x - tsum, total = 0;
+#pragma unroll
+        for (int w = 0; w < PB_THREADS / BYO_WAVE; ++w) {
+          if (w < t / BYO_WAVE) run += s_wsum[w];
+          total += s_wsum[w];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const unsigned long long i = (unsigned long long)t * PER + j;
+          if (i < k) {
+            s_pre[i] = run;
+            s_shift[i] = bl[j] - (int64_t)run;
+            s_u[i] = ul[j];
+          }
+          run += dl[j];
+        }
+        __syncthreads();
+        const int kk = (int)k;
+        // the list position holding edge e: the last i with s_pre[i] <= e
+        // (its degree is not zero, as s_pre[i + 1] > e)
+        auto find = [&](uint32_t e) {
+          int lo = 0, hi = kk;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= e) lo = mid;
+            else hi = mid;
+          }
+          return lo;
+        };
+        for (unsigned long long e0 = (unsigned long long)blockIdx.x * PB_THREADS + t; e0 < total; e0 += 8 * nthreads) {
+          int32_t v[8], su[8];
+          uint64_t vw[8];
+          bool tried[8];
+          int32_t old[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const unsigned long long e = e0 + j * nthreads;
+            su[j] = -1;
+            v[j] = -1;
+            if (e < total) {
+              const int i = find((uint32_t)e);
+              su[j] = s_u[i];
+              v[j] = nbr[(int64_t)e + s_shift[i]];
             }
+          }
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-              if (tried[j] && old[j] == -1) won(v[j]);
+          for (int j = 0; j < 8; ++j) vw[j] = v[j] >= 0 ? visited[v[j] >> 6] : ~0ull;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            tried[j] = v[j] >= 0 && !((vw[j] >> (v[j] & 63)) & 1ull);
+            old[j] = tried[j] ? atomicCAS(&parent[v[j]], -1, su[j]) : 0;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (tried[j] && old[j] == -1) won(v[j]);
+        }
+      } else {
+        // a frontier list is walked by groups of g lanes per vertex, g a power
+        // of two sized from the level's mean degree (about four entries per
+        // lane), raised to a whole wavefront when the list has no more vertices
+        // than the grid has wavefronts; the bitmap left by a pull level is
+        // walked a lane per vertex
+        unsigned g = 1;
+        if (!prev_pull) {
+          if (k * BYO_WAVE <= nthreads) {
+            g = BYO_WAVE;
+          } else {
+            while (g < (unsigned)BYO_WAVE && (unsigned long long)g * 4 * k < ds && (unsigned long long)g * 2 * k <= nthreads) g *= 2;
           }
         }
-        // a list longer than g * t_wave is walked by the whole wavefront;
-        // the lanes of one group hold the same vertex, so only its first
-        // lane raises the ballot
-        uint64_t wm = __ballot(wide && sub == 0);
-        while (wm) {
-          const int l = __ffsll((long long)wm) - 1;
-          wm &= wm - 1;
-          const int32_t wu = read_lane_i32(u, l);
-          const int64_t wb = (int64_t)read_lane_u64((uint64_t)b, l), we = (int64_t)read_lane_u64((uint64_t)e, l);
-          wave_list(wu, wb, we);
+        const unsigned sub = (unsigned)t & (g - 1);
+        const unsigned long long items = prev_pull ? (unsigned long long)words * BYO_WAVE : k;
+        for (unsigned long long base = (unsigned long long)blockIdx.x * PB_THREADS; base < items * g; base += nthreads) {
+          const unsigned long long i = (base + t) / g;
+          int32_t u = -1;
+          int64_t b = 0, e = 0;
+          if (prev_pull) {
+            if (i < items && ((bin[i >> 6] >> (i & 63)) & 1ull)) u = (int32_t)i;
+          } else if (i < k) {
+            u = qin[i];
+          }
+          if (u >= 0) {
+            b = off[u];
+            e = off[u + 1];
+          }
+          const bool wide = u >= 0 && e - b > (int64_t)g * tw;
+          if (u >= 0 && !wide) {
+            // lane sub of the group takes entries b + sub, b + sub + g, ...:
+            // eight entries, their visited words and their CASes in flight per step
+            for (int64_t x0 = b + sub; x0 - sub < e; x0 += 8 * (int64_t)g) {
+              int32_t v[8];
+              uint64_t vw[8];
+              bool tried[8];
+              int32_t old[8];
+  #pragma unroll
+              for (int j = 0; j < 8; ++j) v[j] = x0 + j * (int64_t)g < e ? nbr[x0 + j * (int64_t)g] : -1;
+  #pragma unroll
+              for (int j = 0; j < 8; ++j) vw[j] = v[j] >= 0 ? visited[v[j] >> 6] : ~0ull;
+  #pragma unroll
+              for (int j = 0; j < 8; ++j) {
+                tried[j] = v[j] >= 0 && !((vw[j] >> (v[j] & 63)) & 1ull);
+                old[j] = tried[j] ? atomicCAS(&parent[v[j]], -1, u) : 0;
+              }
+  #pragma unroll
+              for (int j = 0; j < 8; ++j)
+                if (tried[j] && old[j] == -1) won(v[j]);
+            }
+          }
+          // a list longer than g * t_wave is walked by the whole wavefront;
+          // the lanes of one group hold the same vertex, so only its first
+          // lane raises the ballot
+          uint64_t wm = __ballot(wide && sub == 0);
+          while (wm) {
+            const int l = __ffsll((long long)wm) - 1;
+            wm &= wm - 1;
+            const int32_t wu = read_lane_i32(u, l);
+            const int64_t wb = (int64_t)read_lane_u64((uint64_t)b, l), we = (int64_t)read_lane_u64((uint64_t)e, l);
+            wave_list(wu, wb, we);
+          }
         }
       }
     }
@@ -297,7 +442,7 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
     if (!grid_barrier(&c->sync, nblocks, PB_SPIN_LIMIT)) break;
   }
   if (blockIdx.x == 0 && t == 0) {
-    res->levels = L;
+    res->levels = L < 0 ? 0 : L;
     res->limit = limit;
     res->fail = ld_rlx(&c->sync.fail[0]) ? 1 : 0;
     res->reached = reached;
@@ -353,18 +498,20 @@ byo_status bfs_persistent_run(byo_graph *g, const int32_t *srcs, int64_t ns, int
   byo_workspace &w = g->ws;
   const int64_t n = g->n;
   BYO_CHECK(ns >= 1 && ns <= n, BYO_EINVAL, "bad source count");
-  BYO_TRY(fill_i32(d_parent, n, -1, s));
-  BYO_TRY(fill_i32(d_depth, n, -1, s));
-  // sources: staged through ids[1], then visited, parent/depth and the first
-  // list (ids[0]) and bitmap (bits[0]); the other bitmaps start clear
-  BYO_HIP(hipMemcpyAsync(w.ids[1], srcs, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
-  BYO_TRY(bfs_sources_init(g, w.ids[1], ns, d_parent, d_depth, s));
-  BYO_TRY(ids_to_bitmap(w.ids[0], ns, w.bits[0], w.words, s));
-  BYO_TRY(bitmap_clear(w.bits[1], w.words, s));
-  BYO_TRY(frontier_degree_scan(g, w.ids[0], ns, w.scan, w.partial, w.partial_cap, s));
-  BYO_HIP(hipMemsetAsync(d->ctl, 0, sizeof(pb_ctl), s));
-  pb_init_kernel<<<1, 64, 0, s>>>(d->ctl, (unsigned long long)ns, w.scan + ns);
-  BYO_HIP(hipGetLastError());
+  // up to PB_ARG_SRCS sources travel in the arguments, more through ids[1]
+  pb_srcs sarg;
+  std::memset(&sarg, 0, sizeof(sarg));
+  const int32_t *sdev = nullptr;
+  if (ns <= PB_ARG_SRCS) {
+    std::memcpy(sarg.v, srcs, sizeof(int32_t) * (size_t)ns);
+  } else {
+    BYO_HIP(hipMemcpyAsync(w.ids[1], srcs, sizeof(int32_t) * (size_t)ns, hipMemcpyHostToDevice, s));
+    sdev = w.ids[1];
+  }
+  if (d->reset) {
+    BYO_HIP(hipMemsetAsync(d->ctl, 0, sizeof(pb_ctl), s));
+    d->reset = false;
+  }
   const int64_t m = g->m, words = w.words;
   const int32_t div = o.dense_divisor > 0 ? o.dense_divisor : 20;
   const int32_t tw = o.t_wave > 0 ? o.t_wave : 32;
@@ -372,7 +519,8 @@ byo_status bfs_persistent_run(byo_graph *g, const int32_t *srcs, int64_t ns, int
   void *args[] = {(void *)&g->off, (void *)&g->nbr, (void *)&g->deg, (void *)&n, (void *)&m, (void *)&div,
                   (void *)&tw, (void *)&d_parent, (void *)&d_depth, (void *)&w.visited, (void *)&words,
                   (void *)&w.bits[0], (void *)&w.bits[1], (void *)&d->bits2, (void *)&w.ids[0], (void *)&w.ids[1],
-                  (void *)&d->ctl, (void *)&cap, (void *)&d->res};
+                  (void *)&d->ctl, (void *)&cap, (void *)&d->res, (void *)&g->zero_bits, (void *)&sarg,
+                  (void *)&sdev, (void *)&ns};
   {
     ktimer_scope kt(BYO_K_SMALL_LOOP, s);
     BYO_HIP(hipLaunchCooperativeKernel((const void *)bfs_persistent_kernel, dim3((unsigned)d->nblocks),
@@ -380,6 +528,8 @@ byo_status bfs_persistent_run(byo_graph *g, const int32_t *srcs, int64_t ns, int
   }
   pb_result r;
   BYO_TRY(sync_read(s, d->res, &r, sizeof(r)));
+  // a failed wait leaves the barrier's counters mid-count
+  if (r.fail) d->reset = true;
   BYO_CHECK(!r.fail, BYO_EHIP, "persistent BFS: a grid barrier wait timed out");
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
