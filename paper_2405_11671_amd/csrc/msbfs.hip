@@ -518,6 +518,15 @@ __device__ __forceinline__ void ms_add_tallies(const ms_tallies &tl, byo_counter
 // A tile cut into one chunk is finished by that chunk's workgroup (its
 // accumulators are the tile's whole result); the chunk results of a tile cut
 // into several go to `partial` for the apply pass.
+// an entry word read once per pass: loaded non-temporally
+__device__ __forceinline__ void tile_entry_nt(const uint32_t *__restrict__ ent, const int32_t *__restrict__ anchor,
+                                              int64_t e, int32_t &src, uint32_t &dst) {
+  const uint32_t x = __builtin_nontemporal_load(&ent[e]);
+  const int32_t g = __builtin_amdgcn_readfirstlane((int32_t)(e >> 6));
+  dst = x >> 16;
+  src = anchor[g] + (int32_t)(x & 0xffffu);
+}
+
 template <int W>
 __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__restrict__ ent,
                                                              const int32_t *__restrict__ anchor,
@@ -574,7 +583,7 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
   for (int j = 0; j < MT_ILP; ++j) {
     int64_t i = beg + t + (int64_t)j * MT_THREADS;
     i = i < end ? i : beg;  // a chunk is never empty
-    tile_entry(ent, anchor, i, un[j], dn[j]);
+    tile_entry_nt(ent, anchor, i, un[j], dn[j]);
   }
   for (int64_t e0 = beg + t; e0 < end; e0 += (int64_t)MT_THREADS * MT_ILP) {
     int32_t u[MT_ILP];
@@ -592,7 +601,7 @@ __global__ void __launch_bounds__(MT_THREADS) ms_tile_kernel(const uint32_t *__r
     for (int j = 0; j < MT_ILP; ++j) {
       int64_t i = e1 + (int64_t)j * MT_THREADS;
       i = i < end ? i : beg;
-      tile_entry(ent, anchor, i, un[j], dn[j]);
+      tile_entry_nt(ent, anchor, i, un[j], dn[j]);
     }
     bool ok[MT_ILP];
     bool some = false;
