@@ -83,6 +83,24 @@ def test_batch_persistent_level_cap():
     B = byo.Batch.from_pairs([graphs.path(100)])
     with pytest.raises(byo.ByoError, match="ELIMIT"):
         B.bfs([0], max_levels=10)
+    # the launch state left by a capped search does not leak into the next one
+    depth, parent, st = B.bfs([0])
+    assert np.array_equal(depth.cpu().numpy(), np.arange(100, dtype=np.int32))
+    assert st["levels"] == 100
+
+
+@pytest.mark.parametrize("count", [63, 64, 65, 130])
+def test_batch_persistent_many_sources(count):
+    """Up to 64 sources travel in the persistent launch's arguments, more are
+    copied to the device first: both sides of that boundary, twice in a row
+    (the launch resets everything it reads)."""
+    plist = gen.batch_pairs(count, seed=11, log2_hi=12.0)
+    st = check_batch(plist)
+    assert st["device_levels"] == st["levels"]
+    st2 = check_batch(plist)
+    assert st2["reached"] == st["reached"] and st2["levels"] == st["levels"]
+    st_host = check_batch(plist, persistent=0)
+    assert st_host["reached"] == st["reached"] and st_host["levels"] == st["levels"]
 
 
 def test_batch_mixed_shapes():
