@@ -297,7 +297,10 @@ unsigned kc_grid(int64_t count, int64_t per, int64_t cap) {
 // ---------------------------------------------------------------- persistent form
 
 constexpr int KP_THREADS = 512;
-constexpr int KP_PER_CU = 3;
+// one workgroup per CU (256 on the chip): the kernel's registers allow no
+// more, and capping them for two or three per CU spilled and ran slower
+// (42.8 and 70.5 ms against 37.0 ms at RMAT-22)
+constexpr int KP_PER_CU = 1;
 constexpr int KP_MAX_BLOCKS = 4096;
 constexpr unsigned KP_SPIN_LIMIT = 1u << 22;
 constexpr int KP_ILP = 4;                    // vertices per thread in flight in the passes over all vertices
@@ -311,7 +314,7 @@ constexpr int KP_STAGE = 5120;               // LDS staging of a workgroup's ite
 __host__ __device__ inline int64_t kp_items(int64_t d) { return (d + KC_RUN - 1) / KC_RUN; }
 
 // Same-address atomics from every workgroup serialise (tens of microseconds
-// per phase at 768 workgroups), so a phase's totals go through per-workgroup
+// per phase with hundreds of workgroups), so a phase's totals go through per-workgroup
 // records instead: each workgroup writes its own, and after the barrier every
 // workgroup reduces all of them to the same values. Only the append cursor of
 // the next frontier's items is an atomic, taken about once per workgroup.
