@@ -465,7 +465,15 @@ byo_status byo_batch_info(const byo_batch *b, int64_t *total_n, int64_t *total_m
 byo_status byo_batch_vertex_offset(const byo_batch *b, int32_t i, int64_t *out);
 /* BFS in every graph at once: h_srcs[i] is the source of graph i (local ID).
  * Outputs are concatenated: entries [voff(i), voff(i+1)) belong to graph i,
- * parent IDs are local to their graph. */
+ * parent IDs are local to their graph. d_depth and d_parent: device int32
+ * [total_n], caller-owned. Each graph's depths are those of its own BFS
+ * (edgeMap levels, Section 3.2) and its parents a valid BFS tree. With
+ * opts->persistent (default) the whole search is one cooperative launch that
+ * also resets the outputs and places the sources, and the call returns after
+ * one read-back of its totals. Errors: BYO_EINVAL for a null argument or a
+ * source outside its graph (nothing is launched), BYO_ELIMIT if max_levels
+ * levels do not finish the search, BYO_EHIP if a grid barrier wait of the
+ * persistent launch times out (the next call resets the barrier). */
 byo_status byo_batch_bfs(byo_batch *b, const int64_t *h_srcs, int32_t *d_depth, int32_t *d_parent,
                          const byo_opts *opts, void *stream, byo_run_stats *stats);
 /* Connectivity in every graph at once; labels are local IDs. */
