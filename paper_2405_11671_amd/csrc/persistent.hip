@@ -16,11 +16,13 @@
 //  - reads the frontier's size and degree sum (written by the level before),
 //    and picks the direction with the threshold rule: dense pull iff
 //    |U| + sum(deg U) > m / dense_divisor;
-//  - push: the frontier's ID list; a list of up to PB_EB vertices edge-
-//    balanced over the whole grid (each workgroup builds its degree prefix
-//    in LDS), a longer one by lane groups sized from the mean degree, lists
-//    longer than the group's share taken by the whole wavefront; eight
-//    neighbours in flight per lane; a CAS on parent[v] claims v;
+//  - push: edge-balanced over tiles of frontier vertices whose degree
+//    prefix a workgroup builds in LDS: a list of up to PB_EB vertices is one
+//    tile shared by the whole grid, a longer one a tile per workgroup, and
+//    the bitmap a pull level leaves is ranked by a workgroup scan over words
+//    interleaved between the workgroups; eight neighbours in flight per
+//    lane; a CAS on parent[v] claims v (lane groups per vertex remain for a
+//    degree sum beyond 32 bits);
 //  - pull: a wavefront per 64-vertex word of the visited bitmap, words
 //    already all visited skipped; each unvisited vertex scans its list until
 //    a neighbour in the frontier bitmap (the lane the first t_wave entries,
@@ -273,29 +275,24 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
             if (tried[j] && old[j] == -1) won(v[j]);
         }
       };
-      // a short frontier list with many edges (a hub among a few vertices)
-      // would leave one wavefront walking the hub's list: every workgroup
-      // builds the list's degree prefix in LDS and the grid takes the
-      // level's edges in equal shares, eight in flight per lane
+      // Edge-balanced push, in tiles of frontier vertices whose degree prefix
+      // a workgroup builds in LDS; eight edges in flight per lane.
+      //  - A list of at most PB_EB vertices is one tile that every workgroup
+      //    builds and whose edges the whole grid shares (a hub among a few
+      //    vertices would otherwise leave one wavefront walking its list).
+      //  - A longer list is cut into tiles of ceil(k / workgroups) vertices
+      //    (at most PB_EB), one workgroup per tile, which shares the tile's
+      //    edges among its own lanes.
+      //  - After a pull level the frontier is a bitmap: a workgroup takes 512
+      //    of its words, interleaved with the other workgroups' words, ranks
+      //    their set bits with a workgroup scan, and pushes them in tiles of up
+      //    to PB_EB.
       const unsigned long long nthreads = (unsigned long long)nblocks * PB_THREADS;
-      if (!prev_pull && k <= (unsigned long long)PB_EB && ds < (1ull << 32)) {
-        constexpr int PER = PB_EB / PB_THREADS;
-        int32_t ul[PER];
-        int64_t bl[PER];
-        uint32_t dl[PER], tsum = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          const unsigned long long i = (unsigned long long)t * PER + j;
-          ul[j] = i < k ? qin[i] : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-          bl[j] = ul[j] >= 0 ? off[ul[j]] : 0;
-          dl[j] = ul[j] >= 0 ? (uint32_t)deg[ul[j]] : 0u;
-          tsum += dl[j];
-        }
-        // exclusive scan of the per-thread sums over the workgroup
-        uint32_t x = tsum;
+      constexpr int PER = PB_EB / PB_THREADS;
+      // exclusive scan over the workgroup (every thread calls it); *total = sum
+      auto bscan = [&](uint32_t val, uint32_t *total) {
+        __syncthreads();  // s_wsum's previous readers are done
+        uint32_t x = val;
 #pragma unroll
         for (int o = 1; o < BYO_WAVE; o <<= 1) {
           const uint32_t y = __shfl_up(x, o);
@@ -303,16 +300,40 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
         }
         if (lane_id() == BYO_WAVE - 1) s_wsum[t / BYO_WAVE] = x;
         __syncthreads();
-        uint32_t run = x - tsum, total = 0;
+        uint32_t run = x - val, tot = 0;
 #pragma unroll
         for (int w = 0; w < PB_THREADS / BYO_WAVE; ++w) {
           if (w < t / BYO_WAVE) run += s_wsum[w];
-          total += s_wsum[w];
+          tot += s_wsum[w];
         }
+        *total = tot;
+        return run;
+      };
+      // one tile of cnt vertices, from qin[lo ...] or (in_lds) from s_u; its
+      // edges e = ebase + lane, + estride, ... of the tile's degree prefix
+      auto eb_tile = [&](unsigned long long cnt, bool in_lds, unsigned long long lo, unsigned long long ebase,
+                         unsigned long long estride) {
+        int32_t ul[PER];
+        int64_t bl[PER];
+        uint32_t dl[PER], tsum = 0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
           const unsigned long long i = (unsigned long long)t * PER + j;
-          if (i < k) {
+          ul[j] = i < cnt ? (in_lds ? s_u[i] : qin[lo + i]) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          bl[j] = ul[j] >= 0 ? off[ul[j]] : 0;
+          dl[j] = ul[j] >= 0 ? (uint32_t)deg[ul[j]] : 0u;
+          tsum += dl[j];
+        }
+        uint32_t total;
+        uint32_t run = bscan(tsum, &total);
+        // each thread rewrites only the positions it read
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+          const unsigned long long i = (unsigned long long)t * PER + j;
+          if (i < cnt) {
             s_pre[i] = run;
             s_shift[i] = bl[j] - (int64_t)run;
             s_u[i] = ul[j];
@@ -320,26 +341,26 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
           run += dl[j];
         }
         __syncthreads();
-        const int kk = (int)k;
-        // the list position holding edge e: the last i with s_pre[i] <= e
+        const int kk = (int)cnt;
+        // the tile position holding edge e: the last i with s_pre[i] <= e
         // (its degree is not zero, as s_pre[i + 1] > e)
         auto find = [&](uint32_t e) {
-          int lo = 0, hi = kk;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= e) lo = mid;
-            else hi = mid;
+          int a = 0, b = kk;
+          while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (s_pre[mid] <= e) a = mid;
+            else b = mid;
           }
-          return lo;
+          return a;
         };
-        for (unsigned long long e0 = (unsigned long long)blockIdx.x * PB_THREADS + t; e0 < total; e0 += 8 * nthreads) {
+        for (unsigned long long e0 = ebase + t; e0 < total; e0 += 8 * estride) {
           int32_t v[8], su[8];
           uint64_t vw[8];
           bool tried[8];
           int32_t old[8];
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            const unsigned long long e = e0 + j * nthreads;
+            const unsigned long long e = e0 + j * estride;
             su[j] = -1;
             v[j] = -1;
             if (e < total) {
@@ -358,6 +379,43 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
 #pragma unroll
           for (int j = 0; j < 8; ++j)
             if (tried[j] && old[j] == -1) won(v[j]);
+        }
+        // the next tile rewrites the prefix and the vertices
+        __syncthreads();
+      };
+      if (!prev_pull && ds < (1ull << 32)) {
+        const bool whole = k <= (unsigned long long)PB_EB;
+        const unsigned long long T =
+            whole ? k : std::min<unsigned long long>(PB_EB, (k + nblocks - 1) / nblocks);
+        const unsigned long long tstep = whole ? k : T * nblocks;
+        for (unsigned long long lo = whole ? 0ull : (unsigned long long)blockIdx.x * T; lo < k; lo += tstep)
+          eb_tile(std::min<unsigned long long>(T, k - lo), false, lo,
+                  whole ? (unsigned long long)blockIdx.x * PB_THREADS : 0ull,
+                  whole ? nthreads : (unsigned long long)PB_THREADS);
+      } else if (prev_pull && ds < (1ull << 32)) {
+        // word p0 + t * workgroups + workgroup: every workgroup samples the
+        // whole vertex range, so dense stretches of the bitmap are shared
+        for (unsigned long long p0 = 0; p0 < (unsigned long long)words; p0 += nthreads) {
+          const unsigned long long w = p0 + (unsigned long long)t * nblocks + blockIdx.x;
+          const uint64_t word = w < (unsigned long long)words ? bin[w] : 0ull;
+          const uint32_t pc = (uint32_t)__popcll(word);
+          uint32_t tot;
+          const uint32_t r0 = bscan(pc, &tot);
+          for (uint32_t plo = 0; plo < tot; plo += PB_EB) {
+            // this thread's set bits whose rank falls in [plo, plo + PB_EB)
+            if (pc && r0 + pc > plo && r0 < plo + PB_EB) {
+              uint64_t x = word;
+              uint32_t r = r0;
+              while (x) {
+                const int b = __ffsll((long long)x) - 1;
+                x &= x - 1;
+                if (r >= plo && r < plo + PB_EB) s_u[r - plo] = (int32_t)(w * 64 + b);
+                ++r;
+              }
+            }
+            __syncthreads();
+            eb_tile(std::min<uint32_t>(PB_EB, tot - plo), true, 0ull, 0ull, (unsigned long long)PB_THREADS);
+          }
         }
       } else {
         // a frontier list is walked by groups of g lanes per vertex, g a power
