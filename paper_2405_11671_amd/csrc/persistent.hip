@@ -418,7 +418,8 @@ __global__ void __launch_bounds__(PB_THREADS) bfs_persistent_kernel(
           }
         }
       } else {
-        // a frontier list is walked by groups of g lanes per vertex, g a power
+        // a degree sum of 2^32 or more (beyond the tiles' 32-bit prefixes): a
+        // frontier list is walked by groups of g lanes per vertex, g a power
         // of two sized from the level's mean degree (about four entries per
         // lane), raised to a whole wavefront when the list has no more vertices
         // than the grid has wavefronts; the bitmap left by a pull level is
