@@ -126,7 +126,10 @@ typedef struct byo_opts {
                              the same frontier tests as the host loop); where cooperative
                              launches are not supported, and for k-core with api_omit != 0,
                              the host loop runs instead. 0 = the host-driven loop (for the
-                             batch also hipGraph levels with use_graph = 1) */
+                             batch also hipGraph levels with use_graph = 1). 2 = as 1, and
+                             byo_bfs too runs its search in that one launch (direction by the
+                             threshold rule: selector, small_frontier and per-level traces do
+                             not apply; not with use_graph, compressed or api_omit) */
 } byo_opts;
 
 /* Container functions a traversal can be denied (Section 4.2 defines the

@@ -465,6 +465,10 @@ byo_status byo_bfs(byo_graph *g, int64_t src, int32_t *d_depth, int32_t *d_paren
   byo_opts_default(&o);
   if (opts) o = *opts;
   std::vector<int32_t> srcs(1, (int32_t)src);
+  // persistent = 2: the whole search in one persistent launch, the one the
+  // batch runs (direction by the threshold rule on the device)
+  if (o.persistent == 2 && o.api_omit == 0 && !o.compressed && !o.use_graph && bfs_persistent_usable(g))
+    return bfs_persistent_run(g, srcs.data(), 1, d_depth, d_parent, o, (hipStream_t)stream, stats);
   if (o.use_graph && o.api_omit == 0 && !o.compressed) return bfs_graph_run(g, srcs, d_depth, d_parent, o, (hipStream_t)stream, stats);
   return bfs_run(g, srcs.data(), (int64_t)srcs.size(), d_depth, d_parent, o, (hipStream_t)stream, stats);
 }
